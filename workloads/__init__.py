@@ -1,0 +1,237 @@
+"""Seeded synthetic workloads shared by the oracle, the tests and the benchmark.
+
+This module holds the configurations (grid, ions, orbitals, propagation
+parameters) and the seeded generators of their inputs: ion positions, initial
+orbitals and control amplitudes.  It contains none of the method's arithmetic
+(no Hamiltonian, no propagator, no density, no forces); both the FP64 CPU
+oracle and the GPU library receive the arrays produced here as plain inputs.
+
+Recipe of the inputs (all seeded; see ``rngs``):
+
+* Ion positions.  ``pair``: two ions at L*(1/4,1/2,1/2) and L*(3/4,1/2,1/2)
+  plus N(0, 0.1 bohr) jitter per coordinate.  ``uniform``: uniform in the
+  periodic cube with rejection of any candidate closer than ``min_sep``
+  (minimum image) to an accepted ion.  ``lattice``: simple cubic lattice of
+  ceil(N^(1/3)) sites per side, the first N sites in a seeded random order,
+  each jittered by U(-jitter, +jitter) per coordinate.
+* Orbitals.  Per orbital a complex field with independent N(0,1) real and
+  imaginary parts at every grid point, multiplied in Fourier space by
+  exp(-(|G| h)^2), normalised to h^3 sum |psi|^2 = 1, then one Loewdin step
+  Psi <- Psi S^(-1/2) with S = h^3 Psi^H Psi, so the set is orthonormal under
+  the grid quadrature.
+* Controls.  Per-step field amplitudes eps_n ~ N(0, sigma), sigma = 0.01 au.
+
+The ion mass is that of beryllium-9 (the element with Z=4), in electron
+masses; initial ion velocities are zero.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+AMU_IN_ME = 1822.888486
+BE9_MASS = 9.0121831 * AMU_IN_ME
+
+PRECISIONS = ("f64", "f32", "f32_bf16x3")
+
+
+@dataclass(frozen=True)
+class Config:
+    """One system: grid, ions, orbitals and propagation parameters (atomic units)."""
+    name: str
+    n: int                      # grid points per axis (periodic cube)
+    h: float                    # grid spacing, bohr
+    n_ions: int
+    n_orb: int
+    mu: float                   # the electronic time-scale parameter
+    dt: float                   # ionic time step, au
+    steps: int
+    placement: str = "uniform"  # pair | uniform | lattice
+    min_sep: float = 2.5
+    jitter: float = 0.0
+    zval: float = 4.0
+    mass: float = BE9_MASS
+    loc_a: float = 0.5          # V_loc = -Z erf(r/a)/r
+    kb_sigma: float = 0.4
+    kb_rcut_sigmas: float = 3.0
+    kb_energy: float = 2.0
+    occ: float = 2.0            # closed shell: two electrons per orbital
+    freeze_ions: bool = False
+    precision: str = "f64"
+    seed: int = 812
+    control_sigma: float = 0.0  # > 0: per-step control amplitudes are drawn
+    coarse_n: int = 0           # > 0: coarse static-potential perturbation grid
+
+    @property
+    def L(self) -> float:
+        return self.n * self.h
+
+    @property
+    def n_points(self) -> int:
+        return self.n ** 3
+
+    @property
+    def kb_rcut(self) -> float:
+        return self.kb_rcut_sigmas * self.kb_sigma
+
+    def replace(self, **kw) -> "Config":
+        return dataclasses.replace(self, **kw)
+
+
+# The five workloads.  Where the workload description leaves a value open the
+# chosen value is noted: c2 dt; c3 h/mu/dt; c4 h/mu/dt; c5 h/mu/dt.
+C1 = Config("c1_fp64_16", n=16, h=0.3, n_ions=2, n_orb=4, mu=1.0, dt=0.02,
+            steps=10, placement="pair", seed=812 + 1)
+C2 = Config("c2_single_96", n=96, h=0.25, n_ions=64, n_orb=128, mu=4.0,
+            dt=0.08, steps=100, placement="uniform", min_sep=2.5,
+            seed=812 + 2, precision="f32")
+C4 = Config("c4_precision_128", n=128, h=0.25, n_ions=216, n_orb=432, mu=4.0,
+            dt=0.08, steps=20, placement="lattice", jitter=0.25,
+            seed=812 + 4, precision="f32_bf16x3")
+C5 = Config("c5_adjoint_64", n=64, h=0.25, n_ions=32, n_orb=64, mu=1.0,
+            dt=0.02, steps=50, placement="uniform", min_sep=2.5,
+            freeze_ions=True, seed=812 + 5, precision="f32",
+            control_sigma=0.01, coarse_n=16)
+
+CONFIGS = {"c1": C1, "c2": C2, "c4": C4, "c5": C5}
+
+
+def batch_configs(n_systems: int = 16, seed: int = 812 + 3,
+                  steps: int = 50) -> List[Config]:
+    """The batched uneven workload: grids in {32,48,64,80,96}^3, 4-64 ions on
+    a jittered lattice, 8-256 orbitals (multiples of 8), complex FP32."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed))
+    out = []
+    for s in range(n_systems):
+        n = int(rng.choice([32, 48, 64, 80, 96]))
+        n_ions = int(rng.integers(4, 65))
+        n_orb = 8 * int(rng.integers(1, 33))
+        out.append(Config(f"c3_sys{s:02d}_{n}", n=n, h=0.25, n_ions=n_ions,
+                          n_orb=n_orb, mu=4.0, dt=0.08, steps=steps,
+                          placement="lattice", seed=seed * 100 + s,
+                          precision="f32"))
+    # the lattice jitter is a tenth of the lattice constant
+    return [c.replace(jitter=0.1 * c.L / math.ceil(c.n_ions ** (1.0 / 3.0) - 1e-9))
+            for c in out]
+
+
+def rngs(cfg: Config) -> Tuple[np.random.Generator, np.random.Generator,
+                               np.random.Generator]:
+    """Independent streams for positions, orbitals and controls."""
+    ss = np.random.SeedSequence(cfg.seed)
+    a, b, c = ss.spawn(3)
+    return (np.random.default_rng(a), np.random.default_rng(b),
+            np.random.default_rng(c))
+
+
+def _min_image_dist(a: np.ndarray, b: np.ndarray, L: float) -> np.ndarray:
+    d = a[None, :] - b
+    d -= L * np.round(d / L)
+    return np.sqrt((d * d).sum(-1))
+
+
+def ion_positions(cfg: Config, rng: Optional[np.random.Generator] = None) -> np.ndarray:
+    """[n_ions, 3] float64 positions in [0, L)^3."""
+    if rng is None:
+        rng = rngs(cfg)[0]
+    L = cfg.L
+    if cfg.placement == "pair":
+        base = np.array([[0.25, 0.5, 0.5], [0.75, 0.5, 0.5]]) * L
+        base = base[: cfg.n_ions]
+        pos = base + rng.normal(0.0, 0.1, size=base.shape)
+    elif cfg.placement == "uniform":
+        acc = []
+        tries = 0
+        while len(acc) < cfg.n_ions:
+            tries += 1
+            if tries > 2_000_000:
+                raise RuntimeError("could not place ions with the requested separation")
+            cand = rng.uniform(0.0, L, size=3)
+            if acc and _min_image_dist(cand, np.array(acc), L).min() < cfg.min_sep:
+                continue
+            acc.append(cand)
+        pos = np.array(acc)
+    elif cfg.placement == "lattice":
+        side = math.ceil(cfg.n_ions ** (1.0 / 3.0) - 1e-9)
+        a = L / side
+        sites = np.array([(i, j, k) for i in range(side) for j in range(side)
+                          for k in range(side)], dtype=np.float64)
+        order = rng.permutation(len(sites))[: cfg.n_ions]
+        pos = (sites[order] + 0.5) * a
+        pos = pos + rng.uniform(-cfg.jitter, cfg.jitter, size=pos.shape)
+    else:
+        raise ValueError(cfg.placement)
+    return np.mod(pos, L)
+
+
+def _gsq_smoothing(n: int, h: float) -> np.ndarray:
+    m = np.fft.fftfreq(n) * n
+    g = 2.0 * np.pi * m / (n * h)
+    g2 = g[:, None, None] ** 2 + g[None, :, None] ** 2 + g[None, None, :] ** 2
+    return np.exp(-g2 * h * h)
+
+
+def initial_orbitals(cfg: Config, rng: Optional[np.random.Generator] = None,
+                     n_orb: Optional[int] = None) -> np.ndarray:
+    """[n_orb, n, n, n] complex128, orthonormal under h^3 sum conj(a) b.
+
+    Axis order is (z, y, x): x is the fastest-varying index in memory."""
+    import scipy.fft as sfft
+    if rng is None:
+        rng = rngs(cfg)[1]
+    n, h = cfg.n, cfg.h
+    no = cfg.n_orb if n_orb is None else n_orb
+    filt = _gsq_smoothing(n, h)
+    psi = np.empty((no, n, n, n), dtype=np.complex128)
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    h3 = h ** 3
+    for a in range(no):
+        f = rng.standard_normal((2, n, n, n))
+        z = f[0] + 1j * f[1]
+        z = sfft.ifftn(sfft.fftn(z, workers=workers) * filt, workers=workers)
+        z /= math.sqrt(h3 * float(np.vdot(z, z).real))
+        psi[a] = z
+    flat = psi.reshape(no, -1)
+    s = h3 * (flat.conj() @ flat.T)
+    s = 0.5 * (s + s.conj().T)
+    w, v = np.linalg.eigh(s)
+    x = (v * (1.0 / np.sqrt(w))) @ v.conj().T   # S^(-1/2), Hermitian
+    xt = np.ascontiguousarray(x.T)
+    chunk = 1 << 18
+    for i0 in range(0, flat.shape[1], chunk):
+        flat[:, i0:i0 + chunk] = xt @ flat[:, i0:i0 + chunk]
+    return psi
+
+
+def controls(cfg: Config, rng: Optional[np.random.Generator] = None,
+             steps: Optional[int] = None) -> np.ndarray:
+    """Per-step control amplitudes eps_n, float64 [steps]."""
+    if rng is None:
+        rng = rngs(cfg)[2]
+    k = cfg.steps if steps is None else steps
+    return rng.normal(0.0, cfg.control_sigma, size=k)
+
+
+def coarse_perturbation(cfg: Config, scale: float, seed_offset: int = 0) -> np.ndarray:
+    """A seeded smooth coarse-grid static potential perturbation [m,m,m] float64."""
+    rng = np.random.default_rng(np.random.SeedSequence([cfg.seed, 77, seed_offset]))
+    m = cfg.coarse_n
+    return scale * rng.standard_normal((m, m, m))
+
+
+def make_inputs(cfg: Config, n_orb: Optional[int] = None) -> dict:
+    """Everything a run needs, as plain arrays."""
+    rp, ro, rc = rngs(cfg)
+    out = {"pos": ion_positions(cfg, rp),
+           "psi": initial_orbitals(cfg, ro, n_orb),
+           "vel": np.zeros((cfg.n_ions, 3)),
+           "zval": np.full(cfg.n_ions, cfg.zval),
+           "mass": np.full(cfg.n_ions, cfg.mass)}
+    if cfg.control_sigma > 0:
+        out["ctrl"] = controls(cfg, rc)
+    return out
