@@ -1,0 +1,204 @@
+/*
+ * modehr.h -- C ABI of the MI355X (gfx950) modified-Ehrenfest propagation
+ * library.
+ *
+ * The library advances a set of doubly occupied Kohn-Sham orbitals and the
+ * ions of one periodic system by the modified Ehrenfest equations of motion
+ * of Andrade et al., arXiv:0812.2801, eq. (new_EoM):
+ *     i mu d(phi_A)/dt = H phi_A,     M_J d^2 R_J/dt^2 = -grad_J E_KS,
+ * with H = -1/2 Lap (8th-order finite differences on a periodic grid)
+ *        + v_eff (local ionic + Hartree + Slater exchange [+ field])
+ *        + sum_J E_KB |p_J><p_J|  (Gaussian s-channel Kleinman-Bylander).
+ * One step (sec. 5.1) is velocity Verlet for the ions around the AETRS
+ * propagator of eq. (aetrs), each exponential a fourth-order Taylor
+ * polynomial with electronic step tau = dt/(2 mu) (eq. transf), followed by
+ * the density of eq. (density) and the forces -grad_R E_KS at fixed orbitals.
+ * The problem statement follows sec. 5.1: given phi(0) and R(0), compute
+ * phi(t) and R(t).
+ *
+ * Conventions
+ *   - Grid: n[0] x n[1] x n[2] points (x, y, z), spacing h, periodic cube of
+ *     side L = n h, point (ix,iy,iz) at r = h (ix,iy,iz).  A grid function is
+ *     stored with x fastest: offset = (iz*n[1] + iy)*n[0] + ix.
+ *   - Orbitals: complex, interleaved (re, im).  Precision ME_F64 uses
+ *     complex128 (double2); ME_F32 and ME_F32_BF16X3 use complex64 (float2).
+ *     A set of orbitals is [n_orb][orb_stride] complex elements; the first
+ *     N = n[0]*n[1]*n[2] elements of each row are the grid function.
+ *   - Inner product: h^3 sum conj(a) b.  Orbitals handed to me_set_state are
+ *     expected to be orthonormal under it (the library does not enforce it).
+ *   - Atomic units (bohr, hartree, electron masses, au of time).
+ *
+ * Memory ownership
+ *   - Host arrays in me_params are copied during me_init_system.
+ *   - All device memory is owned by the caller: the workspace (size from
+ *     me_workspace_size) and every device pointer argument.  The library
+ *     never allocates device memory for system state; rocFFT plans may hold
+ *     their own small twiddle tables.
+ *   - The handle is owned by the library and released by me_destroy.
+ *
+ * Streams and errors
+ *   - Every call that launches work enqueues it on the stream given to
+ *     me_init_system (a hipStream_t passed as void*; NULL = default stream)
+ *     and returns without waiting, unless its comment says it synchronises.
+ *   - Every call returns an me_status.  Arguments are validated before any
+ *     launch; an invalid argument returns ME_EINVAL and changes nothing.
+ *     Asynchronous device errors surface at the next synchronising call.
+ *     No call aborts, exits or throws; me_last_error gives the text.
+ *   - A handle is not thread-safe: use one handle per host thread/stream.
+ */
+#ifndef MODEHR_H
+#define MODEHR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ME_OK = 0,
+    ME_EINVAL = 1,        /* null pointer, bad size, sphere does not fit, ... */
+    ME_ENOMEM = 2,        /* workspace smaller than me_workspace_size */
+    ME_EDEVICE = 3,       /* HIP or rocFFT error (text in me_last_error) */
+    ME_ESTATE = 4,        /* call before me_set_state, or wrong mode */
+    ME_EUNSTABLE = 5,     /* an orbital norm grew or became non-finite */
+    ME_EUNSUPPORTED = 6   /* valid request this build does not support */
+} me_status;
+
+typedef enum {
+    ME_F64 = 0,           /* complex128 orbitals, FP64 everywhere */
+    ME_F32 = 1,           /* complex64 orbitals and FP32 stencil/Taylor */
+    ME_F32_BF16X3 = 2     /* ME_F32 with the projector contraction as split-bf16 MFMA */
+} me_precision;
+
+typedef struct me_system me_system;
+
+/* Parameters of one system.  Host pointers; copied by me_init_system. */
+typedef struct {
+    int32_t n[3];          /* grid points along x, y, z (each >= 9) */
+    double h;              /* grid spacing, bohr (> 0) */
+    int32_t n_ions;        /* >= 0 */
+    const double* pos;     /* [n_ions][3] initial positions, bohr */
+    const double* vel;     /* [n_ions][3] initial velocities, or NULL for zero */
+    const double* mass;    /* [n_ions] masses, electron masses (> 0) */
+    const double* zval;    /* [n_ions] ionic charges */
+    double loc_a;          /* V_loc = -Z erf(r/loc_a)/r, loc_a > 0 */
+    double kb_sigma;       /* projector width sigma (> 0) */
+    double kb_rcut;        /* projector cutoff radius; 2*kb_rcut < L along every axis */
+    double kb_energy;      /* E_KB, hartree */
+    int32_t n_orb;         /* number of orbitals (>= 1) */
+    double occ;            /* occupation per orbital (2 for closed shell) */
+    double mu;             /* the electronic time-scale parameter (> 0) */
+    double dt;             /* ionic time step, au (!= 0) */
+    int32_t taylor_order;  /* order of the Taylor exponential (1..8; 4 in the method) */
+    int32_t precision;     /* me_precision */
+    int32_t freeze_ions;   /* nonzero: ions do not move (forces still computed) */
+    int32_t reserved;      /* must be 0 */
+} me_params;
+
+/* Diagnostics of the current state.  Energies in hartree. */
+typedef struct {
+    double e_kinetic;      /* f sum_A h^3 Re<psi_A|T psi_A> */
+    double e_local;        /* h^3 sum rho V_loc (incl. any static potential) */
+    double e_hartree;
+    double e_xc;
+    double e_nonlocal;     /* f E_KB sum |c_JA|^2 */
+    double e_ion;          /* Ewald ion-ion energy */
+    double e_ks;           /* sum of the six above */
+    double e_ion_kinetic;  /* sum 1/2 M V^2 */
+    double e_total;        /* e_ks + e_ion_kinetic: the conserved energy of eq. (E_new) */
+    double max_norm_dev;   /* max_A |h^3 sum |psi_A|^2 - 1| */
+    double max_force;      /* max_J |F_J| */
+    double charge;         /* h^3 sum rho */
+    int64_t step;          /* steps taken since me_set_state */
+} me_step_report;
+
+/* Bytes of device workspace me_init_system needs for these parameters.
+ * Pure host computation. */
+me_status me_workspace_size(const me_params* p, size_t* bytes);
+
+/* Create a system.  workspace: caller-owned device memory of at least
+ * me_workspace_size bytes, 256-byte aligned, untouched by the caller until
+ * me_destroy.  stream: hipStream_t (as void*) all work is enqueued on.
+ * Validates p (ME_EINVAL), checks ws_bytes (ME_ENOMEM), uploads the ion data
+ * and builds FFT plans.  No orbital state yet: call me_set_state. */
+me_status me_init_system(const me_params* p, void* workspace, size_t ws_bytes,
+                         void* stream, me_system** out);
+
+/* Release the handle (not the caller's device memory).  NULL is allowed. */
+me_status me_destroy(me_system* sys);
+
+/* Wait for all work enqueued by this handle.  Returns ME_EDEVICE on a
+ * pending device error. */
+me_status me_sync(me_system* sys);
+
+/* Load orbitals psi_dev ([n_orb][orb_stride] complex of the handle's
+ * precision, device) as the state at t = 0 (eq. Ehr_ic), then compute the
+ * density, v_eff and the forces F(0).  orb_stride >= N.  Resets the step
+ * counter and the potential history. */
+me_status me_set_state(me_system* sys, const void* psi_dev, int64_t orb_stride);
+
+/* Copy the current orbitals to psi_dev ([n_orb][orb_stride], device). */
+me_status me_get_state(me_system* sys, void* psi_dev, int64_t orb_stride);
+
+/* hpsi_out = H psi_in for n_orb orbitals of the handle's precision, with the
+ * current Hamiltonian H(t) (eq. new_EoM(a): kinetic + v_eff + nonlocal).
+ * Input and output must not overlap.  n_orb >= 1, orb_stride >= N. */
+me_status me_apply_H(me_system* sys, const void* psi_in_dev, void* hpsi_out_dev,
+                     int32_t n_orb, int64_t orb_stride);
+
+/* One molecular-dynamics step (sec. 5.1): R(t+dt) by velocity Verlet, the
+ * AETRS propagator of eq. (aetrs) with Taylor exponentials of step
+ * tau = dt/(2 mu), the density (eq. density), Hartree/exchange, forces and
+ * velocities.  ctrl: host pointer to the amplitude eps of a uniform field
+ * adding eps * (x - L/2) to v_eff in both exponentials of this step, or NULL
+ * for no field.  rep: host, nullable; when given, the step's diagnostics are
+ * computed and the call synchronises.  Returns ME_EUNSTABLE (after the step)
+ * if an orbital norm exceeded 1 + 1e-6 or became non-finite; the check is
+ * made at the next synchronising call when rep is NULL. */
+me_status me_propagate_step(me_system* sys, const double* ctrl, me_step_report* rep);
+
+/* Diagnostics of the current state (synchronises). */
+me_status me_report(me_system* sys, me_step_report* rep);
+
+/* rho_dev[N] = f sum_A |psi_A|^2 of the current state, FP64, device. */
+me_status me_density(me_system* sys, double* rho_dev);
+
+/* f_host[3*n_ions] = total force on each ion at the current state, FP64,
+ * host (synchronises). */
+me_status me_forces(me_system* sys, double* f_host);
+
+/* Current ion positions and velocities, host, [n_ions][3] each; either may be
+ * NULL (synchronises). */
+me_status me_get_ions(me_system* sys, double* pos_host, double* vel_host);
+
+/* Components of the current potential, FP64, device [N]:
+ * which = 0: V_loc (incl. static potential), 1: v_Hxc (newest history level),
+ * 2: v_eff(t) as used by the next step's first exponential (without field). */
+me_status me_get_potential(me_system* sys, int32_t which, double* v_dev);
+
+/* Add a static local potential dv_dev[N] (FP64, device; copied) to V_loc, or
+ * clear it with NULL.  Takes effect for the next me_set_state. */
+me_status me_set_static_potential(me_system* sys, const double* dv_dev);
+
+/* Per-kernel timing.  me_timing_enable(sys, 1) brackets every launch of the
+ * Horner-stage stencil kernel with HIP events on the handle's stream;
+ * me_timing_read synchronises and returns the number of timed launches,
+ * their summed duration in milliseconds and the algorithmic bytes they moved
+ * (3 complex streams per orbital point, 2 for the first stage, plus v_eff).
+ * me_timing_enable(sys, 0) stops and clears. */
+me_status me_timing_enable(me_system* sys, int32_t enable);
+me_status me_timing_read(me_system* sys, int64_t* launches, double* total_ms,
+                         double* total_bytes);
+
+/* Text of the last error on this handle ("" if none).  NULL sys gives the
+ * last error of a failed me_init_system on this thread. */
+const char* me_last_error(const me_system* sys);
+const char* me_strerror(me_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MODEHR_H */

@@ -1,0 +1,273 @@
+"""Python binding of libmodehr.so (the C ABI in include/modehr.h).
+
+Argument marshalling only: every step of the propagation runs in the HIP
+library.  PyTorch provides device memory (the workspace and orbital
+tensors) and the stream.  If the library is missing or cannot be loaded the
+binding raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_size_t, c_void_p
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmodehr.so")
+
+ME_OK, ME_EINVAL, ME_ENOMEM, ME_EDEVICE, ME_ESTATE, ME_EUNSTABLE, ME_EUNSUPPORTED = range(7)
+PRECISION = {"f64": 0, "f32": 1, "f32_bf16x3": 2}
+
+SYMBOLS = [
+    "me_workspace_size", "me_init_system", "me_destroy", "me_sync", "me_set_state",
+    "me_get_state", "me_apply_H", "me_propagate_step", "me_report", "me_density",
+    "me_forces", "me_get_ions", "me_get_potential", "me_set_static_potential",
+    "me_timing_enable", "me_timing_read", "me_last_error", "me_strerror",
+]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("n", c_int32 * 3), ("h", c_double), ("n_ions", c_int32),
+        ("pos", POINTER(c_double)), ("vel", POINTER(c_double)),
+        ("mass", POINTER(c_double)), ("zval", POINTER(c_double)),
+        ("loc_a", c_double), ("kb_sigma", c_double), ("kb_rcut", c_double),
+        ("kb_energy", c_double), ("n_orb", c_int32), ("occ", c_double),
+        ("mu", c_double), ("dt", c_double), ("taylor_order", c_int32),
+        ("precision", c_int32), ("freeze_ions", c_int32), ("reserved", c_int32),
+    ]
+
+
+class StepReport(ctypes.Structure):
+    _fields_ = [(k, c_double) for k in (
+        "e_kinetic", "e_local", "e_hartree", "e_xc", "e_nonlocal", "e_ion", "e_ks",
+        "e_ion_kinetic", "e_total", "max_norm_dev", "max_force", "charge")] + [("step", c_int64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ModehrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"modehr status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the library (once).  Raises if it is missing or lacks a symbol."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with python -m paper_0812_2801_amd.build")
+    lib = ctypes.CDLL(path)
+    for s in SYMBOLS:
+        getattr(lib, s)
+    lib.me_last_error.restype = c_char_p
+    lib.me_last_error.argtypes = [c_void_p]
+    lib.me_strerror.restype = c_char_p
+    lib.me_strerror.argtypes = [c_int32]
+    lib.me_workspace_size.argtypes = [POINTER(Params), POINTER(c_size_t)]
+    lib.me_init_system.argtypes = [POINTER(Params), c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]
+    lib.me_destroy.argtypes = [c_void_p]
+    lib.me_sync.argtypes = [c_void_p]
+    lib.me_set_state.argtypes = [c_void_p, c_void_p, c_int64]
+    lib.me_get_state.argtypes = [c_void_p, c_void_p, c_int64]
+    lib.me_apply_H.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_int64]
+    lib.me_propagate_step.argtypes = [c_void_p, POINTER(c_double), POINTER(StepReport)]
+    lib.me_report.argtypes = [c_void_p, POINTER(StepReport)]
+    lib.me_density.argtypes = [c_void_p, c_void_p]
+    lib.me_forces.argtypes = [c_void_p, POINTER(c_double)]
+    lib.me_get_ions.argtypes = [c_void_p, POINTER(c_double), POINTER(c_double)]
+    lib.me_get_potential.argtypes = [c_void_p, c_int32, c_void_p]
+    lib.me_set_static_potential.argtypes = [c_void_p, c_void_p]
+    lib.me_timing_enable.argtypes = [c_void_p, c_int32]
+    lib.me_timing_read.argtypes = [c_void_p, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]
+    for s in SYMBOLS:
+        if s not in ("me_last_error", "me_strerror"):
+            getattr(lib, s).restype = c_int32
+    _lib = lib
+    return lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(POINTER(c_double))
+
+
+def make_params(*, n, h, pos, mass, zval, n_orb, mu, dt, vel=None, loc_a=0.5,
+                kb_sigma=0.4, kb_rcut=1.2, kb_energy=2.0, occ=2.0, taylor_order=4,
+                precision="f64", freeze_ions=False):
+    """Params plus the host arrays it points to (keep both alive)."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+    mass = np.ascontiguousarray(mass, dtype=np.float64).ravel()
+    zval = np.ascontiguousarray(zval, dtype=np.float64).ravel()
+    keep = [pos, mass, zval]
+    p = Params()
+    nn = (n, n, n) if np.isscalar(n) else tuple(n)
+    p.n = (c_int32 * 3)(*nn)
+    p.h = h
+    p.n_ions = len(pos)
+    p.pos = _dptr(pos)
+    if vel is not None:
+        vel = np.ascontiguousarray(vel, dtype=np.float64).reshape(-1, 3)
+        keep.append(vel)
+        p.vel = _dptr(vel)
+    p.mass = _dptr(mass)
+    p.zval = _dptr(zval)
+    p.loc_a, p.kb_sigma, p.kb_rcut, p.kb_energy = loc_a, kb_sigma, kb_rcut, kb_energy
+    p.n_orb = n_orb
+    p.occ, p.mu, p.dt = occ, mu, dt
+    p.taylor_order = taylor_order
+    p.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    p.freeze_ions = int(bool(freeze_ions))
+    p.reserved = 0
+    return p, keep
+
+
+def params_from_config(cfg, pos, vel=None, precision=None, **over):
+    kw = dict(n=cfg.n, h=cfg.h, pos=pos, mass=np.full(cfg.n_ions, cfg.mass),
+              zval=np.full(cfg.n_ions, cfg.zval), n_orb=cfg.n_orb, mu=cfg.mu, dt=cfg.dt,
+              vel=vel, loc_a=cfg.loc_a, kb_sigma=cfg.kb_sigma, kb_rcut=cfg.kb_rcut,
+              kb_energy=cfg.kb_energy, occ=cfg.occ,
+              precision=precision or cfg.precision, freeze_ions=cfg.freeze_ions)
+    kw.update(over)
+    return make_params(**kw)
+
+
+def workspace_size(p: Params) -> int:
+    lib = load()
+    out = c_size_t(0)
+    st = lib.me_workspace_size(ctypes.byref(p), ctypes.byref(out))
+    if st != ME_OK:
+        raise ModehrError(st, lib.me_last_error(None).decode())
+    return out.value
+
+
+class System:
+    """One system on one GPU; device memory from torch, work on torch's current stream."""
+
+    def __init__(self, params: Params, keep=None, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.params = params
+        self._keep = keep
+        self.device = torch.device(device)
+        self.cdtype = torch.complex128 if params.precision == 0 else torch.complex64
+        self.N = params.n[0] * params.n[1] * params.n[2]
+        self.n_orb = params.n_orb
+        self.n_ions = params.n_ions
+        size = workspace_size(params)
+        self.workspace = torch.empty(size, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = c_void_p()
+        st = self.lib.me_init_system(ctypes.byref(params), c_void_p(self.workspace.data_ptr()),
+                                     c_size_t(size), c_void_p(self.stream.cuda_stream),
+                                     ctypes.byref(h))
+        if st != ME_OK:
+            raise ModehrError(st, self.lib.me_last_error(None).decode())
+        self.h = h
+
+    # -------------------------------------------------------------- helpers
+    def _check(self, st: int):
+        if st != ME_OK:
+            raise ModehrError(st, self.lib.me_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.me_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _orbitals(self, psi):
+        t = self.torch
+        if not isinstance(psi, t.Tensor):
+            psi = t.from_numpy(np.ascontiguousarray(psi))
+        psi = psi.to(device=self.device, dtype=self.cdtype).reshape(psi.shape[0], -1).contiguous()
+        if psi.shape[1] != self.N:
+            raise ValueError("orbitals must have N grid points each")
+        return psi
+
+    # -------------------------------------------------------------- API
+    def set_state(self, psi):
+        psi = self._orbitals(psi)
+        if psi.shape[0] != self.n_orb:
+            raise ValueError("set_state needs n_orb orbitals")
+        self._check(self.lib.me_set_state(self.h, c_void_p(psi.data_ptr()), c_int64(self.N)))
+
+    def get_state(self):
+        out = self.torch.empty((self.n_orb, self.N), dtype=self.cdtype, device=self.device)
+        self._check(self.lib.me_get_state(self.h, c_void_p(out.data_ptr()), c_int64(self.N)))
+        return out
+
+    def apply_H(self, psi):
+        psi = self._orbitals(psi)
+        out = self.torch.empty_like(psi)
+        self._check(self.lib.me_apply_H(self.h, c_void_p(psi.data_ptr()), c_void_p(out.data_ptr()),
+                                        c_int32(psi.shape[0]), c_int64(self.N)))
+        return out
+
+    def step(self, ctrl: Optional[float] = None, report: bool = False):
+        c = c_double(ctrl) if ctrl is not None else None
+        rep = StepReport() if report else None
+        st = self.lib.me_propagate_step(self.h, ctypes.byref(c) if c is not None else None,
+                                        ctypes.byref(rep) if rep is not None else None)
+        self._check(st)
+        return rep.as_dict() if rep is not None else None
+
+    def report(self) -> dict:
+        rep = StepReport()
+        self._check(self.lib.me_report(self.h, ctypes.byref(rep)))
+        return rep.as_dict()
+
+    def sync(self):
+        self._check(self.lib.me_sync(self.h))
+
+    def density(self):
+        out = self.torch.empty(self.N, dtype=self.torch.float64, device=self.device)
+        self._check(self.lib.me_density(self.h, c_void_p(out.data_ptr())))
+        return out
+
+    def forces(self) -> np.ndarray:
+        f = np.zeros((self.n_ions, 3))
+        self._check(self.lib.me_forces(self.h, _dptr(f)))
+        return f
+
+    def ions(self):
+        p = np.zeros((self.n_ions, 3))
+        v = np.zeros((self.n_ions, 3))
+        self._check(self.lib.me_get_ions(self.h, _dptr(p), _dptr(v)))
+        return p, v
+
+    def potential(self, which: int):
+        out = self.torch.empty(self.N, dtype=self.torch.float64, device=self.device)
+        self._check(self.lib.me_get_potential(self.h, c_int32(which), c_void_p(out.data_ptr())))
+        return out
+
+    def set_static_potential(self, dv):
+        if dv is None:
+            self._check(self.lib.me_set_static_potential(self.h, None))
+            return
+        dv = self.torch.as_tensor(dv, dtype=self.torch.float64).to(self.device).reshape(-1).contiguous()
+        self._dv = dv
+        self._check(self.lib.me_set_static_potential(self.h, c_void_p(dv.data_ptr())))
+
+    def timing_enable(self, on: bool = True):
+        self._check(self.lib.me_timing_enable(self.h, c_int32(1 if on else 0)))
+
+    def timing_read(self):
+        n = c_int64(0)
+        ms = c_double(0)
+        by = c_double(0)
+        self._check(self.lib.me_timing_read(self.h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+        return n.value, ms.value, by.value

@@ -1,0 +1,986 @@
+// Host runtime and C ABI: workspace planning, rocFFT plans, and the
+// orchestration of one modified-Ehrenfest step (sec. 5.1): ions moved by
+// velocity Verlet, the AETRS propagator of eq. (aetrs) as two fourth-order
+// Taylor exponentials evaluated in Horner form, then the density, Hartree /
+// exchange, and the forces at the new positions.
+#include <hip/hip_runtime.h>
+#include <rocfft/rocfft.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/modehr.h"
+#include "common.hpp"
+#include "fields.hpp"
+
+using namespace me;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+struct Carver {
+    size_t off = 0;
+    char* base = nullptr;
+    template <typename P>
+    P* take(size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + std::max<size_t>(bytes, 1));
+        return base ? reinterpret_cast<P*>(base + o) : nullptr;
+    }
+};
+
+// Host-side Ewald set-up: splitting, real-space cutoff, reciprocal vectors.
+struct EwaldHost {
+    double L = 0, eta = 0, rc = 0, e_const = 0;
+    int nmax = 0;
+    std::vector<double> gv, wv;
+};
+
+EwaldHost ewald_setup(double L, const std::vector<double>& z) {
+    EwaldHost e;
+    e.L = L;
+    e.eta = 5.0 / L;
+    const double tol = 1e-17;
+    double rc = 1.0;
+    while (std::erfc(e.eta * rc) > tol) rc *= 1.1;
+    e.rc = rc;
+    e.nmax = (int)std::ceil(rc / L) + 1;
+    const double gc = 2.0 * e.eta * std::sqrt(-std::log(tol));
+    const int mmax = (int)std::ceil(gc * L / (2.0 * M_PI));
+    for (int i = -mmax; i <= mmax; ++i)
+        for (int j = -mmax; j <= mmax; ++j)
+            for (int k = -mmax; k <= mmax; ++k) {
+                if (!i && !j && !k) continue;
+                const double gx = 2 * M_PI * i / L, gy = 2 * M_PI * j / L, gz = 2 * M_PI * k / L;
+                const double g2 = gx * gx + gy * gy + gz * gz;
+                if (g2 >= gc * gc) continue;
+                e.gv.push_back(gx); e.gv.push_back(gy); e.gv.push_back(gz);
+                e.wv.push_back(std::exp(-g2 / (4.0 * e.eta * e.eta)) / g2);
+            }
+    double z2 = 0, zs = 0;
+    for (double q : z) { z2 += q * q; zs += q; }
+    const double omega = L * L * L;
+    e.e_const = -e.eta / std::sqrt(M_PI) * z2 - M_PI * zs * zs / (2.0 * omega * e.eta * e.eta);
+    return e;
+}
+
+struct Geometry {
+    int nx, ny, nz;
+    int64_t N, stride;
+    int n_orb, n_ions;
+    bool f64;
+    size_t bc;        // bytes per complex
+    size_t br;        // bytes per real of the compute precision
+    int px, ty, nyt, zchunk, nzc;
+    int kcap, words;
+    int side[3];
+    int m;
+    int64_t nhalf;    // half-spectrum size
+    int floc_chunks;
+    int64_t nblk256;  // 256-point blocks of the grid
+    size_t fft_work;
+    int ewald_ng;
+};
+
+int choose_px(int nx, bool f64) {
+    const int w = f64 ? 1 : 2;
+    return nx % w == 0 ? w : 1;
+}
+
+int choose_ty(int nx, int ny, int px, size_t bc) {
+    const int nxt = nx / px;
+    for (int ty : {16, 8, 4, 2, 1}) {
+        if (ny % ty) continue;
+        if ((int64_t)nxt * ty > 1024) continue;
+        if ((size_t)(ty + 8) * nx * bc > 64 * 1024) continue;
+        return ty;
+    }
+    return -1;
+}
+
+int choose_zchunk(int nz, int64_t base_blocks) {
+    // the largest divisor of nz (>= 8 planes, or nz) giving >= 1024 workgroups
+    int best = nz;
+    for (int zc = nz; zc >= 1; --zc) {
+        if (nz % zc) continue;
+        if (zc < 8 && zc != nz) break;
+        best = zc;
+        if (base_blocks * (nz / zc) >= 1024) break;
+    }
+    return best;
+}
+
+me_status validate(const me_params* p, std::string& err) {
+    if (!p) { err = "params is NULL"; return ME_EINVAL; }
+    for (int a = 0; a < 3; ++a)
+        if (p->n[a] < 8 || p->n[a] > 4096) { err = "grid size must be in [8, 4096] along every axis"; return ME_EINVAL; }
+    if (!(p->h > 0) || !std::isfinite(p->h)) { err = "h must be positive"; return ME_EINVAL; }
+    if (p->n_ions < 0 || p->n_ions > 32 * MAX_WORDS) { err = "n_ions out of range"; return ME_EINVAL; }
+    if (p->n_ions > 0 && (!p->pos || !p->mass || !p->zval)) { err = "pos/mass/zval must not be NULL"; return ME_EINVAL; }
+    for (int J = 0; J < p->n_ions; ++J) {
+        if (!(p->mass[J] > 0)) { err = "masses must be positive"; return ME_EINVAL; }
+        for (int c = 0; c < 3; ++c)
+            if (!std::isfinite(p->pos[3 * J + c])) { err = "positions must be finite"; return ME_EINVAL; }
+    }
+    if (!(p->loc_a > 0) || !(p->kb_sigma > 0) || !(p->kb_rcut > 0)) { err = "loc_a, kb_sigma, kb_rcut must be positive"; return ME_EINVAL; }
+    for (int a = 0; a < 3; ++a)
+        if (!(2.0 * p->kb_rcut < p->n[a] * p->h)) { err = "projector sphere does not fit: need 2*kb_rcut < L"; return ME_EINVAL; }
+    if (p->n_orb < 1) { err = "n_orb must be >= 1"; return ME_EINVAL; }
+    if (!(p->mu > 0) || !std::isfinite(p->dt) || p->dt == 0.0) { err = "mu must be positive and dt nonzero"; return ME_EINVAL; }
+    if (p->taylor_order < 1 || p->taylor_order > MAX_TAYLOR) { err = "taylor_order must be in [1, 8]"; return ME_EINVAL; }
+    if (p->precision < ME_F64 || p->precision > ME_F32_BF16X3) { err = "unknown precision"; return ME_EINVAL; }
+    if (p->reserved != 0) { err = "reserved must be 0"; return ME_EINVAL; }
+    const bool f64 = p->precision == ME_F64;
+    const int px = choose_px(p->n[0], f64);
+    if (choose_ty(p->n[0], p->n[1], px, f64 ? 16 : 8) < 0) { err = "grid x extent too large for one workgroup row"; return ME_EUNSUPPORTED; }
+    return ME_OK;
+}
+
+Geometry make_geometry(const me_params* p) {
+    Geometry g{};
+    g.nx = p->n[0]; g.ny = p->n[1]; g.nz = p->n[2];
+    g.N = (int64_t)g.nx * g.ny * g.nz;
+    g.stride = (int64_t)align_up((size_t)g.N, 64);
+    g.n_orb = p->n_orb;
+    g.n_ions = p->n_ions;
+    g.f64 = p->precision == ME_F64;
+    g.bc = g.f64 ? 16 : 8;
+    g.br = g.f64 ? 8 : 4;
+    g.px = choose_px(g.nx, g.f64);
+    g.ty = choose_ty(g.nx, g.ny, g.px, g.bc);
+    g.nyt = g.ny / g.ty;
+    g.zchunk = choose_zchunk(g.nz, (int64_t)g.n_orb * g.nyt);
+    g.nzc = g.nz / g.zchunk;
+    const int m = (int)std::ceil(p->kb_rcut / p->h);
+    g.m = m;
+    int kc = 1;
+    for (int a = 0; a < 3; ++a) {
+        g.side[a] = std::min(2 * m + 2, p->n[a]);
+        kc *= g.side[a];
+    }
+    g.kcap = kc;
+    g.words = std::max(1, (g.n_ions + 31) / 32);
+    g.nhalf = (int64_t)(g.nx / 2 + 1) * g.ny * g.nz;
+    g.floc_chunks = local_force_chunks(g.N);
+    g.nblk256 = (g.N + 255) / 256;
+    g.fft_work = (size_t)(2 * g.nhalf) * 16;
+    return g;
+}
+
+}  // namespace
+
+struct Layout {
+    void *psi, *bufA, *bufB, *veff0, *veff1, *cnl;
+    double *vloc_cur, *vloc_next, *vstatic, *hist[3], *rho, *vh;
+    double2 *rhok, *spec, *phase, *ewald_sg;
+    void* fft_work;
+    double *pos, *pos_next, *vel, *frc, *mass, *zval;
+    int32_t* tidx[2];
+    void* tp[2];
+    void* tbox[2];
+    int32_t* tstart[2];
+    int32_t* tcount[2];
+    uint32_t* tmask[2];
+    double *fnl, *enl_part, *floc_part, *fion, *eion_part, *erec_part;
+    double *ewald_gv, *ewald_wv;
+    double *norm_part, *kin_part, *hxc_part, *loc_part, *rep;
+    size_t total;
+};
+
+static Layout carve(const Geometry& g, char* base) {
+    Carver c;
+    c.base = base;
+    Layout L{};
+    const size_t orb = (size_t)g.n_orb * g.stride * g.bc;
+    L.psi = c.take<void>(orb);
+    L.bufA = c.take<void>(orb);
+    L.bufB = c.take<void>(orb);
+    L.veff0 = c.take<void>(g.N * g.br);
+    L.veff1 = c.take<void>(g.N * g.br);
+    L.cnl = c.take<void>((size_t)std::max(1, g.n_ions) * g.n_orb * g.bc);
+    L.vloc_cur = c.take<double>(g.N * 8);
+    L.vloc_next = c.take<double>(g.N * 8);
+    L.vstatic = c.take<double>(g.N * 8);
+    for (int i = 0; i < 3; ++i) L.hist[i] = c.take<double>(g.N * 8);
+    L.rho = c.take<double>(g.N * 8);
+    L.vh = c.take<double>(g.N * 8);
+    L.rhok = c.take<double2>(g.nhalf * 16);
+    L.spec = c.take<double2>(g.nhalf * 16);
+    L.phase = c.take<double2>((size_t)std::max(1, g.n_ions) * (g.nx + g.ny + g.nz) * 16);
+    L.fft_work = c.take<void>(g.fft_work);
+    const size_t ion3 = (size_t)std::max(1, g.n_ions) * 3 * 8;
+    L.pos = c.take<double>(ion3);
+    L.pos_next = c.take<double>(ion3);
+    L.vel = c.take<double>(ion3);
+    L.frc = c.take<double>(ion3);
+    L.mass = c.take<double>(ion3 / 3);
+    L.zval = c.take<double>(ion3 / 3);
+    for (int t = 0; t < 2; ++t) {
+        L.tidx[t] = c.take<int32_t>((size_t)std::max(1, g.n_ions) * g.kcap * 4);
+        L.tp[t] = c.take<void>((size_t)std::max(1, g.n_ions) * g.kcap * g.br);
+        L.tbox[t] = c.take<void>((size_t)std::max(1, g.n_ions) * g.kcap * g.br);
+        L.tstart[t] = c.take<int32_t>((size_t)std::max(1, g.n_ions) * 3 * 4);
+        L.tcount[t] = c.take<int32_t>((size_t)std::max(1, g.n_ions) * 4);
+        L.tmask[t] = c.take<uint32_t>((size_t)g.nz * g.nyt * g.words * 4);
+    }
+    L.fnl = c.take<double>(ion3);
+    L.enl_part = c.take<double>(ion3 / 3);
+    L.floc_part = c.take<double>((size_t)std::max(1, g.n_ions) * g.floc_chunks * 3 * 8);
+    L.fion = c.take<double>(ion3);
+    L.eion_part = c.take<double>(ion3 / 3);
+    L.ewald_sg = c.take<double2>((size_t)std::max(1, g.ewald_ng) * 16);
+    L.erec_part = c.take<double>((size_t)((std::max(1, g.ewald_ng) + 255) / 256) * 8);
+    L.ewald_gv = c.take<double>((size_t)std::max(1, g.ewald_ng) * 3 * 8);
+    L.ewald_wv = c.take<double>((size_t)std::max(1, g.ewald_ng) * 8);
+    L.norm_part = c.take<double>((size_t)g.n_orb * g.nyt * g.nzc * 8);
+    L.kin_part = c.take<double>((size_t)g.n_orb * g.nyt * g.nzc * 8);
+    L.hxc_part = c.take<double>((size_t)g.nblk256 * 3 * 8);
+    L.loc_part = c.take<double>((size_t)g.nblk256 * 8);
+    L.rep = c.take<double>(SLOT_COUNT * 8);
+    L.total = c.off;
+    return L;
+}
+
+struct me_system {
+    me_params prm{};
+    std::vector<double> pos0, vel0, mass, zval;
+    Geometry g{};
+    Layout w{};
+    hipStream_t stream = nullptr;
+    KbGeom geo{};
+    EwaldHost ew;
+    EwaldPlan ewp{};
+    rocfft_plan r2c = nullptr, c2r = nullptr;
+    rocfft_execution_info info = nullptr;
+    int tab_cur = 0;
+    int hist_count = 0, hist_newest = 0;
+    bool has_state = false;
+    bool static_set = false;
+    int64_t step = 0;
+    std::string err;
+    // timing of the Horner-stage stencil launches
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<double> ev_bytes;
+    std::vector<hipEvent_t> ev_pool;
+    double rep_host[SLOT_COUNT];
+};
+
+namespace {
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            sys->err = std::string(#expr) + ": " + hipGetErrorString(e_);               \
+            return ME_EDEVICE;                                                         \
+        }                                                                              \
+    } while (0)
+
+#define FFTCHK(expr)                                                                   \
+    do {                                                                               \
+        rocfft_status e_ = (expr);                                                     \
+        if (e_ != rocfft_status_success) {                                             \
+            sys->err = std::string(#expr) + ": rocfft status " + std::to_string((int)e_); \
+            return ME_EDEVICE;                                                         \
+        }                                                                              \
+    } while (0)
+
+#define CHK(expr)                                                                      \
+    do {                                                                               \
+        me_status s_ = (expr);                                                         \
+        if (s_ != ME_OK) return s_;                                                    \
+    } while (0)
+
+KbTables tables(me_system* sys, int t) {
+    KbTables k;
+    k.idx = sys->w.tidx[t];
+    k.p = sys->w.tp[t];
+    k.pbox = sys->w.tbox[t];
+    k.start = sys->w.tstart[t];
+    for (int a = 0; a < 3; ++a) k.side[a] = sys->g.side[a];
+    k.m = sys->g.m;
+    k.count = sys->w.tcount[t];
+    k.mask = sys->w.tmask[t];
+    k.kcap = sys->g.kcap;
+    k.words = sys->g.words;
+    k.ty = sys->g.ty;
+    return k;
+}
+
+double Lx(const me_system* s) { return s->g.nx * s->prm.h; }
+
+me_status fft_r2c(me_system* sys, double* in, double2* out) {
+    void* i[1] = {in};
+    void* o[1] = {out};
+    FFTCHK(rocfft_execute(sys->r2c, i, o, sys->info));
+    return ME_OK;
+}
+
+me_status fft_c2r(me_system* sys, double2* in, double* out) {
+    void* i[1] = {in};
+    void* o[1] = {out};
+    FFTCHK(rocfft_execute(sys->c2r, i, o, sys->info));
+    return ME_OK;
+}
+
+// V_loc at positions `pos` (device) into `out` (+ the static potential).
+// Leaves the phase tables of `pos` in w.phase.
+me_status ion_fields(me_system* sys, const double* pos, double* out) {
+    const Geometry& g = sys->g;
+    const double L[3] = {g.nx * sys->prm.h, g.ny * sys->prm.h, g.nz * sys->prm.h};
+    HIPCHK(launch_phases(pos, g.n_ions, g.nx, g.ny, g.nz, L, sys->w.phase, sys->stream));
+    HIPCHK(launch_vloc_spectrum(sys->w.phase, sys->w.zval, g.n_ions, g.nx, g.ny, g.nz, L,
+                                sys->prm.loc_a, sys->w.spec, sys->stream));
+    CHK(fft_c2r(sys, sys->w.spec, out));
+    if (sys->static_set) HIPCHK(launch_add(out, sys->w.vstatic, g.N, sys->stream));
+    return ME_OK;
+}
+
+me_status build_tables(me_system* sys, const double* pos, int t) {
+    const Geometry& g = sys->g;
+    if (g.f64)
+        HIPCHK(launch_kb_tables<double>(pos, g.n_ions, g.nx, g.ny, g.nz, sys->geo, tables(sys, t), sys->stream));
+    else
+        HIPCHK(launch_kb_tables<float>(pos, g.n_ions, g.nx, g.ny, g.nz, sys->geo, tables(sys, t), sys->stream));
+    return ME_OK;
+}
+
+// density, Hartree + exchange of the current orbitals; pushes v_Hxc onto the
+// history (or, with push = false, only refreshes the energy partials)
+me_status density_vhxc(me_system* sys, bool energy, bool push = true) {
+    const Geometry& g = sys->g;
+    const double L[3] = {g.nx * sys->prm.h, g.ny * sys->prm.h, g.nz * sys->prm.h};
+    if (g.f64)
+        HIPCHK(launch_density<double>((const double2*)sys->w.psi, g.stride, g.n_orb, g.N, sys->prm.occ, sys->w.rho, sys->stream));
+    else
+        HIPCHK(launch_density<float>((const float2*)sys->w.psi, g.stride, g.n_orb, g.N, sys->prm.occ, sys->w.rho, sys->stream));
+    CHK(fft_r2c(sys, sys->w.rho, sys->w.rhok));
+    HIPCHK(launch_hartree_spectrum(sys->w.rhok, g.nx, g.ny, g.nz, L, sys->w.spec, sys->stream));
+    CHK(fft_c2r(sys, sys->w.spec, sys->w.vh));
+    if (!push) {
+        HIPCHK(launch_vhxc(sys->w.rho, sys->w.vh, g.N, sys->w.vh, energy ? sys->w.hxc_part : nullptr,
+                           sys->stream));
+        return ME_OK;
+    }
+    const int slot = sys->hist_count == 0 ? 0 : (sys->hist_newest + 1) % 3;
+    HIPCHK(launch_vhxc(sys->w.rho, sys->w.vh, g.N, sys->w.hist[slot], energy ? sys->w.hxc_part : nullptr,
+                       sys->stream));
+    sys->hist_newest = slot;
+    sys->hist_count = std::min(3, sys->hist_count + 1);
+    return ME_OK;
+}
+
+// forces at `pos` (phases of `pos` already in w.phase, tables t at pos);
+// partial results in floc_part, fnl, fion
+me_status forces_parts(me_system* sys, const double* pos, int t) {
+    const Geometry& g = sys->g;
+    const double L[3] = {g.nx * sys->prm.h, g.ny * sys->prm.h, g.nz * sys->prm.h};
+    HIPCHK(launch_local_forces(sys->w.rhok, sys->w.phase, sys->w.zval, g.n_ions, g.nx, g.ny, g.nz, L,
+                               sys->prm.h, sys->prm.loc_a, sys->w.floc_part, sys->stream));
+    if (g.f64)
+        HIPCHK(launch_kb_forces<double>((const double2*)sys->w.psi, g.stride, g.n_orb, g.n_ions, tables(sys, t), pos,
+                                        sys->geo, g.nx, g.ny, sys->prm.occ, sys->prm.kb_energy, sys->w.fnl,
+                                        sys->w.enl_part, sys->stream));
+    else
+        HIPCHK(launch_kb_forces<float>((const float2*)sys->w.psi, g.stride, g.n_orb, g.n_ions, tables(sys, t), pos,
+                                       sys->geo, g.nx, g.ny, sys->prm.occ, sys->prm.kb_energy, sys->w.fnl,
+                                       sys->w.enl_part, sys->stream));
+    HIPCHK(launch_ewald(sys->ewp, pos, sys->w.zval, g.n_ions, sys->w.ewald_sg, sys->w.erec_part, sys->w.fion,
+                        sys->w.eion_part, sys->stream));
+    return ME_OK;
+}
+
+hipEvent_t pooled_event(me_system* sys) {
+    if (!sys->ev_pool.empty()) {
+        hipEvent_t e = sys->ev_pool.back();
+        sys->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+template <typename T>
+StencilArgs<T> base_args(me_system* sys, const T* v, const cx_t<T>* cnl, int t, int n_orb) {
+    const Geometry& g = sys->g;
+    StencilArgs<T> a{};
+    a.v = v;
+    a.stride = g.stride;
+    a.nx = g.nx; a.ny = g.ny; a.nz = g.nz;
+    a.n_orb = n_orb;
+    a.zchunk = g.zchunk;
+    a.nyt = g.nyt;
+    a.nzc = g.nzc;
+    a.kin = (T)(-0.5 / (sys->prm.h * sys->prm.h));
+    a.cnl = g.n_ions > 0 ? cnl : nullptr;
+    a.mask = sys->w.tmask[t];
+    a.words = g.words;
+    a.pbox = (const T*)sys->w.tbox[t];
+    a.start = sys->w.tstart[t];
+    for (int k = 0; k < 3; ++k) a.side[k] = g.side[k];
+    return a;
+}
+
+// One Taylor exponential psi <- T_K(tau, H) psi, Horner form:
+// u_K = psi, u_{k-1} = psi + (-i tau/k) H u_k, result u_0 written over psi.
+template <typename T>
+me_status exponential(me_system* sys, const T* veff, int t, bool last) {
+    using C = cx_t<T>;
+    const Geometry& g = sys->g;
+    const double tau = sys->prm.dt / (2.0 * sys->prm.mu);
+    const int K = sys->prm.taylor_order;
+    C* psi = (C*)sys->w.psi;
+    C* bufs[2] = {(C*)sys->w.bufA, (C*)sys->w.bufB};
+    const double ekb_h3 = sys->prm.kb_energy * sys->prm.h * sys->prm.h * sys->prm.h;
+    const C* u = psi;
+    int nb = 0;
+    for (int k = K; k >= 1; --k) {
+        // the last stage overwrites psi in place (each point reads its own
+        // psi0 only), except for K = 1 where it also reads psi's neighbours
+        C* out = (k == 1 && K > 1) ? psi : bufs[nb];
+        HIPCHK(launch_kb_gather<T>(u, g.stride, g.n_orb, g.n_ions, tables(sys, t), ekb_h3, (C*)sys->w.cnl,
+                                   sys->stream));
+        StencilArgs<T> a = base_args<T>(sys, veff, (const C*)sys->w.cnl, t, g.n_orb);
+        a.u = u;
+        a.psi0 = psi;
+        a.out = out;
+        a.alpha = (T)(-tau / k);
+        const bool norm = last && k == 1;
+        a.partial = norm ? sys->w.norm_part : nullptr;
+        const int mode = k == K ? MODE_HORNER_FIRST : MODE_HORNER;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (sys->timing) {
+            e0 = pooled_event(sys);
+            e1 = pooled_event(sys);
+            if (e0 && e1) HIPCHK(hipEventRecord(e0, sys->stream));
+        }
+        HIPCHK(launch_stencil<T>(a, mode, norm, g.ty, sys->stream));
+        if (sys->timing && e0 && e1) {
+            HIPCHK(hipEventRecord(e1, sys->stream));
+            sys->ev.emplace_back(e0, e1);
+            const double streams = mode == MODE_HORNER_FIRST ? 2.0 : 3.0;
+            sys->ev_bytes.push_back(streams * g.bc * (double)g.N * g.n_orb + (double)g.br * g.N);
+        }
+        u = out;
+        nb ^= 1;
+    }
+    if (K == 1) std::swap(sys->w.psi, sys->w.bufA);
+    return ME_OK;
+}
+
+template <typename T>
+me_status two_exponentials(me_system* sys) {
+    const int next = sys->tab_cur ^ 1;
+    CHK(exponential<T>(sys, (const T*)sys->w.veff0, sys->tab_cur, false));
+    CHK(exponential<T>(sys, (const T*)sys->w.veff1, next, true));
+    return ME_OK;
+}
+
+me_status make_veff(me_system* sys, double eps, bool both) {
+    const Geometry& g = sys->g;
+    const double* hn = sys->w.hist[sys->hist_newest];
+    const double* hn1 = sys->w.hist[(sys->hist_newest + 2) % 3];
+    const double* hn2 = sys->w.hist[(sys->hist_newest + 1) % 3];
+    if (g.f64)
+        HIPCHK(launch_veff<double>(sys->w.vloc_cur, sys->w.vloc_next, hn, hn1, hn2, sys->hist_count, g.nx, g.N,
+                                   sys->prm.h, Lx(sys), eps, (double*)sys->w.veff0,
+                                   both ? (double*)sys->w.veff1 : nullptr, sys->stream));
+    else
+        HIPCHK(launch_veff<float>(sys->w.vloc_cur, sys->w.vloc_next, hn, hn1, hn2, sys->hist_count, g.nx, g.N,
+                                  sys->prm.h, Lx(sys), eps, (float*)sys->w.veff0,
+                                  both ? (float*)sys->w.veff1 : nullptr, sys->stream));
+    return ME_OK;
+}
+
+// fill the report buffer (norm check always; energies when `energy`)
+me_status finalize(me_system* sys, bool with_norm, bool energy) {
+    const Geometry& g = sys->g;
+    if (energy) {
+        // kinetic expectation per orbital, E_loc = h^3 sum rho V_loc
+        if (g.f64) {
+            StencilArgs<double> a = base_args<double>(sys, nullptr, nullptr, sys->tab_cur, g.n_orb);
+            a.u = (const double2*)sys->w.psi;
+            a.partial = sys->w.kin_part;
+            HIPCHK(launch_stencil<double>(a, MODE_EXPECT_T, false, g.ty, sys->stream));
+        } else {
+            StencilArgs<float> a = base_args<float>(sys, nullptr, nullptr, sys->tab_cur, g.n_orb);
+            a.u = (const float2*)sys->w.psi;
+            a.partial = sys->w.kin_part;
+            HIPCHK(launch_stencil<float>(a, MODE_EXPECT_T, false, g.ty, sys->stream));
+        }
+        HIPCHK(launch_dot_partial(sys->w.rho, sys->w.vloc_cur, g.N, sys->w.loc_part, sys->stream));
+    }
+    FinalizeArgs f{};
+    f.rep = sys->w.rep;
+    f.norm_part = with_norm ? sys->w.norm_part : nullptr;
+    f.n_orb = g.n_orb;
+    f.norm_tiles = g.nyt * g.nzc;
+    f.norm_tol = g.f64 ? 1e-6 : 1e-5;
+    f.dv = sys->prm.h * sys->prm.h * sys->prm.h;
+    f.occ = sys->prm.occ;
+    f.energy = energy ? 1 : 0;
+    f.kin_part = sys->w.kin_part;
+    f.kin_n = (int64_t)g.n_orb * g.nyt * g.nzc;
+    f.hxc_part = sys->w.hxc_part;
+    f.hxc_n = g.nblk256;
+    f.loc_part = sys->w.loc_part;
+    f.loc_n = g.nblk256;
+    f.enl_part = sys->w.enl_part;
+    f.eion_part = sys->w.eion_part;
+    f.erec_part = sys->w.erec_part;
+    f.erec_n = (std::max(1, sys->ewp.ng) + 255) / 256;
+    f.ewald_rec_scale = 2.0 * M_PI / (sys->ew.L * sys->ew.L * sys->ew.L);
+    f.ewald_const = sys->ew.e_const;
+    f.vel = sys->w.vel;
+    f.frc = sys->w.frc;
+    f.mass = sys->w.mass;
+    f.n_ions = g.n_ions;
+    HIPCHK(launch_report(f, sys->stream));
+    return ME_OK;
+}
+
+me_status read_report(me_system* sys, me_step_report* rep) {
+    HIPCHK(hipMemcpyAsync(sys->rep_host, sys->w.rep, sizeof(sys->rep_host), hipMemcpyDeviceToHost, sys->stream));
+    HIPCHK(hipStreamSynchronize(sys->stream));
+    const double* r = sys->rep_host;
+    if (rep) {
+        rep->e_kinetic = r[SLOT_EKIN];
+        rep->e_local = r[SLOT_ELOC];
+        rep->e_hartree = r[SLOT_EH];
+        rep->e_xc = r[SLOT_EX];
+        rep->e_nonlocal = r[SLOT_ENL];
+        rep->e_ion = r[SLOT_EION];
+        rep->e_ks = r[SLOT_EKS];
+        rep->e_ion_kinetic = r[SLOT_EIONKIN];
+        rep->e_total = r[SLOT_ETOT];
+        rep->max_norm_dev = r[SLOT_NORM_DEV];
+        rep->max_force = r[SLOT_FMAX];
+        rep->charge = r[SLOT_CHARGE];
+        rep->step = sys->step;
+    }
+    if (r[SLOT_UNSTABLE] != 0.0) {
+        sys->err = "orbital norm grew beyond tolerance or became non-finite";
+        return ME_EUNSTABLE;
+    }
+    return ME_OK;
+}
+
+me_status initial_fields(me_system* sys) {
+    // V_loc, tables and forces at the current positions; density and v_Hxc
+    sys->hist_count = 0;
+    sys->hist_newest = 0;
+    sys->tab_cur = 0;
+    CHK(build_tables(sys, sys->w.pos, sys->tab_cur));
+    CHK(density_vhxc(sys, true));
+    CHK(ion_fields(sys, sys->w.pos, sys->w.vloc_cur));
+    CHK(forces_parts(sys, sys->w.pos, sys->tab_cur));
+    HIPCHK(hipMemcpyAsync(sys->w.pos_next, sys->w.pos, 3 * 8 * std::max(1, sys->g.n_ions),
+                          hipMemcpyDeviceToDevice, sys->stream));
+    HIPCHK(launch_ions_finish(sys->w.pos, sys->w.vel, sys->w.frc, sys->w.pos_next, sys->w.floc_part,
+                              sys->g.floc_chunks, sys->w.fnl, sys->w.fion, sys->w.mass, sys->g.n_ions,
+                              sys->prm.dt, 1, sys->stream));
+    HIPCHK(hipMemsetAsync(sys->w.rep, 0, SLOT_COUNT * 8, sys->stream));
+    return ME_OK;
+}
+
+template <typename T>
+me_status step_impl(me_system* sys, double eps, bool energy) {
+    const Geometry& g = sys->g;
+    const int next = sys->tab_cur ^ 1;
+    // 1. ions: R(t+dt) by velocity Verlet
+    HIPCHK(launch_ions_predict(sys->w.pos, sys->w.vel, sys->w.frc, sys->w.mass, g.n_ions, sys->prm.dt,
+                               sys->prm.freeze_ions, sys->w.pos_next, sys->stream));
+    // 2. ionic part of H(t+dt): V_loc and projector tables at R(t+dt)
+    CHK(ion_fields(sys, sys->w.pos_next, sys->w.vloc_next));
+    CHK(build_tables(sys, sys->w.pos_next, next));
+    CHK(make_veff(sys, eps, true));
+    // 3-4. AETRS: exp(-i tau H(t+dt)) exp(-i tau H(t))
+    CHK(two_exponentials<T>(sys));
+    // 5. density, Hartree + exchange, forces at the new positions
+    CHK(density_vhxc(sys, energy));
+    CHK(forces_parts(sys, sys->w.pos_next, next));
+    HIPCHK(launch_ions_finish(sys->w.pos, sys->w.vel, sys->w.frc, sys->w.pos_next, sys->w.floc_part,
+                              g.floc_chunks, sys->w.fnl, sys->w.fion, sys->w.mass, g.n_ions, sys->prm.dt,
+                              sys->prm.freeze_ions, sys->stream));
+    std::swap(sys->w.vloc_cur, sys->w.vloc_next);
+    sys->tab_cur = next;
+    sys->step += 1;
+    return finalize(sys, true, energy);
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+const char* me_strerror(me_status s) {
+    switch (s) {
+    case ME_OK: return "ok";
+    case ME_EINVAL: return "invalid argument";
+    case ME_ENOMEM: return "workspace too small";
+    case ME_EDEVICE: return "device error";
+    case ME_ESTATE: return "invalid state";
+    case ME_EUNSTABLE: return "propagation unstable";
+    case ME_EUNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* me_last_error(const me_system* sys) {
+    return sys ? sys->err.c_str() : g_init_error.c_str();
+}
+
+me_status me_workspace_size(const me_params* p, size_t* bytes) {
+    try {
+        std::string err;
+        me_status st = validate(p, err);
+        if (st != ME_OK) { g_init_error = err; return st; }
+        if (!bytes) { g_init_error = "bytes is NULL"; return ME_EINVAL; }
+        Geometry g = make_geometry(p);
+        std::vector<double> z(p->zval, p->zval + p->n_ions);
+        g.ewald_ng = (int)ewald_setup(p->n[0] * p->h, z).wv.size();
+        *bytes = carve(g, nullptr).total;
+        return ME_OK;
+    } catch (...) {
+        g_init_error = "internal error";
+        return ME_EINVAL;
+    }
+}
+
+me_status me_init_system(const me_params* p, void* workspace, size_t ws_bytes, void* stream,
+                         me_system** out) {
+    me_system* sys = nullptr;
+    try {
+        std::string err;
+        me_status st = validate(p, err);
+        if (st != ME_OK) { g_init_error = err; return st; }
+        if (!out || !workspace) { g_init_error = "out/workspace is NULL"; return ME_EINVAL; }
+        if (reinterpret_cast<uintptr_t>(workspace) % 256) { g_init_error = "workspace must be 256-byte aligned"; return ME_EINVAL; }
+        if (p->n[0] != p->n[1] || p->n[1] != p->n[2]) {
+            g_init_error = "only cubic grids are supported";
+            return ME_EUNSUPPORTED;
+        }
+        sys = new (std::nothrow) me_system();
+        if (!sys) { g_init_error = "out of host memory"; return ME_EINVAL; }
+        sys->prm = *p;
+        sys->pos0.assign(p->pos, p->pos + 3 * p->n_ions);
+        if (p->vel) sys->vel0.assign(p->vel, p->vel + 3 * p->n_ions);
+        else sys->vel0.assign(3 * p->n_ions, 0.0);
+        sys->mass.assign(p->mass, p->mass + p->n_ions);
+        sys->zval.assign(p->zval, p->zval + p->n_ions);
+        sys->prm.pos = sys->prm.vel = sys->prm.mass = sys->prm.zval = nullptr;
+        sys->g = make_geometry(p);
+        sys->ew = ewald_setup(p->n[0] * p->h, sys->zval);
+        sys->g.ewald_ng = (int)sys->ew.wv.size();
+        const size_t need = carve(sys->g, nullptr).total;
+        if (ws_bytes < need) {
+            g_init_error = "workspace too small: need " + std::to_string(need) + " bytes";
+            delete sys;
+            return ME_ENOMEM;
+        }
+        sys->w = carve(sys->g, reinterpret_cast<char*>(workspace));
+        sys->stream = reinterpret_cast<hipStream_t>(stream);
+        const double L = p->n[0] * p->h;
+        sys->geo.h = p->h;
+        sys->geo.L[0] = p->n[0] * p->h;
+        sys->geo.L[1] = p->n[1] * p->h;
+        sys->geo.L[2] = p->n[2] * p->h;
+        sys->geo.rcut2 = p->kb_rcut * p->kb_rcut;
+        sys->geo.inv2s2 = 1.0 / (2.0 * p->kb_sigma * p->kb_sigma);
+        sys->geo.pnorm = std::pow(M_PI * p->kb_sigma * p->kb_sigma, -0.75);
+        sys->geo.inv_s2 = 1.0 / (p->kb_sigma * p->kb_sigma);
+        sys->ewp.L = L;
+        sys->ewp.eta = sys->ew.eta;
+        sys->ewp.rc = sys->ew.rc;
+        sys->ewp.nmax = sys->ew.nmax;
+        sys->ewp.ng = sys->g.ewald_ng;
+        sys->ewp.gv = sys->w.ewald_gv;
+        sys->ewp.wv = sys->w.ewald_wv;
+
+        auto fail = [&](me_status s2) {
+            g_init_error = sys->err;
+            if (sys->info) rocfft_execution_info_destroy(sys->info);
+            if (sys->r2c) rocfft_plan_destroy(sys->r2c);
+            if (sys->c2r) rocfft_plan_destroy(sys->c2r);
+            delete sys;
+            return s2;
+        };
+#define INITCHK(expr)                                                       \
+    do {                                                                    \
+        hipError_t e_ = (expr);                                             \
+        if (e_ != hipSuccess) {                                             \
+            sys->err = std::string(#expr) + ": " + hipGetErrorString(e_);    \
+            return fail(ME_EDEVICE);                                        \
+        }                                                                   \
+    } while (0)
+        const size_t n3 = 3 * (size_t)p->n_ions * sizeof(double);
+        if (p->n_ions > 0) {
+            INITCHK(hipMemcpyAsync(sys->w.pos, sys->pos0.data(), n3, hipMemcpyHostToDevice, sys->stream));
+            INITCHK(hipMemcpyAsync(sys->w.vel, sys->vel0.data(), n3, hipMemcpyHostToDevice, sys->stream));
+            INITCHK(hipMemcpyAsync(sys->w.mass, sys->mass.data(), n3 / 3, hipMemcpyHostToDevice, sys->stream));
+            INITCHK(hipMemcpyAsync(sys->w.zval, sys->zval.data(), n3 / 3, hipMemcpyHostToDevice, sys->stream));
+            INITCHK(hipMemcpyAsync(sys->w.ewald_gv, sys->ew.gv.data(), sys->ew.gv.size() * 8,
+                                   hipMemcpyHostToDevice, sys->stream));
+            INITCHK(hipMemcpyAsync(sys->w.ewald_wv, sys->ew.wv.data(), sys->ew.wv.size() * 8,
+                                   hipMemcpyHostToDevice, sys->stream));
+        }
+        INITCHK(hipMemsetAsync(sys->w.vstatic, 0, sys->g.N * 8, sys->stream));
+        INITCHK(hipMemsetAsync(sys->w.rep, 0, SLOT_COUNT * 8, sys->stream));
+        // FFT plans: lengths fastest-first
+        if (rocfft_setup() != rocfft_status_success) { sys->err = "rocfft_setup failed"; return fail(ME_EDEVICE); }
+        size_t len[3] = {(size_t)p->n[0], (size_t)p->n[1], (size_t)p->n[2]};
+        if (rocfft_plan_create(&sys->r2c, rocfft_placement_notinplace, rocfft_transform_type_real_forward,
+                               rocfft_precision_double, 3, len, 1, nullptr) != rocfft_status_success ||
+            rocfft_plan_create(&sys->c2r, rocfft_placement_notinplace, rocfft_transform_type_real_inverse,
+                               rocfft_precision_double, 3, len, 1, nullptr) != rocfft_status_success) {
+            sys->err = "rocfft_plan_create failed";
+            return fail(ME_EDEVICE);
+        }
+        size_t w1 = 0, w2 = 0;
+        rocfft_plan_get_work_buffer_size(sys->r2c, &w1);
+        rocfft_plan_get_work_buffer_size(sys->c2r, &w2);
+        if (std::max(w1, w2) > sys->g.fft_work) {
+            sys->err = "rocFFT work buffer larger than reserved";
+            return fail(ME_EUNSUPPORTED);
+        }
+        if (rocfft_execution_info_create(&sys->info) != rocfft_status_success ||
+            rocfft_execution_info_set_stream(sys->info, sys->stream) != rocfft_status_success ||
+            (std::max(w1, w2) > 0 &&
+             rocfft_execution_info_set_work_buffer(sys->info, sys->w.fft_work, sys->g.fft_work) !=
+                 rocfft_status_success)) {
+            sys->err = "rocfft execution info failed";
+            return fail(ME_EDEVICE);
+        }
+#undef INITCHK
+        *out = sys;
+        return ME_OK;
+    } catch (...) {
+        g_init_error = "internal error during init";
+        delete sys;
+        return ME_EDEVICE;
+    }
+}
+
+me_status me_destroy(me_system* sys) {
+    if (!sys) return ME_OK;
+    hipStreamSynchronize(sys->stream);
+    if (sys->info) rocfft_execution_info_destroy(sys->info);
+    if (sys->r2c) rocfft_plan_destroy(sys->r2c);
+    if (sys->c2r) rocfft_plan_destroy(sys->c2r);
+    for (auto& e : sys->ev) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
+    for (auto& e : sys->ev_pool) hipEventDestroy(e);
+    delete sys;
+    return ME_OK;
+}
+
+me_status me_sync(me_system* sys) {
+    if (!sys) return ME_EINVAL;
+    HIPCHK(hipStreamSynchronize(sys->stream));
+    HIPCHK(hipGetLastError());
+    if (sys->has_state) return read_report(sys, nullptr);
+    return ME_OK;
+}
+
+me_status me_set_state(me_system* sys, const void* psi_dev, int64_t orb_stride) {
+    if (!sys) return ME_EINVAL;
+    if (!psi_dev || orb_stride < sys->g.N) { sys->err = "psi is NULL or orb_stride < N"; return ME_EINVAL; }
+    try {
+        const Geometry& g = sys->g;
+        HIPCHK(hipMemcpy2DAsync(sys->w.psi, g.stride * g.bc, psi_dev, orb_stride * g.bc, g.N * g.bc, g.n_orb,
+                                hipMemcpyDeviceToDevice, sys->stream));
+        const size_t n3 = 3 * (size_t)g.n_ions * sizeof(double);
+        if (g.n_ions > 0) {
+            HIPCHK(hipMemcpyAsync(sys->w.pos, sys->pos0.data(), n3, hipMemcpyHostToDevice, sys->stream));
+            HIPCHK(hipMemcpyAsync(sys->w.vel, sys->vel0.data(), n3, hipMemcpyHostToDevice, sys->stream));
+        }
+        CHK(initial_fields(sys));
+        sys->step = 0;
+        sys->has_state = true;
+        HIPCHK(hipStreamSynchronize(sys->stream));
+        return ME_OK;
+    } catch (...) {
+        sys->err = "internal error";
+        return ME_EDEVICE;
+    }
+}
+
+me_status me_get_state(me_system* sys, void* psi_dev, int64_t orb_stride) {
+    if (!sys) return ME_EINVAL;
+    if (!sys->has_state) { sys->err = "no state"; return ME_ESTATE; }
+    if (!psi_dev || orb_stride < sys->g.N) { sys->err = "psi is NULL or orb_stride < N"; return ME_EINVAL; }
+    const Geometry& g = sys->g;
+    HIPCHK(hipMemcpy2DAsync(psi_dev, orb_stride * g.bc, sys->w.psi, g.stride * g.bc, g.N * g.bc, g.n_orb,
+                            hipMemcpyDeviceToDevice, sys->stream));
+    return ME_OK;
+}
+
+me_status me_apply_H(me_system* sys, const void* psi_in_dev, void* hpsi_out_dev, int32_t n_orb,
+                     int64_t orb_stride) {
+    if (!sys) return ME_EINVAL;
+    if (!sys->has_state) { sys->err = "no state"; return ME_ESTATE; }
+    const Geometry& g = sys->g;
+    if (!psi_in_dev || !hpsi_out_dev || n_orb < 1 || orb_stride < g.N) {
+        sys->err = "bad apply_H arguments";
+        return ME_EINVAL;
+    }
+    const char* a0 = (const char*)psi_in_dev;
+    const char* a1 = a0 + ((size_t)(n_orb - 1) * orb_stride + g.N) * g.bc;
+    const char* b0 = (const char*)hpsi_out_dev;
+    const char* b1 = b0 + ((size_t)(n_orb - 1) * orb_stride + g.N) * g.bc;
+    if (a0 < b1 && b0 < a1) { sys->err = "input and output overlap"; return ME_EINVAL; }
+    if (((uintptr_t)a0 | (uintptr_t)b0 | (uintptr_t)(orb_stride * g.bc)) % 16) {
+        sys->err = "orbital rows must be 16-byte aligned";
+        return ME_EINVAL;
+    }
+    CHK(make_veff(sys, 0.0, false));
+    const double ekb_h3 = sys->prm.kb_energy * sys->prm.h * sys->prm.h * sys->prm.h;
+    for (int o0 = 0; o0 < n_orb; o0 += g.n_orb) {
+        const int nb = std::min(g.n_orb, n_orb - o0);
+        if (g.f64) {
+            const double2* in = (const double2*)psi_in_dev + (size_t)o0 * orb_stride;
+            double2* outp = (double2*)hpsi_out_dev + (size_t)o0 * orb_stride;
+            HIPCHK(launch_kb_gather<double>(in, orb_stride, nb, g.n_ions, tables(sys, sys->tab_cur), ekb_h3,
+                                            (double2*)sys->w.cnl, sys->stream));
+            StencilArgs<double> a = base_args<double>(sys, (const double*)sys->w.veff0, (const double2*)sys->w.cnl,
+                                                      sys->tab_cur, nb);
+            a.u = in; a.psi0 = in; a.out = outp; a.stride = orb_stride;
+            a.zchunk = g.nz; a.nzc = 1;
+            HIPCHK(launch_stencil<double>(a, MODE_APPLY, false, g.ty, sys->stream));
+        } else {
+            const float2* in = (const float2*)psi_in_dev + (size_t)o0 * orb_stride;
+            float2* outp = (float2*)hpsi_out_dev + (size_t)o0 * orb_stride;
+            HIPCHK(launch_kb_gather<float>(in, orb_stride, nb, g.n_ions, tables(sys, sys->tab_cur), ekb_h3,
+                                           (float2*)sys->w.cnl, sys->stream));
+            StencilArgs<float> a = base_args<float>(sys, (const float*)sys->w.veff0, (const float2*)sys->w.cnl,
+                                                    sys->tab_cur, nb);
+            a.u = in; a.psi0 = in; a.out = outp; a.stride = orb_stride;
+            a.zchunk = g.nz; a.nzc = 1;
+            HIPCHK(launch_stencil<float>(a, MODE_APPLY, false, g.ty, sys->stream));
+        }
+    }
+    return ME_OK;
+}
+
+me_status me_propagate_step(me_system* sys, const double* ctrl, me_step_report* rep) {
+    if (!sys) return ME_EINVAL;
+    if (!sys->has_state) { sys->err = "no state: call me_set_state first"; return ME_ESTATE; }
+    const double eps = ctrl ? *ctrl : 0.0;
+    if (!std::isfinite(eps)) { sys->err = "control amplitude must be finite"; return ME_EINVAL; }
+    try {
+        me_status st = sys->g.f64 ? step_impl<double>(sys, eps, rep != nullptr)
+                                  : step_impl<float>(sys, eps, rep != nullptr);
+        if (st != ME_OK) return st;
+        if (rep) return read_report(sys, rep);
+        return ME_OK;
+    } catch (...) {
+        sys->err = "internal error";
+        return ME_EDEVICE;
+    }
+}
+
+me_status me_report(me_system* sys, me_step_report* rep) {
+    if (!sys || !rep) return ME_EINVAL;
+    if (!sys->has_state) { sys->err = "no state"; return ME_ESTATE; }
+    // energies of the current state need fresh partials of rho V_H and e_x,
+    // and the nonlocal / Ewald parts at the current positions
+    const Geometry& g = sys->g;
+    const double L[3] = {g.nx * sys->prm.h, g.ny * sys->prm.h, g.nz * sys->prm.h};
+    CHK(density_vhxc(sys, true, false));
+    HIPCHK(launch_phases(sys->w.pos, g.n_ions, g.nx, g.ny, g.nz, L, sys->w.phase, sys->stream));
+    CHK(forces_parts(sys, sys->w.pos, sys->tab_cur));
+    CHK(finalize(sys, false, true));
+    return read_report(sys, rep);
+}
+
+me_status me_density(me_system* sys, double* rho_dev) {
+    if (!sys || !rho_dev) return ME_EINVAL;
+    if (!sys->has_state) { sys->err = "no state"; return ME_ESTATE; }
+    HIPCHK(hipMemcpyAsync(rho_dev, sys->w.rho, sys->g.N * 8, hipMemcpyDeviceToDevice, sys->stream));
+    return ME_OK;
+}
+
+me_status me_forces(me_system* sys, double* f_host) {
+    if (!sys || !f_host) return ME_EINVAL;
+    if (!sys->has_state) { sys->err = "no state"; return ME_ESTATE; }
+    if (sys->g.n_ions == 0) return ME_OK;
+    HIPCHK(hipMemcpyAsync(f_host, sys->w.frc, 3 * 8 * sys->g.n_ions, hipMemcpyDeviceToHost, sys->stream));
+    HIPCHK(hipStreamSynchronize(sys->stream));
+    return ME_OK;
+}
+
+me_status me_get_ions(me_system* sys, double* pos_host, double* vel_host) {
+    if (!sys) return ME_EINVAL;
+    if (sys->g.n_ions == 0) return ME_OK;
+    if (pos_host)
+        HIPCHK(hipMemcpyAsync(pos_host, sys->w.pos, 3 * 8 * sys->g.n_ions, hipMemcpyDeviceToHost, sys->stream));
+    if (vel_host)
+        HIPCHK(hipMemcpyAsync(vel_host, sys->w.vel, 3 * 8 * sys->g.n_ions, hipMemcpyDeviceToHost, sys->stream));
+    HIPCHK(hipStreamSynchronize(sys->stream));
+    return ME_OK;
+}
+
+me_status me_get_potential(me_system* sys, int32_t which, double* v_dev) {
+    if (!sys || !v_dev || which < 0 || which > 2) return ME_EINVAL;
+    if (!sys->has_state) { sys->err = "no state"; return ME_ESTATE; }
+    const Geometry& g = sys->g;
+    if (which == 0) {
+        HIPCHK(hipMemcpyAsync(v_dev, sys->w.vloc_cur, g.N * 8, hipMemcpyDeviceToDevice, sys->stream));
+    } else if (which == 1) {
+        HIPCHK(hipMemcpyAsync(v_dev, sys->w.hist[sys->hist_newest], g.N * 8, hipMemcpyDeviceToDevice,
+                              sys->stream));
+    } else {
+        HIPCHK(hipMemcpyAsync(v_dev, sys->w.vloc_cur, g.N * 8, hipMemcpyDeviceToDevice, sys->stream));
+        HIPCHK(launch_add(v_dev, sys->w.hist[sys->hist_newest], g.N, sys->stream));
+    }
+    return ME_OK;
+}
+
+me_status me_set_static_potential(me_system* sys, const double* dv_dev) {
+    if (!sys) return ME_EINVAL;
+    if (dv_dev) {
+        HIPCHK(hipMemcpyAsync(sys->w.vstatic, dv_dev, sys->g.N * 8, hipMemcpyDeviceToDevice, sys->stream));
+        sys->static_set = true;
+    } else {
+        HIPCHK(hipMemsetAsync(sys->w.vstatic, 0, sys->g.N * 8, sys->stream));
+        sys->static_set = false;
+    }
+    return ME_OK;
+}
+
+me_status me_timing_enable(me_system* sys, int32_t enable) {
+    if (!sys) return ME_EINVAL;
+    HIPCHK(hipStreamSynchronize(sys->stream));
+    for (auto& e : sys->ev) { sys->ev_pool.push_back(e.first); sys->ev_pool.push_back(e.second); }
+    sys->ev.clear();
+    sys->ev_bytes.clear();
+    sys->timing = enable != 0;
+    return ME_OK;
+}
+
+me_status me_timing_read(me_system* sys, int64_t* launches, double* total_ms, double* total_bytes) {
+    if (!sys || !launches || !total_ms || !total_bytes) return ME_EINVAL;
+    HIPCHK(hipStreamSynchronize(sys->stream));
+    double ms = 0.0, by = 0.0;
+    for (size_t i = 0; i < sys->ev.size(); ++i) {
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, sys->ev[i].first, sys->ev[i].second));
+        ms += t;
+        by += sys->ev_bytes[i];
+    }
+    *launches = (int64_t)sys->ev.size();
+    *total_ms = ms;
+    *total_bytes = by;
+    return ME_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// Internal declarations shared by the HIP kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+
+namespace me {
+
+// complex element type of each precision: interleaved (re, im)
+template <typename T> struct cx;
+template <> struct cx<double> { using type = double2; };
+template <> struct cx<float> { using type = float2; };
+template <typename T> using cx_t = typename cx<T>::type;
+
+// 8th-order central second difference, f'' ~ (1/h^2)[c0 f0 + sum_m cm (f_m + f_-m)]
+constexpr double FD_C0 = -205.0 / 72.0;
+constexpr double FD_C1 = 8.0 / 5.0;
+constexpr double FD_C2 = -1.0 / 5.0;
+constexpr double FD_C3 = 8.0 / 315.0;
+constexpr double FD_C4 = -1.0 / 560.0;
+
+constexpr int MAX_TAYLOR = 8;
+constexpr int MAX_WORDS = 64;    // ion bitmask words per stencil tile row (<= 2048 ions)
+
+// Geometry of the Gaussian projector, FP64 (shared by table build, stencil
+// scatter and force gather so the three agree bit for bit).
+struct KbGeom {
+    double h;
+    double L[3];
+    double rcut2;      // r_cut^2
+    double inv2s2;     // 1/(2 sigma^2)
+    double pnorm;      // (pi sigma^2)^(-3/4)
+    double inv_s2;     // 1/sigma^2
+};
+
+// Per-ion projector tables (one set per ion configuration).
+struct KbTables {
+    int32_t* idx;      // [n_ions][kcap] linear grid index
+    void* p;           // [n_ions][kcap] projector value in the compute precision
+    void* pbox;        // [n_ions][kcap] the same values on the dense candidate box (0 outside)
+    int32_t* start;    // [n_ions][3] first box point per axis, wrapped into [0, n)
+    int side[3];       // box extent per axis (kcap = side[0]*side[1]*side[2])
+    int m;             // box half-width: side = min(2m+2, n)
+    int32_t* count;    // [n_ions]
+    uint32_t* mask;    // [nz][nyt][words] ions touching (plane z, y-tile)
+    int kcap;
+    int words;
+    int ty;            // y rows per stencil tile the masks were built for
+};
+
+enum StencilMode : int {
+    MODE_APPLY = 0,        // out = H u
+    MODE_HORNER = 1,       // out = psi0 + i*alpha*(H u)
+    MODE_HORNER_FIRST = 2, // as HORNER with psi0 == u
+    MODE_EXPECT_T = 3      // partial[A][tile] = sum Re(conj(u) T u); no output
+};
+
+template <typename T>
+struct StencilArgs {
+    const cx_t<T>* u;
+    const cx_t<T>* psi0;
+    cx_t<T>* out;
+    const T* v;              // v_eff [N] (unused by EXPECT_T)
+    int64_t stride;          // complex elements between orbitals (u, psi0, out)
+    int nx, ny, nz;
+    int n_orb;
+    int zchunk;              // planes per workgroup
+    int nyt, nzc;            // tiles along y, chunks along z
+    T kin;                   // -1/(2 h^2)
+    T alpha;                 // Horner coefficient: c_k = i*alpha, alpha = -tau/k
+    // nonlocal scatter: cnl[J*n_orb + A] = E_KB * c_JA ; nullptr = no projectors
+    const cx_t<T>* cnl;
+    const uint32_t* mask;
+    int words;
+    const T* pbox;           // projector values on each ion's candidate box
+    const int32_t* start;    // box origin per ion
+    int side[3];
+    double* partial;         // [n_orb][nyt*nzc] norm or expectation partials, or nullptr
+};
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `s` and return hipGetLastError().
+template <typename T>
+hipError_t launch_stencil(const StencilArgs<T>& a, int mode, bool want_norm,
+                          int ty, hipStream_t s);
+
+template <typename T>
+hipError_t launch_kb_tables(const double* pos, int n_ions, int nx, int ny, int nz,
+                            const KbGeom& g, KbTables t, hipStream_t s);
+
+// cnl[J*n_orb + A] = ekb * h^3 sum_k p_J(k) u_A(idx_J(k))
+template <typename T>
+hipError_t launch_kb_gather(const cx_t<T>* u, int64_t stride, int n_orb, int n_ions,
+                            KbTables t, double ekb_h3, cx_t<T>* cnl, hipStream_t s);
+
+// nonlocal forces and energy, FP64 accumulation:
+// fnl[J][3] = -2 f E_KB sum_A Re(conj(c_JA) d_JA); enl_part[J] = f E_KB sum_A |c_JA|^2
+template <typename T>
+hipError_t launch_kb_forces(const cx_t<T>* psi, int64_t stride, int n_orb, int n_ions,
+                            KbTables t, const double* pos, const KbGeom& g,
+                            int nx, int ny, double occ, double ekb,
+                            double* fnl, double* enl_part, hipStream_t s);
+
+// rho[i] = occ * sum_A |psi_A[i]|^2 (FP64)
+template <typename T>
+hipError_t launch_density(const cx_t<T>* psi, int64_t stride, int n_orb, int64_t N,
+                          double occ, double* rho, hipStream_t s);
+
+}  // namespace me

@@ -1,0 +1,587 @@
+// Grid-wide quantities of one step, all in FP64: density, the local ionic
+// potential by structure factor (eq. ionicpotential), Hartree and Slater
+// exchange, the effective potentials of the two AETRS exponentials, the
+// local-potential forces (eq. ionicforces, as -dE/dR), the Ewald ion-ion
+// term, velocity Verlet and deterministic reductions.
+#include "fields.hpp"
+#include "geometry.hpp"
+
+namespace me {
+
+__device__ __forceinline__ int wavenum(int i, int n) { return i <= (n - 1) / 2 ? i : i - n; }
+
+__device__ __forceinline__ double dsum_wave(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// block-level sum for 256-thread blocks; result valid in thread 0
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+    v = dsum_wave(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    __syncthreads();
+    return r;
+}
+
+// ------------------------------------------------------------ density
+template <typename T>
+__global__ void __launch_bounds__(256) density_kernel(const cx_t<T>* __restrict__ psi, int64_t stride,
+                                                      int n_orb, int64_t N, double occ,
+                                                      double* __restrict__ rho) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double s = 0.0;
+    for (int A = 0; A < n_orb; ++A) {
+        const cx_t<T> z = psi[(int64_t)A * stride + i];
+        s += (double)z.x * (double)z.x + (double)z.y * (double)z.y;
+    }
+    rho[i] = occ * s;
+}
+
+template <typename T>
+hipError_t launch_density(const cx_t<T>* psi, int64_t stride, int n_orb, int64_t N,
+                          double occ, double* rho, hipStream_t s) {
+    density_kernel<T><<<(unsigned)((N + 255) / 256), 256, 0, s>>>(psi, stride, n_orb, N, occ, rho);
+    return hipGetLastError();
+}
+template hipError_t launch_density<double>(const cx_t<double>*, int64_t, int, int64_t, double, double*, hipStream_t);
+template hipError_t launch_density<float>(const cx_t<float>*, int64_t, int, int64_t, double, double*, hipStream_t);
+
+// ------------------------------------------------------------ phases
+// ph[J][a][i] = exp(-i G_a(i) R_Ja), G_a(i) = 2 pi m(i)/L_a, for i in [0, n_a)
+__global__ void phase_kernel(const double* __restrict__ pos, int n_ions, int nx, int ny, int nz,
+                             double Lx, double Ly, double Lz, double2* __restrict__ ph) {
+    const int nt = nx + ny + nz;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n_ions * nt) return;
+    const int J = (int)(t / nt);
+    int i = (int)(t % nt);
+    int a = 0, n = nx;
+    double L = Lx;
+    if (i >= nx) { i -= nx; a = 1; n = ny; L = Ly; if (i >= ny) { i -= ny; a = 2; n = nz; L = Lz; } }
+    const double g = 2.0 * M_PI * (double)wavenum(i, n) / L;
+    double sn, cs;
+    sincos(-g * pos[3 * J + a], &sn, &cs);
+    ph[t] = make_double2(cs, sn);
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// structure factor S(G) = sum_J Z_J exp(-i G.R_J) at box index (ix, iy, iz)
+__device__ __forceinline__ double2 sfac(const double2* __restrict__ ph, const double* __restrict__ zval,
+                                        int n_ions, int nt, int nx, int ny, int ix, int iy, int iz) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int J = 0; J < n_ions; ++J) {
+        const double2* pj = ph + (int64_t)J * nt;
+        const double2 e = cmul(cmul(pj[ix], pj[nx + iy]), pj[nx + ny + iz]);
+        s.x += zval[J] * e.x;
+        s.y += zval[J] * e.y;
+    }
+    return s;
+}
+
+__device__ __forceinline__ double vloc_ff(double g2, double a) {
+    return -4.0 * M_PI / g2 * exp(-g2 * a * a / 4.0);
+}
+
+// Half spectrum (ix in [0, nx/2]) of the Hermitian part of V_loc(G)/Omega:
+// W(k) = (V(k) + conj(V(k*)))/2, k* the index mirror; W = V(k) away from the
+// Nyquist planes.  Its complex-to-real transform is Re of the full-box sum.
+__global__ void vloc_spectrum_kernel(const double2* __restrict__ ph, const double* __restrict__ zval,
+                                     int n_ions, int nx, int ny, int nz, double Lx, double Ly,
+                                     double Lz, double a, double inv_omega,
+                                     double2* __restrict__ out) {
+    const int nh = nx / 2 + 1;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nh * ny * nz) return;
+    const int ix = (int)(t % nh);
+    const int iy = (int)((t / nh) % ny);
+    const int iz = (int)(t / ((int64_t)nh * ny));
+    const int nt = nx + ny + nz;
+    const double gx = 2.0 * M_PI * wavenum(ix, nx) / Lx;
+    const double gy = 2.0 * M_PI * wavenum(iy, ny) / Ly;
+    const double gz = 2.0 * M_PI * wavenum(iz, nz) / Lz;
+    const double g2 = gx * gx + gy * gy + gz * gz;
+    double2 w = make_double2(0.0, 0.0);
+    if (g2 > 0.0) {
+        const double2 s = sfac(ph, zval, n_ions, nt, nx, ny, ix, iy, iz);
+        const double f = vloc_ff(g2, a) * inv_omega;
+        w = make_double2(f * s.x, f * s.y);
+        const bool nyq = ((nx % 2 == 0) && ix == nx / 2) || ((ny % 2 == 0) && iy == ny / 2) ||
+                         ((nz % 2 == 0) && iz == nz / 2);
+        if (nyq) {
+            const int mx = (nx - ix) % nx, my = (ny - iy) % ny, mz = (nz - iz) % nz;
+            const double hx = 2.0 * M_PI * wavenum(mx, nx) / Lx;
+            const double hy = 2.0 * M_PI * wavenum(my, ny) / Ly;
+            const double hz = 2.0 * M_PI * wavenum(mz, nz) / Lz;
+            const double h2 = hx * hx + hy * hy + hz * hz;
+            const double2 sm = sfac(ph, zval, n_ions, nt, nx, ny, mx, my, mz);
+            const double fm = vloc_ff(h2, a) * inv_omega;
+            w = make_double2(0.5 * (w.x + fm * sm.x), 0.5 * (w.y - fm * sm.y));
+        }
+    }
+    out[t] = w;
+}
+
+// ------------------------------------------------------------ Hartree
+// tmp(k) = rho(k) 4 pi / G^2 / N (G != 0), for the complex-to-real transform
+__global__ void hartree_spectrum_kernel(const double2* __restrict__ rhok, int nx, int ny, int nz,
+                                        double Lx, double Ly, double Lz, double inv_n,
+                                        double2* __restrict__ out) {
+    const int nh = nx / 2 + 1;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nh * ny * nz) return;
+    const int ix = (int)(t % nh);
+    const int iy = (int)((t / nh) % ny);
+    const int iz = (int)(t / ((int64_t)nh * ny));
+    const double gx = 2.0 * M_PI * wavenum(ix, nx) / Lx;
+    const double gy = 2.0 * M_PI * wavenum(iy, ny) / Ly;
+    const double gz = 2.0 * M_PI * wavenum(iz, nz) / Lz;
+    const double g2 = gx * gx + gy * gy + gz * gz;
+    double2 r = make_double2(0.0, 0.0);
+    if (g2 > 0.0) {
+        const double k = 4.0 * M_PI / g2 * inv_n;
+        r = make_double2(rhok[t].x * k, rhok[t].y * k);
+    }
+    out[t] = r;
+}
+
+// v_Hxc = V_H + v_x, v_x = -(3 rho/pi)^(1/3); optional energy partials
+// part[b] = (sum rho V_H, sum e_x(rho), sum rho) per 256-point block
+__global__ void __launch_bounds__(256) vhxc_kernel(const double* __restrict__ rho,
+                                                   const double* __restrict__ vh, int64_t N,
+                                                   double* __restrict__ vhxc,
+                                                   double* __restrict__ part) {
+    __shared__ double sh[4];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double eh = 0.0, ex = 0.0, q = 0.0;
+    if (i < N) {
+        const double r = rho[i];
+        q = r;
+        const double vx = -cbrt(3.0 * r / M_PI);
+        vhxc[i] = vh[i] + vx;
+        eh = r * vh[i];
+        ex = -(0.75 * cbrt(3.0 / M_PI)) * cbrt(r) * r;
+    }
+    if (part != nullptr) {
+        const double a = block_sum256(eh, sh);
+        const double b = block_sum256(ex, sh);
+        const double c = block_sum256(q, sh);
+        if (threadIdx.x == 0) {
+            part[3 * blockIdx.x] = a;
+            part[3 * blockIdx.x + 1] = b;
+            part[3 * blockIdx.x + 2] = c;
+        }
+    }
+}
+
+// ------------------------------------------------------------ v_eff
+template <typename T>
+__global__ void veff_kernel(const double* __restrict__ vloc0, const double* __restrict__ vloc1,
+                            const double* __restrict__ hn, const double* __restrict__ hn1,
+                            const double* __restrict__ hn2, int nhist, int nx, int64_t N,
+                            double h, double Lx, double eps, T* __restrict__ veff0,
+                            T* __restrict__ veff1) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double a = hn[i];
+    double ext = 0.0;
+    if (eps != 0.0) ext = eps * (h * (double)(i % nx) - 0.5 * Lx);
+    double v0 = vloc0[i] + a;
+    double vt;
+    if (nhist >= 3) vt = (3.0 * a - 3.0 * hn1[i]) + hn2[i];
+    else if (nhist == 2) vt = 2.0 * a - hn1[i];
+    else vt = a;
+    double v1 = vloc1[i] + vt;
+    if (eps != 0.0) { v0 += ext; v1 += ext; }
+    veff0[i] = (T)v0;
+    if (veff1 != nullptr) veff1[i] = (T)v1;
+}
+
+// ------------------------------------------------------------ local forces
+// F_J = (1/Omega) Re sum_{G in box} conj(rho(G)) (i G) v(G) Z_J exp(-i G.R_J),
+// rho(G) = h^3 fft(rho).  Thread per full-box G; 8 ions per block column.
+// part[((J*nchunk) + chunk)*3 + c]
+__global__ void __launch_bounds__(256) local_force_kernel(const double2* __restrict__ rhok,
+                                                          const double2* __restrict__ ph,
+                                                          const double* __restrict__ zval,
+                                                          int n_ions, int nx, int ny, int nz,
+                                                          double Lx, double Ly, double Lz,
+                                                          double a, double scale, int per_thread,
+                                                          double* __restrict__ part) {
+    __shared__ double sh[4];
+    const int nh = nx / 2 + 1;
+    const int nt = nx + ny + nz;
+    const int64_t N = (int64_t)nx * ny * nz;
+    const int J0 = blockIdx.y * 8;
+    const int nj = min(8, n_ions - J0);
+    double acc[8][3];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
+    const int64_t base = ((int64_t)blockIdx.x * blockDim.x) * per_thread + threadIdx.x;
+    for (int r = 0; r < per_thread; ++r) {
+        const int64_t t = base + (int64_t)r * blockDim.x;
+        if (t >= N) break;
+        const int ix = (int)(t % nx);
+        const int iy = (int)((t / nx) % ny);
+        const int iz = (int)(t / ((int64_t)nx * ny));
+        const double gx = 2.0 * M_PI * wavenum(ix, nx) / Lx;
+        const double gy = 2.0 * M_PI * wavenum(iy, ny) / Ly;
+        const double gz = 2.0 * M_PI * wavenum(iz, nz) / Lz;
+        const double g2 = gx * gx + gy * gy + gz * gz;
+        if (g2 == 0.0) continue;
+        double2 rk;
+        if (ix < nh) {
+            rk = rhok[((int64_t)iz * ny + iy) * nh + ix];
+        } else {
+            const int mx = nx - ix, my = (ny - iy) % ny, mz = (nz - iz) % nz;
+            const double2 q = rhok[((int64_t)mz * ny + my) * nh + mx];
+            rk = make_double2(q.x, -q.y);
+        }
+        const double f = vloc_ff(g2, a) * scale;          // scale = h^3 / Omega
+        const double2 w = make_double2(f * rk.x, -f * rk.y);   // conj(rho) v
+        for (int j = 0; j < nj; ++j) {
+            const double2* pj = ph + (int64_t)(J0 + j) * nt;
+            const double2 e = cmul(cmul(pj[ix], pj[nx + iy]), pj[nx + ny + iz]);
+            const double2 tt = cmul(w, e);
+            const double im = zval[J0 + j] * tt.y;         // Re(i G t) = -G Im(t)
+            acc[j][0] -= gx * im;
+            acc[j][1] -= gy * im;
+            acc[j][2] -= gz * im;
+        }
+    }
+    for (int j = 0; j < 8; ++j)
+        for (int c = 0; c < 3; ++c) {
+            const double s = block_sum256(acc[j][c], sh);
+            if (threadIdx.x == 0 && j < nj)
+                part[((int64_t)(J0 + j) * gridDim.x + blockIdx.x) * 3 + c] = s;
+        }
+}
+
+// ------------------------------------------------------------ Ewald
+// S(G) = sum_K Z_K exp(i G.R_K) for the Ewald reciprocal vectors
+__global__ void ewald_sg_kernel(const double* __restrict__ gv, const double* __restrict__ wv, int ng,
+                                const double* __restrict__ pos, const double* __restrict__ zval,
+                                int n_ions, double2* __restrict__ sg, double* __restrict__ epart) {
+    __shared__ double sh[4];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    double e = 0.0;
+    if (t < ng) {
+        double sr = 0.0, si = 0.0;
+        for (int K = 0; K < n_ions; ++K) {
+            const double ph = gv[3 * t] * pos[3 * K] + gv[3 * t + 1] * pos[3 * K + 1] +
+                              gv[3 * t + 2] * pos[3 * K + 2];
+            double sn, cs;
+            sincos(ph, &sn, &cs);
+            sr += zval[K] * cs;
+            si += zval[K] * sn;
+        }
+        sg[t] = make_double2(sr, si);
+        e = wv[t] * (sr * sr + si * si);
+    }
+    const double s = block_sum256(e, sh);
+    if (threadIdx.x == 0) epart[blockIdx.x] = s;
+}
+
+// one block per ion: real-space pair/image sum and reciprocal force
+__global__ void __launch_bounds__(256) ewald_ion_kernel(const double* __restrict__ pos,
+                                                        const double* __restrict__ zval, int n_ions,
+                                                        double L, int nmax, double eta, double rc,
+                                                        const double* __restrict__ gv,
+                                                        const double* __restrict__ wv,
+                                                        const double2* __restrict__ sg, int ng,
+                                                        double four_pi_over_omega,
+                                                        double* __restrict__ f,
+                                                        double* __restrict__ epart) {
+    __shared__ double sh[4];
+    const int J = blockIdx.x;
+    const int side = 2 * nmax + 1;
+    const int nimg = side * side * side;
+    const double rj[3] = {pos[3 * J], pos[3 * J + 1], pos[3 * J + 2]};
+    double e = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+    const double two_eta_pi = 2.0 * eta / sqrt(M_PI);
+    for (int64_t t = threadIdx.x; t < (int64_t)n_ions * nimg; t += blockDim.x) {
+        const int K = (int)(t / nimg);
+        const int im = (int)(t % nimg);
+        const int ii = im % side - nmax, jj = (im / side) % side - nmax, kk = im / (side * side) - nmax;
+        const double dx = rj[0] - pos[3 * K] + ii * L;
+        const double dy = rj[1] - pos[3 * K + 1] + jj * L;
+        const double dz = rj[2] - pos[3 * K + 2] + kk * L;
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        if (r > 1e-12 && r < rc) {
+            const double zz = zval[J] * zval[K];
+            const double ec = erfc(eta * r) / r;
+            e += 0.5 * zz * ec;
+            const double g = (ec / r + two_eta_pi * exp(-(eta * r) * (eta * r)) / r) / r;
+            fx += zz * g * dx;
+            fy += zz * g * dy;
+            fz += zz * g * dz;
+        }
+    }
+    // reciprocal: F_J = (4 pi Z_J / Omega) sum_G w(G) G Im(exp(i G.R_J) conj(S(G)))
+    for (int t = threadIdx.x; t < ng; t += blockDim.x) {
+        const double ph = gv[3 * t] * rj[0] + gv[3 * t + 1] * rj[1] + gv[3 * t + 2] * rj[2];
+        double sn, cs;
+        sincos(ph, &sn, &cs);
+        const double2 s = sg[t];
+        const double im = sn * s.x - cs * s.y;     // Im(e^{i ph} conj(S))
+        const double c = four_pi_over_omega * zval[J] * wv[t] * im;
+        fx += c * gv[3 * t];
+        fy += c * gv[3 * t + 1];
+        fz += c * gv[3 * t + 2];
+    }
+    const double se = block_sum256(e, sh);
+    const double sx = block_sum256(fx, sh);
+    const double sy = block_sum256(fy, sh);
+    const double sz = block_sum256(fz, sh);
+    if (threadIdx.x == 0) {
+        f[3 * J] = sx;
+        f[3 * J + 1] = sy;
+        f[3 * J + 2] = sz;
+        epart[J] = se;
+    }
+}
+
+// ------------------------------------------------------------ ions
+__global__ void ions_predict_kernel(const double* __restrict__ pos, const double* __restrict__ vel,
+                                    const double* __restrict__ frc, const double* __restrict__ mass,
+                                    int n_ions, double dt, int frozen, double* __restrict__ pos1) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * n_ions) return;
+    if (frozen) { pos1[t] = pos[t]; return; }
+    pos1[t] = (pos[t] + vel[t] * dt) + frc[t] * (dt * dt) / (2.0 * mass[t / 3]);
+}
+
+// total force F = F_loc + F_NL + F_ion; velocities; the new state becomes current
+__global__ void ions_finish_kernel(double* __restrict__ pos, double* __restrict__ vel,
+                                   double* __restrict__ frc, const double* __restrict__ pos1,
+                                   const double* __restrict__ floc_part, int nchunk,
+                                   const double* __restrict__ fnl, const double* __restrict__ fion,
+                                   const double* __restrict__ mass, int n_ions, double dt,
+                                   int frozen) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * n_ions) return;
+    const int J = t / 3, c = t % 3;
+    double fl = 0.0;
+    for (int k = 0; k < nchunk; ++k) fl += floc_part[((int64_t)J * nchunk + k) * 3 + c];
+    const double f1 = (fl + fnl[t]) + fion[t];
+    if (!frozen) vel[t] = vel[t] + (frc[t] + f1) * dt / (2.0 * mass[J]);
+    pos[t] = pos1[t];
+    frc[t] = f1;
+}
+
+// ------------------------------------------------------------ misc
+__global__ void add_inplace_kernel(double* __restrict__ a, const double* __restrict__ b, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] += b[i];
+}
+
+__global__ void scale_copy_kernel(double* __restrict__ dst, const double* __restrict__ src,
+                                  double s, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = s * src[i];
+}
+
+__global__ void __launch_bounds__(256) dot_partial_kernel(const double* __restrict__ a,
+                                                          const double* __restrict__ b, int64_t n,
+                                                          double* __restrict__ part) {
+    __shared__ double sh[4];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double v = i < n ? a[i] * b[i] : 0.0;
+    const double s = block_sum256(v, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Collect the step's diagnostics into rep[] (one block of 256 threads).
+// Layout of rep: see ReportSlot.
+__global__ void __launch_bounds__(256) report_kernel(FinalizeArgs a) {
+    __shared__ double sh[4];
+    const int tid = threadIdx.x;
+    // norms: per orbital h^3 * sum of tile partials, max |n-1| and finiteness
+    double worst = 0.0;
+    int bad = 0;
+    if (a.norm_part != nullptr) {
+        for (int A = tid; A < a.n_orb; A += 256) {
+            double s = 0.0;
+            for (int k = 0; k < a.norm_tiles; ++k) s += a.norm_part[(int64_t)A * a.norm_tiles + k];
+            s *= a.dv;
+            if (!isfinite(s)) bad = 1;
+            const double dev = fabs(s - 1.0);
+            worst = fmax(worst, dev);
+            if (s > 1.0 + a.norm_tol) bad = 1;
+        }
+    }
+    // wave/block max via shared memory
+    __shared__ double mx[256];
+    __shared__ int bd[256];
+    mx[tid] = worst;
+    bd[tid] = bad;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) {
+            mx[tid] = fmax(mx[tid], mx[tid + o]);
+            bd[tid] |= bd[tid + o];
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && a.norm_part != nullptr) {
+        a.rep[SLOT_NORM_DEV] = mx[0];
+        if (bd[0]) a.rep[SLOT_UNSTABLE] = 1.0;
+    }
+    __syncthreads();
+    if (!a.energy) return;
+    // sequential partial sums in fixed order
+    double ek = 0.0, eh = 0.0, ex = 0.0, el = 0.0, en = 0.0, ei = 0.0, er = 0.0, q = 0.0;
+    for (int64_t k = tid; k < a.kin_n; k += 256) ek += a.kin_part[k];
+    for (int64_t k = tid; k < a.hxc_n; k += 256) {
+        eh += a.hxc_part[3 * k];
+        ex += a.hxc_part[3 * k + 1];
+        q += a.hxc_part[3 * k + 2];
+    }
+    for (int64_t k = tid; k < a.loc_n; k += 256) el += a.loc_part[k];
+    for (int k = tid; k < a.n_ions; k += 256) { en += a.enl_part[k]; ei += a.eion_part[k]; }
+    for (int k = tid; k < a.erec_n; k += 256) er += a.erec_part[k];
+    ek = block_sum256(ek, sh); eh = block_sum256(eh, sh); ex = block_sum256(ex, sh);
+    el = block_sum256(el, sh); en = block_sum256(en, sh); ei = block_sum256(ei, sh);
+    er = block_sum256(er, sh); q = block_sum256(q, sh);
+    double ke = 0.0, fmx = 0.0;
+    if (tid == 0) {
+        for (int J = 0; J < a.n_ions; ++J) {
+            const double* v = a.vel + 3 * J;
+            ke += 0.5 * a.mass[J] * ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+            const double* f = a.frc + 3 * J;
+            fmx = fmax(fmx, sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]));
+        }
+        double* r = a.rep;
+        r[SLOT_EKIN] = a.occ * a.dv * ek;
+        r[SLOT_ELOC] = a.dv * el;
+        r[SLOT_EH] = 0.5 * a.dv * eh;
+        r[SLOT_EX] = a.dv * ex;
+        r[SLOT_ENL] = en;
+        r[SLOT_EION] = ei + a.ewald_rec_scale * er + a.ewald_const;
+        r[SLOT_EKS] = ((((r[SLOT_EKIN] + r[SLOT_ELOC]) + r[SLOT_EH]) + r[SLOT_EX]) + r[SLOT_ENL]) +
+                      r[SLOT_EION];
+        r[SLOT_EIONKIN] = ke;
+        r[SLOT_ETOT] = r[SLOT_EKS] + ke;
+        r[SLOT_FMAX] = fmx;
+        r[SLOT_CHARGE] = a.dv * q;
+    }
+}
+
+// ------------------------------------------------------------ launchers
+static inline unsigned nb(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_phases(const double* pos, int n_ions, int nx, int ny, int nz, const double L[3],
+                         double2* ph, hipStream_t s) {
+    if (n_ions == 0) return hipSuccess;
+    const int64_t n = (int64_t)n_ions * (nx + ny + nz);
+    phase_kernel<<<nb(n), 256, 0, s>>>(pos, n_ions, nx, ny, nz, L[0], L[1], L[2], ph);
+    return hipGetLastError();
+}
+
+hipError_t launch_vloc_spectrum(const double2* ph, const double* zval, int n_ions, int nx, int ny,
+                                int nz, const double L[3], double a, double2* out, hipStream_t s) {
+    const int64_t n = (int64_t)(nx / 2 + 1) * ny * nz;
+    vloc_spectrum_kernel<<<nb(n), 256, 0, s>>>(ph, zval, n_ions, nx, ny, nz, L[0], L[1], L[2], a,
+                                               1.0 / (L[0] * L[1] * L[2]), out);
+    return hipGetLastError();
+}
+
+hipError_t launch_hartree_spectrum(const double2* rhok, int nx, int ny, int nz, const double L[3],
+                                   double2* out, hipStream_t s) {
+    const int64_t n = (int64_t)(nx / 2 + 1) * ny * nz;
+    hartree_spectrum_kernel<<<nb(n), 256, 0, s>>>(rhok, nx, ny, nz, L[0], L[1], L[2],
+                                                  1.0 / ((double)nx * ny * nz), out);
+    return hipGetLastError();
+}
+
+hipError_t launch_vhxc(const double* rho, const double* vh, int64_t N, double* vhxc, double* part,
+                       hipStream_t s) {
+    vhxc_kernel<<<nb(N), 256, 0, s>>>(rho, vh, N, vhxc, part);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_veff(const double* vloc0, const double* vloc1, const double* hn, const double* hn1,
+                       const double* hn2, int nhist, int nx, int64_t N, double h, double Lx,
+                       double eps, T* veff0, T* veff1, hipStream_t s) {
+    veff_kernel<T><<<nb(N), 256, 0, s>>>(vloc0, vloc1, hn, hn1, hn2, nhist, nx, N, h, Lx, eps,
+                                         veff0, veff1);
+    return hipGetLastError();
+}
+template hipError_t launch_veff<double>(const double*, const double*, const double*, const double*, const double*, int, int, int64_t, double, double, double, double*, double*, hipStream_t);
+template hipError_t launch_veff<float>(const double*, const double*, const double*, const double*, const double*, int, int, int64_t, double, double, double, float*, float*, hipStream_t);
+
+int local_force_chunks(int64_t N) {
+    const int64_t per_block = 256 * 16;
+    return (int)((N + per_block - 1) / per_block);
+}
+
+hipError_t launch_local_forces(const double2* rhok, const double2* ph, const double* zval,
+                               int n_ions, int nx, int ny, int nz, const double L[3], double h,
+                               double a, double* part, hipStream_t s) {
+    if (n_ions == 0) return hipSuccess;
+    const int64_t N = (int64_t)nx * ny * nz;
+    dim3 grid(local_force_chunks(N), (n_ions + 7) / 8);
+    const double scale = h * h * h / (L[0] * L[1] * L[2]);
+    local_force_kernel<<<grid, 256, 0, s>>>(rhok, ph, zval, n_ions, nx, ny, nz, L[0], L[1], L[2], a,
+                                            scale, 16, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_ewald(const EwaldPlan& e, const double* pos, const double* zval, int n_ions,
+                        double2* sg, double* erec_part, double* f, double* epart, hipStream_t s) {
+    if (n_ions == 0) return hipSuccess;
+    ewald_sg_kernel<<<nb(e.ng), 256, 0, s>>>(e.gv, e.wv, e.ng, pos, zval, n_ions, sg, erec_part);
+    ewald_ion_kernel<<<n_ions, 256, 0, s>>>(pos, zval, n_ions, e.L, e.nmax, e.eta, e.rc, e.gv, e.wv,
+                                            sg, e.ng, 4.0 * M_PI / (e.L * e.L * e.L), f, epart);
+    return hipGetLastError();
+}
+
+hipError_t launch_ions_predict(const double* pos, const double* vel, const double* frc,
+                               const double* mass, int n_ions, double dt, int frozen, double* pos1,
+                               hipStream_t s) {
+    if (n_ions == 0) return hipSuccess;
+    ions_predict_kernel<<<nb(3 * n_ions), 256, 0, s>>>(pos, vel, frc, mass, n_ions, dt, frozen, pos1);
+    return hipGetLastError();
+}
+
+hipError_t launch_ions_finish(double* pos, double* vel, double* frc, const double* pos1,
+                              const double* floc_part, int nchunk, const double* fnl,
+                              const double* fion, const double* mass, int n_ions, double dt,
+                              int frozen, hipStream_t s) {
+    if (n_ions == 0) return hipSuccess;
+    ions_finish_kernel<<<nb(3 * n_ions), 256, 0, s>>>(pos, vel, frc, pos1, floc_part, nchunk, fnl,
+                                                      fion, mass, n_ions, dt, frozen);
+    return hipGetLastError();
+}
+
+hipError_t launch_add(double* a, const double* b, int64_t n, hipStream_t s) {
+    add_inplace_kernel<<<nb(n), 256, 0, s>>>(a, b, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_copy(double* dst, const double* src, double sc, int64_t n, hipStream_t s) {
+    scale_copy_kernel<<<nb(n), 256, 0, s>>>(dst, src, sc, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot_partial(const double* a, const double* b, int64_t n, double* part,
+                              hipStream_t s) {
+    dot_partial_kernel<<<nb(n), 256, 0, s>>>(a, b, n, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_report(const FinalizeArgs& a, hipStream_t s) {
+    report_kernel<<<1, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace me

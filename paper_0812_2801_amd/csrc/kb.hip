@@ -1,0 +1,255 @@
+// Gaussian s-channel Kleinman-Bylander projector: per-ion point tables,
+// the contraction c_JA = h^3 sum_k p_J(r_k) psi_A(r_k) and the nonlocal
+// forces / energy.  The scatter E_KB sum_J p_J c_JA is fused into the
+// stencil kernel.
+#include "common.hpp"
+#include "geometry.hpp"
+
+namespace me {
+
+// ------------------------------------------------------------ tables
+// One workgroup per ion.  Candidates: per axis the 2m+2 points
+// floor(R/h)-m .. floor(R/h)+m+1 (all n points when 2m+2 >= n), enumerated
+// with x fastest; those strictly inside the cutoff are compacted in
+// candidate order with a ballot prefix sum, so the table is deterministic.
+template <typename T>
+__global__ void __launch_bounds__(256) kb_tables_kernel(const double* __restrict__ pos,
+                                                        int nx, int ny, int nz, KbGeom g, int m,
+                                                        int32_t* __restrict__ idx, T* __restrict__ pv,
+                                                        T* __restrict__ pbox, int32_t* __restrict__ bstart,
+                                                        int32_t* __restrict__ count, int kcap) {
+    __shared__ int wsum[4];
+    __shared__ int base_off;
+    const int J = blockIdx.x;
+    const double rx = pos[3 * J], ry = pos[3 * J + 1], rz = pos[3 * J + 2];
+    const int n3[3] = {nx, ny, nz};
+    const double r3[3] = {rx, ry, rz};
+    int side[3], start[3];
+    for (int a = 0; a < 3; ++a) {
+        side[a] = 2 * m + 2;
+        if (side[a] >= n3[a]) {
+            side[a] = n3[a];
+            start[a] = 0;
+        } else {
+            const double w = r3[a] - g.L[a] * floor(r3[a] / g.L[a]);  // into [0, L)
+            start[a] = (int)floor(w / g.h) - m;
+        }
+    }
+    const int total = min(side[0] * side[1] * side[2], kcap);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (tid < 3) {
+        int s0 = start[tid] % n3[tid];
+        if (s0 < 0) s0 += n3[tid];
+        bstart[3 * J + tid] = s0;
+    }
+    if (tid == 0) base_off = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < total; c0 += 256) {
+        const int c = c0 + tid;
+        bool inside = false;
+        int lin = 0;
+        double d2 = 0.0;
+        if (c < total) {
+            const int ox = c % side[0];
+            const int oy = (c / side[0]) % side[1];
+            const int oz = c / (side[0] * side[1]);
+            int gx = (start[0] + ox) % nx; if (gx < 0) gx += nx;
+            int gy = (start[1] + oy) % ny; if (gy < 0) gy += ny;
+            int gz = (start[2] + oz) % nz; if (gz < 0) gz += nz;
+            double dx, dy, dz;
+            d2 = kb_d2(g, gx, gy, gz, rx, ry, rz, dx, dy, dz);
+            inside = d2 < g.rcut2;
+            lin = (gz * ny + gy) * nx + gx;
+            pbox[(int64_t)J * kcap + c] = inside ? (T)kb_value(g, d2) : (T)0;
+        }
+        const unsigned long long bal = __ballot(inside);
+        const int before = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) wsum[wv] = __popcll(bal);
+        __syncthreads();
+        int off = base_off;
+        for (int i = 0; i < wv; ++i) off += wsum[i];
+        if (inside) {
+            const int k = off + before;
+            if (k < kcap) {
+                idx[(int64_t)J * kcap + k] = lin;
+                pv[(int64_t)J * kcap + k] = (T)kb_value(g, d2);
+            }
+        }
+        __syncthreads();
+        if (tid == 0) base_off += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        __syncthreads();
+    }
+    if (tid == 0) count[J] = base_off < kcap ? base_off : kcap;
+}
+
+// Ions whose sphere reaches the rows [y0, y0+TY) of plane z (any x): bit J of
+// mask[(z*nyt + ytile)*words + J/32].  Conservative by a small slack; the
+// stencil re-checks each point exactly.
+__global__ void kb_mask_kernel(const double* __restrict__ pos, int n_ions, int ny, int nz,
+                               int ty, int nyt, int words, KbGeom g, uint32_t* __restrict__ mask) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)nz * nyt * n_ions;
+    if (t >= total) return;
+    const int J = (int)(t % n_ions);
+    const int64_t row = t / n_ions;              // z*nyt + ytile
+    const int ytile = (int)(row % nyt);
+    const int z = (int)(row / nyt);
+    const double dz = min_image(g.h * (double)z - pos[3 * J + 2], g.L[2]);
+    const double dz2 = dz * dz;
+    if (dz2 >= g.rcut2 + 1e-9) return;
+    double dymin2 = 1e300;
+    for (int k = 0; k < ty; ++k) {
+        const double dy = min_image(g.h * (double)(ytile * ty + k) - pos[3 * J + 1], g.L[1]);
+        dymin2 = fmin(dymin2, dy * dy);
+    }
+    if (dz2 + dymin2 < g.rcut2 + 1e-9)
+        atomicOr(&mask[row * words + (J >> 5)], 1u << (J & 31));
+}
+
+__global__ void zero_u32_kernel(uint32_t* __restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+template <typename T>
+hipError_t launch_kb_tables(const double* pos, int n_ions, int nx, int ny, int nz,
+                            const KbGeom& g, KbTables t, hipStream_t s) {
+    if (n_ions == 0) return hipSuccess;
+    kb_tables_kernel<T><<<n_ions, 256, 0, s>>>(pos, nx, ny, nz, g, t.m, t.idx,
+                                               reinterpret_cast<T*>(t.p), reinterpret_cast<T*>(t.pbox),
+                                               t.start, t.count, t.kcap);
+    const int nyt = ny / t.ty;
+    const int64_t mw = (int64_t)nz * nyt * t.words;
+    zero_u32_kernel<<<(unsigned)((mw + 255) / 256), 256, 0, s>>>(t.mask, mw);
+    const int64_t total = (int64_t)nz * nyt * n_ions;
+    kb_mask_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(pos, n_ions, ny, nz, t.ty, nyt,
+                                                                   t.words, g, t.mask);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ contraction
+template <typename T>
+__device__ __forceinline__ T wsum_t(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// one wave per (ion, orbital); four orbitals of one ion per workgroup
+template <typename T>
+__global__ void __launch_bounds__(256) kb_gather_kernel(const cx_t<T>* __restrict__ u, int64_t stride,
+                                                        int n_orb, const int32_t* __restrict__ idx,
+                                                        const T* __restrict__ pv,
+                                                        const int32_t* __restrict__ count, int kcap,
+                                                        T scale, cx_t<T>* __restrict__ cnl) {
+    const int J = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int A = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (A >= n_orb) return;
+    const int K = count[J];
+    const int32_t* ix = idx + (int64_t)J * kcap;
+    const T* pp = pv + (int64_t)J * kcap;
+    const cx_t<T>* ua = u + (int64_t)A * stride;
+    T re = 0, im = 0;
+    for (int k = lane; k < K; k += 64) {
+        const cx_t<T> z = ua[ix[k]];
+        const T w = pp[k];
+        re += w * z.x;
+        im += w * z.y;
+    }
+    re = wsum_t(re);
+    im = wsum_t(im);
+    if (lane == 0) cnl[(int64_t)J * n_orb + A] = cx_t<T>{scale * re, scale * im};
+}
+
+template <typename T>
+hipError_t launch_kb_gather(const cx_t<T>* u, int64_t stride, int n_orb, int n_ions,
+                            KbTables t, double ekb_h3, cx_t<T>* cnl, hipStream_t s) {
+    if (n_ions == 0) return hipSuccess;
+    dim3 grid((n_orb + 3) / 4, n_ions);
+    kb_gather_kernel<T><<<grid, 256, 0, s>>>(u, stride, n_orb, t.idx, reinterpret_cast<const T*>(t.p),
+                                             t.count, t.kcap, (T)ekb_h3, cnl);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ forces
+// One workgroup per ion; each wave takes every fourth orbital.  Everything
+// is accumulated in FP64: c = sum p psi, d = sum (r-R)/s^2 p psi (per axis),
+// F_J = -2 f E_KB h^6 sum_A Re(conj(c) d), E_J = f E_KB h^6 sum_A |c|^2.
+template <typename T>
+__global__ void __launch_bounds__(256) kb_forces_kernel(const cx_t<T>* __restrict__ psi, int64_t stride,
+                                                        int n_orb, const int32_t* __restrict__ idx,
+                                                        const int32_t* __restrict__ count, int kcap,
+                                                        const double* __restrict__ pos, KbGeom g,
+                                                        int nx, int ny, double occ, double ekb,
+                                                        double* __restrict__ fnl,
+                                                        double* __restrict__ enl_part) {
+    __shared__ double red[4][4];
+    const int J = blockIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int K = count[J];
+    const int32_t* ix = idx + (int64_t)J * kcap;
+    const double rx = pos[3 * J], ry = pos[3 * J + 1], rz = pos[3 * J + 2];
+    double fx = 0, fy = 0, fz = 0, en = 0;
+    for (int A = wv; A < n_orb; A += 4) {
+        const cx_t<T>* pa = psi + (int64_t)A * stride;
+        double cr = 0, ci = 0, xr = 0, xi = 0, yr = 0, yi = 0, zr = 0, zi = 0;
+        for (int k = lane; k < K; k += 64) {
+            const int lin = ix[k];
+            const int gx = lin % nx;
+            const int gy = (lin / nx) % ny;
+            const int gz = lin / (nx * ny);
+            double dx, dy, dz;
+            const double d2 = kb_d2(g, gx, gy, gz, rx, ry, rz, dx, dy, dz);
+            const double w = kb_value(g, d2);
+            const cx_t<T> zv = pa[lin];
+            const double pr = w * (double)zv.x, pi = w * (double)zv.y;
+            cr += pr; ci += pi;
+            xr += dx * pr; xi += dx * pi;
+            yr += dy * pr; yi += dy * pi;
+            zr += dz * pr; zi += dz * pi;
+        }
+        cr = wsum_t(cr); ci = wsum_t(ci);
+        xr = wsum_t(xr); xi = wsum_t(xi);
+        yr = wsum_t(yr); yi = wsum_t(yi);
+        zr = wsum_t(zr); zi = wsum_t(zi);
+        fx += cr * xr + ci * xi;
+        fy += cr * yr + ci * yi;
+        fz += cr * zr + ci * zi;
+        en += cr * cr + ci * ci;
+    }
+    if (lane == 0) {
+        red[wv][0] = fx; red[wv][1] = fy; red[wv][2] = fz; red[wv][3] = en;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double h6 = g.h * g.h * g.h * g.h * g.h * g.h;
+        double s[4];
+        for (int c = 0; c < 4; ++c) s[c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+        const double kf = -2.0 * occ * ekb * h6 * g.inv_s2;
+        fnl[3 * J] = kf * s[0];
+        fnl[3 * J + 1] = kf * s[1];
+        fnl[3 * J + 2] = kf * s[2];
+        enl_part[J] = occ * ekb * h6 * s[3];
+    }
+}
+
+template <typename T>
+hipError_t launch_kb_forces(const cx_t<T>* psi, int64_t stride, int n_orb, int n_ions,
+                            KbTables t, const double* pos, const KbGeom& g,
+                            int nx, int ny, double occ, double ekb,
+                            double* fnl, double* enl_part, hipStream_t s) {
+    if (n_ions == 0) return hipSuccess;
+    kb_forces_kernel<T><<<n_ions, 256, 0, s>>>(psi, stride, n_orb, t.idx, t.count, t.kcap, pos, g,
+                                               nx, ny, occ, ekb, fnl, enl_part);
+    return hipGetLastError();
+}
+
+template hipError_t launch_kb_tables<double>(const double*, int, int, int, int, const KbGeom&, KbTables, hipStream_t);
+template hipError_t launch_kb_tables<float>(const double*, int, int, int, int, const KbGeom&, KbTables, hipStream_t);
+template hipError_t launch_kb_gather<double>(const cx_t<double>*, int64_t, int, int, KbTables, double, cx_t<double>*, hipStream_t);
+template hipError_t launch_kb_gather<float>(const cx_t<float>*, int64_t, int, int, KbTables, double, cx_t<float>*, hipStream_t);
+template hipError_t launch_kb_forces<double>(const cx_t<double>*, int64_t, int, int, KbTables, const double*, const KbGeom&, int, int, double, double, double*, double*, hipStream_t);
+template hipError_t launch_kb_forces<float>(const cx_t<float>*, int64_t, int, int, KbTables, const double*, const KbGeom&, int, int, double, double, double*, double*, hipStream_t);
+
+}  // namespace me
