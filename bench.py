@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Benchmark of the modified-Ehrenfest MD step on one MI355X.
+
+Workload (default): the single-system configuration -- periodic 96^3 grid,
+h = 0.25 bohr, 64 Z=4 ions placed uniformly with minimum separation 2.5 bohr,
+128 complex orbitals (seeded random smoothed fields, Loewdin-orthonormalised),
+mu = 4, dt = 0.08 au, AETRS with fourth-order Taylor exponentials.  One
+"step" is one full MD step: ion update, V_loc and projector tables at the new
+positions, both exponentials (8 H psi per orbital), density, Hartree +
+exchange, local / nonlocal / Ewald forces and velocities.
+
+The headline value is the FP32 run's orbital*gridpoint*H psi per second over
+the whole step (N_orb * N * 8 per step); the same workload in FP64 is timed
+beside it and the speed-up reported, together with each precision's
+one-step error against the FP64 CPU oracle on sampled orbitals.
+
+Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "orbital·gridpts Hψ/s + ms/MD step, FP32/batched vs FP64 GPU at stated error"
+STENCIL_SRC = os.path.join(ROOT, "paper_0812_2801_amd", "csrc", "stencil.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stencil_traffic_c2.json")
+
+
+def stencil_hash() -> str:
+    with open(STENCIL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def run_precision(cfg, inp, prec, steps, warmup, sample):
+    import numpy as np
+    import torch
+    from paper_0812_2801_amd import binding as B
+    p, keep = B.params_from_config(cfg, inp["pos"], precision=prec)
+    s = B.System(p, keep, device="cuda:0")
+    psi0 = torch.from_numpy(inp["psi"].reshape(cfg.n_orb, -1))
+    s.set_state(psi0)
+    del psi0
+    e_start = s.report()["e_total"]
+    # one step from the initial state: the sampled orbitals for the error check
+    s.step()
+    got = s.get_state()[list(sample)].cpu().numpy()
+    for _ in range(warmup):
+        s.step()
+    s.sync()
+    s.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s.sync()                      # raises if an orbital norm became unstable
+    launches, kms, kbytes = s.timing_read()
+    s.timing_enable(False)
+    rep = s.report()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    ms = (t1 - t0) * 1e3 / steps
+    return {"ms_per_step": ms, "launches": launches, "kernel_ms": kms, "kernel_bytes": kbytes,
+            "psi_sample": got, "report": rep, "energy_drift": rep["e_total"] - e_start,
+            "steps_total": 1 + warmup + steps}
+
+
+def oracle_sample(cfg, inp, sample):
+    """FP64 oracle: one AETRS propagation of the sampled orbitals (both
+    exponentials) from the initial state, single-threaded; timed."""
+    import contextlib
+    from oracle import Model, dynamics
+    try:
+        from threadpoolctl import threadpool_limits
+        ctx = threadpool_limits(1)
+    except Exception:
+        ctx = contextlib.nullcontext()
+    with ctx:
+        m = Model.from_config(cfg)
+        st = dynamics.init_state(m, inp["psi"], inp["pos"])
+        pos1, h0, h1 = dynamics.step_hamiltonians(m, st)
+        psi = inp["psi"][list(sample)]
+        t0 = time.perf_counter()
+        out = dynamics.propagate_orbitals(m, psi, h0, h1)
+        t1 = time.perf_counter()
+    return out, t1 - t0
+
+
+def traffic_entry():
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except Exception:
+        return None
+    if d.get("stencil_sha256_16") != stencil_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def calibrate_copy(gib: float = 2.0, reps: int = 5):
+    """A plain device copy of known size, for scaling HBM counters."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each": 2 * n * 4, "reps": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--sample", type=int, default=4, help="orbitals in the oracle sample")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--precision", default="f32", choices=["f32", "f32_bf16x3", "f64"])
+    ap.add_argument("--calibrate-copy", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+
+    import numpy as np
+    import torch
+    import workloads as W
+    cfg = W.C2
+    t_gen = time.perf_counter()
+    inp = W.make_inputs(cfg)
+    t_gen = time.perf_counter() - t_gen
+    print(f"# inputs generated in {t_gen:.1f} s", file=sys.stderr, flush=True)
+    sample = list(range(min(args.sample, cfg.n_orb)))
+    work = cfg.n_orb * cfg.n_points * 8          # orbital*gridpoint*H psi per step
+
+    main_run = run_precision(cfg, inp, args.precision, args.steps, args.warmup, sample)
+    print(f"# {args.precision}: {main_run['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    f64_run = None
+    if not args.no_fp64 and args.precision != "f64":
+        f64_run = run_precision(cfg, inp, "f64", max(10, args.steps // 4), args.warmup, sample)
+        print(f"# f64: {f64_run['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+
+    cpu = None
+    errors = {}
+    if not args.no_cpu:
+        ref, t_cpu = oracle_sample(cfg, inp, sample)
+        ref = ref.reshape(len(sample), -1)
+        errors[args.precision] = float(np.abs(main_run["psi_sample"] - ref).max())
+        if f64_run is not None:
+            errors["f64"] = float(np.abs(f64_run["psi_sample"] - ref).max())
+        cpu_work = len(sample) * cfg.n_points * 8
+        cpu = {"value": cpu_work / t_cpu, "unit": "orbital·gridpt·Hψ/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"one AETRS propagation (8 H psi) of {len(sample)} of the 128 orbitals "
+                         f"of the 96^3 workload, FP64 NumPy, single thread, {t_cpu:.1f} s"}
+
+    ms = main_run["ms_per_step"]
+    value = work / (ms * 1e-3)
+    avg_ms = main_run["kernel_ms"] / max(1, main_run["launches"])
+    avg_bytes = main_run["kernel_bytes"] / max(1, main_run["launches"])
+    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = traffic_entry()
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "orbital·gridpt·Hψ/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "f64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "single system: 96^3 grid h=0.25, 64 ions Z=4 (uniform, min sep 2.5), "
+                               "128 complex orbitals, mu=4, dt=0.08, AETRS+Taylor-4, whole MD step",
+                   "precision": args.precision, "grid": 96, "n_orb": cfg.n_orb, "n_ions": cfg.n_ions,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "stencil_kernel (Horner stage)",
+                     "kernel_avg_ms": avg_ms, "algorithmic_bytes_per_launch": avg_bytes},
+        "cpu_baseline": cpu,
+        "errors_vs_fp64_oracle_one_step": errors,
+        "energy_drift": {"total": main_run["energy_drift"], "steps": main_run["steps_total"],
+                         "max_norm_dev": main_run["report"]["max_norm_dev"]},
+    }
+    if f64_run is not None:
+        out["fp64"] = {"ms_per_step": f64_run["ms_per_step"],
+                       "value": work / (f64_run["ms_per_step"] * 1e-3),
+                       "stencil_avg_ms": f64_run["kernel_ms"] / max(1, f64_run["launches"])}
+        out["speedup_vs_fp64"] = f64_run["ms_per_step"] / ms
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -63,7 +63,8 @@ typedef enum {
     ME_EDEVICE = 3,       /* HIP or rocFFT error (text in me_last_error) */
     ME_ESTATE = 4,        /* call before me_set_state, or wrong mode */
     ME_EUNSTABLE = 5,     /* an orbital norm grew or became non-finite */
-    ME_EUNSUPPORTED = 6   /* valid request this build does not support */
+    ME_EUNSUPPORTED = 6   /* valid request this build does not support (e.g. a grid
+                             point inside more than 8 projector spheres) */
 } me_status;
 
 typedef enum {
@@ -76,7 +77,7 @@ typedef struct me_system me_system;
 
 /* Parameters of one system.  Host pointers; copied by me_init_system. */
 typedef struct {
-    int32_t n[3];          /* grid points along x, y, z (each >= 9) */
+    int32_t n[3];          /* grid points along x, y, z (each in [8, 1024]; cubic) */
     double h;              /* grid spacing, bohr (> 0) */
     int32_t n_ions;        /* >= 0 */
     const double* pos;     /* [n_ions][3] initial positions, bohr */

@@ -15,7 +15,7 @@ from typing import Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmodehr.so")
+LIB_PATH = os.environ.get("MODEHR_LIB", os.path.join(HERE, "libmodehr.so"))
 
 ME_OK, ME_EINVAL, ME_ENOMEM, ME_EDEVICE, ME_ESTATE, ME_EUNSTABLE, ME_EUNSUPPORTED = range(7)
 PRECISION = {"f64": 0, "f32": 1, "f32_bf16x3": 2}

@@ -15,8 +15,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-OUT = os.path.join(HERE, "libmodehr.so")
-BUILD = os.path.join(ROOT, "_build")
+OUT = os.environ.get("MODEHR_LIB_OUT", os.path.join(HERE, "libmodehr.so"))
+BUILD = os.path.join(ROOT, "_build", os.path.basename(OUT))
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 ARCH = os.environ.get("MODEHR_ARCH", "gfx950")
@@ -26,7 +26,7 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
-]
+] + os.environ.get("MODEHR_HIPCC_FLAGS", "").split()
 
 
 def sources():

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <new>
 #include <string>
 #include <vector>
@@ -80,8 +81,9 @@ struct Geometry {
     size_t bc;        // bytes per complex
     size_t br;        // bytes per real of the compute precision
     int px, ty, nyt, zchunk, nzc;
-    int kcap, words;
-    int side[3];
+    int kcap;
+    int64_t ucap;      // upper bound of projector-covered grid points
+    int64_t nscan;     // point-numbering blocks
     int m;
     int64_t nhalf;    // half-spectrum size
     int floc_chunks;
@@ -90,17 +92,29 @@ struct Geometry {
     int ewald_ng;
 };
 
-int choose_px(int nx, bool f64) {
-    const int w = f64 ? 1 : 2;
-    return nx % w == 0 ? w : 1;
+int env_int(const char* name, int dflt) {
+    const char* v = std::getenv(name);
+    return v && *v ? std::atoi(v) : dflt;
 }
 
+// x-points per thread of the stencil kernel (1 or 2)
+int choose_px(int nx, bool f64) {
+    int w = env_int("MODEHR_PX", 1);
+    if (w != 1 && w != 2) w = 1;
+    while (w > 1 && nx % w) w /= 2;
+    return w;
+}
+
+// y-rows per stencil workgroup: the largest candidate dividing ny that keeps
+// the workgroup within 1024 threads and its two LDS planes within 64 KiB
 int choose_ty(int nx, int ny, int px, size_t bc) {
     const int nxt = nx / px;
+    const int cap = env_int("MODEHR_TY", 16);
     for (int ty : {16, 8, 4, 2, 1}) {
+        if (ty > cap) continue;
         if (ny % ty) continue;
         if ((int64_t)nxt * ty > 1024) continue;
-        if ((size_t)(ty + 8) * nx * bc > 64 * 1024) continue;
+        if (2 * (size_t)(ty + 8) * nx * bc > 64 * 1024) continue;
         return ty;
     }
     return -1;
@@ -121,7 +135,7 @@ int choose_zchunk(int nz, int64_t base_blocks) {
 me_status validate(const me_params* p, std::string& err) {
     if (!p) { err = "params is NULL"; return ME_EINVAL; }
     for (int a = 0; a < 3; ++a)
-        if (p->n[a] < 8 || p->n[a] > 4096) { err = "grid size must be in [8, 4096] along every axis"; return ME_EINVAL; }
+        if (p->n[a] < 8 || p->n[a] > 1024) { err = "grid size must be in [8, 1024] along every axis"; return ME_EINVAL; }
     if (!(p->h > 0) || !std::isfinite(p->h)) { err = "h must be positive"; return ME_EINVAL; }
     if (p->n_ions < 0 || p->n_ions > 32 * MAX_WORDS) { err = "n_ions out of range"; return ME_EINVAL; }
     if (p->n_ions > 0 && (!p->pos || !p->mass || !p->zval)) { err = "pos/mass/zval must not be NULL"; return ME_EINVAL; }
@@ -163,11 +177,11 @@ Geometry make_geometry(const me_params* p) {
     g.m = m;
     int kc = 1;
     for (int a = 0; a < 3; ++a) {
-        g.side[a] = std::min(2 * m + 2, p->n[a]);
-        kc *= g.side[a];
+        kc *= std::min(2 * m + 2, p->n[a]);
     }
     g.kcap = kc;
-    g.words = std::max(1, (g.n_ions + 31) / 32);
+    g.ucap = std::max<int64_t>(1, std::min<int64_t>(g.N, (int64_t)std::max(1, g.n_ions) * g.kcap));
+    g.nscan = (g.N + 1023) / 1024;
     g.nhalf = (int64_t)(g.nx / 2 + 1) * g.ny * g.nz;
     g.floc_chunks = local_force_chunks(g.N);
     g.nblk256 = (g.N + 255) / 256;
@@ -185,13 +199,12 @@ struct Layout {
     double *pos, *pos_next, *vel, *frc, *mass, *zval;
     int32_t* tidx[2];
     void* tp[2];
-    void* tbox[2];
-    int32_t* tstart[2];
+    int32_t *tmap[2], *tpts[2], *tcnt[2], *tion[2], *tnslots[2], *tflag[2], *tblk[2];
+    void* tpl[2];
     int32_t* tcount[2];
-    uint32_t* tmask[2];
     double *fnl, *enl_part, *floc_part, *fion, *eion_part, *erec_part;
     double *ewald_gv, *ewald_wv;
-    double *norm_part, *kin_part, *hxc_part, *loc_part, *rep;
+    double *norm_part, *fix_part, *kin_part, *hxc_part, *loc_part, *rep;
     size_t total;
 };
 
@@ -226,10 +239,15 @@ static Layout carve(const Geometry& g, char* base) {
     for (int t = 0; t < 2; ++t) {
         L.tidx[t] = c.take<int32_t>((size_t)std::max(1, g.n_ions) * g.kcap * 4);
         L.tp[t] = c.take<void>((size_t)std::max(1, g.n_ions) * g.kcap * g.br);
-        L.tbox[t] = c.take<void>((size_t)std::max(1, g.n_ions) * g.kcap * g.br);
-        L.tstart[t] = c.take<int32_t>((size_t)std::max(1, g.n_ions) * 3 * 4);
+        L.tmap[t] = c.take<int32_t>((size_t)g.N * 4);
+        L.tpts[t] = c.take<int32_t>((size_t)g.ucap * 4);
+        L.tcnt[t] = c.take<int32_t>((size_t)g.ucap * 4);
+        L.tion[t] = c.take<int32_t>((size_t)g.ucap * NL_KMAX * 4);
+        L.tpl[t] = c.take<void>((size_t)g.ucap * NL_KMAX * g.br);
+        L.tnslots[t] = c.take<int32_t>(4);
+        L.tflag[t] = c.take<int32_t>(4);
+        L.tblk[t] = c.take<int32_t>((size_t)(g.nscan + 1) * 4);
         L.tcount[t] = c.take<int32_t>((size_t)std::max(1, g.n_ions) * 4);
-        L.tmask[t] = c.take<uint32_t>((size_t)g.nz * g.nyt * g.words * 4);
     }
     L.fnl = c.take<double>(ion3);
     L.enl_part = c.take<double>(ion3 / 3);
@@ -241,6 +259,7 @@ static Layout carve(const Geometry& g, char* base) {
     L.ewald_gv = c.take<double>((size_t)std::max(1, g.ewald_ng) * 3 * 8);
     L.ewald_wv = c.take<double>((size_t)std::max(1, g.ewald_ng) * 8);
     L.norm_part = c.take<double>((size_t)g.n_orb * g.nyt * g.nzc * 8);
+    L.fix_part = c.take<double>((size_t)g.n_orb * FIX_XB * 8);
     L.kin_part = c.take<double>((size_t)g.n_orb * g.nyt * g.nzc * 8);
     L.hxc_part = c.take<double>((size_t)g.nblk256 * 3 * 8);
     L.loc_part = c.take<double>((size_t)g.nblk256 * 8);
@@ -301,18 +320,21 @@ namespace {
     } while (0)
 
 KbTables tables(me_system* sys, int t) {
-    KbTables k;
+    KbTables k{};
     k.idx = sys->w.tidx[t];
     k.p = sys->w.tp[t];
-    k.pbox = sys->w.tbox[t];
-    k.start = sys->w.tstart[t];
-    for (int a = 0; a < 3; ++a) k.side[a] = sys->g.side[a];
-    k.m = sys->g.m;
     k.count = sys->w.tcount[t];
-    k.mask = sys->w.tmask[t];
     k.kcap = sys->g.kcap;
-    k.words = sys->g.words;
-    k.ty = sys->g.ty;
+    k.m = sys->g.m;
+    k.map = sys->w.tmap[t];
+    k.pts = sys->w.tpts[t];
+    k.cnt = sys->w.tcnt[t];
+    k.ion = sys->w.tion[t];
+    k.pl = sys->w.tpl[t];
+    k.nslots = sys->w.tnslots[t];
+    k.flag = sys->w.tflag[t];
+    k.blk = sys->w.tblk[t];
+    k.ucap = sys->g.ucap;
     return k;
 }
 
@@ -411,7 +433,7 @@ hipEvent_t pooled_event(me_system* sys) {
 }
 
 template <typename T>
-StencilArgs<T> base_args(me_system* sys, const T* v, const cx_t<T>* cnl, int t, int n_orb) {
+StencilArgs<T> base_args(me_system* sys, const T* v, int n_orb) {
     const Geometry& g = sys->g;
     StencilArgs<T> a{};
     a.v = v;
@@ -422,12 +444,6 @@ StencilArgs<T> base_args(me_system* sys, const T* v, const cx_t<T>* cnl, int t, 
     a.nyt = g.nyt;
     a.nzc = g.nzc;
     a.kin = (T)(-0.5 / (sys->prm.h * sys->prm.h));
-    a.cnl = g.n_ions > 0 ? cnl : nullptr;
-    a.mask = sys->w.tmask[t];
-    a.words = g.words;
-    a.pbox = (const T*)sys->w.tbox[t];
-    a.start = sys->w.tstart[t];
-    for (int k = 0; k < 3; ++k) a.side[k] = g.side[k];
     return a;
 }
 
@@ -450,7 +466,7 @@ me_status exponential(me_system* sys, const T* veff, int t, bool last) {
         C* out = (k == 1 && K > 1) ? psi : bufs[nb];
         HIPCHK(launch_kb_gather<T>(u, g.stride, g.n_orb, g.n_ions, tables(sys, t), ekb_h3, (C*)sys->w.cnl,
                                    sys->stream));
-        StencilArgs<T> a = base_args<T>(sys, veff, (const C*)sys->w.cnl, t, g.n_orb);
+        StencilArgs<T> a = base_args<T>(sys, veff, g.n_orb);
         a.u = u;
         a.psi0 = psi;
         a.out = out;
@@ -464,13 +480,17 @@ me_status exponential(me_system* sys, const T* veff, int t, bool last) {
             e1 = pooled_event(sys);
             if (e0 && e1) HIPCHK(hipEventRecord(e0, sys->stream));
         }
-        HIPCHK(launch_stencil<T>(a, mode, norm, g.ty, sys->stream));
+        HIPCHK(launch_stencil<T>(a, mode, norm, g.ty, g.px, sys->stream));
         if (sys->timing && e0 && e1) {
             HIPCHK(hipEventRecord(e1, sys->stream));
             sys->ev.emplace_back(e0, e1);
             const double streams = mode == MODE_HORNER_FIRST ? 2.0 : 3.0;
             sys->ev_bytes.push_back(streams * g.bc * (double)g.N * g.n_orb + (double)g.br * g.N);
         }
+        // nonlocal part at the projector points: out += (-i tau/k) E_KB sum_J p_J c_J
+        if (g.n_ions > 0)
+            HIPCHK(launch_kb_fixup<T>(out, g.stride, g.n_orb, tables(sys, t), (const C*)sys->w.cnl, 0.0, -tau / k,
+                                      norm ? sys->w.fix_part : nullptr, sys->stream));
         u = out;
         nb ^= 1;
     }
@@ -508,21 +528,24 @@ me_status finalize(me_system* sys, bool with_norm, bool energy) {
     if (energy) {
         // kinetic expectation per orbital, E_loc = h^3 sum rho V_loc
         if (g.f64) {
-            StencilArgs<double> a = base_args<double>(sys, nullptr, nullptr, sys->tab_cur, g.n_orb);
+            StencilArgs<double> a = base_args<double>(sys, nullptr, g.n_orb);
             a.u = (const double2*)sys->w.psi;
             a.partial = sys->w.kin_part;
-            HIPCHK(launch_stencil<double>(a, MODE_EXPECT_T, false, g.ty, sys->stream));
+            HIPCHK(launch_stencil<double>(a, MODE_EXPECT_T, false, g.ty, g.px, sys->stream));
         } else {
-            StencilArgs<float> a = base_args<float>(sys, nullptr, nullptr, sys->tab_cur, g.n_orb);
+            StencilArgs<float> a = base_args<float>(sys, nullptr, g.n_orb);
             a.u = (const float2*)sys->w.psi;
             a.partial = sys->w.kin_part;
-            HIPCHK(launch_stencil<float>(a, MODE_EXPECT_T, false, g.ty, sys->stream));
+            HIPCHK(launch_stencil<float>(a, MODE_EXPECT_T, false, g.ty, g.px, sys->stream));
         }
         HIPCHK(launch_dot_partial(sys->w.rho, sys->w.vloc_cur, g.N, sys->w.loc_part, sys->stream));
     }
     FinalizeArgs f{};
     f.rep = sys->w.rep;
     f.norm_part = with_norm ? sys->w.norm_part : nullptr;
+    f.fix_part = (with_norm && g.n_ions > 0) ? sys->w.fix_part : nullptr;
+    f.fix_tiles = FIX_XB;
+    f.nl_flag = g.n_ions > 0 ? sys->w.tflag[sys->tab_cur] : nullptr;
     f.n_orb = g.n_orb;
     f.norm_tiles = g.nyt * g.nzc;
     f.norm_tol = g.f64 ? 1e-6 : 1e-5;
@@ -567,6 +590,10 @@ me_status read_report(me_system* sys, me_step_report* rep) {
         rep->max_force = r[SLOT_FMAX];
         rep->charge = r[SLOT_CHARGE];
         rep->step = sys->step;
+    }
+    if (r[SLOT_UNSTABLE] == 2.0) {
+        sys->err = "a grid point lies inside more than 8 projector spheres";
+        return ME_EUNSUPPORTED;
     }
     if (r[SLOT_UNSTABLE] != 0.0) {
         sys->err = "orbital norm grew beyond tolerance or became non-finite";
@@ -851,21 +878,25 @@ me_status me_apply_H(me_system* sys, const void* psi_in_dev, void* hpsi_out_dev,
             double2* outp = (double2*)hpsi_out_dev + (size_t)o0 * orb_stride;
             HIPCHK(launch_kb_gather<double>(in, orb_stride, nb, g.n_ions, tables(sys, sys->tab_cur), ekb_h3,
                                             (double2*)sys->w.cnl, sys->stream));
-            StencilArgs<double> a = base_args<double>(sys, (const double*)sys->w.veff0, (const double2*)sys->w.cnl,
-                                                      sys->tab_cur, nb);
+            StencilArgs<double> a = base_args<double>(sys, (const double*)sys->w.veff0, nb);
             a.u = in; a.psi0 = in; a.out = outp; a.stride = orb_stride;
             a.zchunk = g.nz; a.nzc = 1;
-            HIPCHK(launch_stencil<double>(a, MODE_APPLY, false, g.ty, sys->stream));
+            HIPCHK(launch_stencil<double>(a, MODE_APPLY, false, g.ty, g.px, sys->stream));
+            if (g.n_ions > 0)
+                HIPCHK(launch_kb_fixup<double>(outp, orb_stride, nb, tables(sys, sys->tab_cur), (const double2*)sys->w.cnl,
+                                               1.0, 0.0, nullptr, sys->stream));
         } else {
             const float2* in = (const float2*)psi_in_dev + (size_t)o0 * orb_stride;
             float2* outp = (float2*)hpsi_out_dev + (size_t)o0 * orb_stride;
             HIPCHK(launch_kb_gather<float>(in, orb_stride, nb, g.n_ions, tables(sys, sys->tab_cur), ekb_h3,
                                            (float2*)sys->w.cnl, sys->stream));
-            StencilArgs<float> a = base_args<float>(sys, (const float*)sys->w.veff0, (const float2*)sys->w.cnl,
-                                                    sys->tab_cur, nb);
+            StencilArgs<float> a = base_args<float>(sys, (const float*)sys->w.veff0, nb);
             a.u = in; a.psi0 = in; a.out = outp; a.stride = orb_stride;
             a.zchunk = g.nz; a.nzc = 1;
-            HIPCHK(launch_stencil<float>(a, MODE_APPLY, false, g.ty, sys->stream));
+            HIPCHK(launch_stencil<float>(a, MODE_APPLY, false, g.ty, g.px, sys->stream));
+            if (g.n_ions > 0)
+                HIPCHK(launch_kb_fixup<float>(outp, orb_stride, nb, tables(sys, sys->tab_cur), (const float2*)sys->w.cnl,
+                                              1.0, 0.0, nullptr, sys->stream));
         }
     }
     return ME_OK;

@@ -34,19 +34,28 @@ struct KbGeom {
     double inv_s2;     // 1/sigma^2
 };
 
-// Per-ion projector tables (one set per ion configuration).
+constexpr int NL_KMAX = 8;       // projectors that may overlap at one grid point
+constexpr int FIX_XB = 32;       // fix-up workgroups per orbital
+
+// Per-ion projector tables (one set per ion configuration), and the same
+// information by grid point: the union of all projector spheres as a list of
+// slots, each with the (ion, value) pairs covering it, ordered by ion.
 struct KbTables {
     int32_t* idx;      // [n_ions][kcap] linear grid index
     void* p;           // [n_ions][kcap] projector value in the compute precision
-    void* pbox;        // [n_ions][kcap] the same values on the dense candidate box (0 outside)
-    int32_t* start;    // [n_ions][3] first box point per axis, wrapped into [0, n)
-    int side[3];       // box extent per axis (kcap = side[0]*side[1]*side[2])
-    int m;             // box half-width: side = min(2m+2, n)
     int32_t* count;    // [n_ions]
-    uint32_t* mask;    // [nz][nyt][words] ions touching (plane z, y-tile)
     int kcap;
-    int words;
-    int ty;            // y rows per stencil tile the masks were built for
+    int m;             // candidate box half-width: per axis min(2m+2, n) points
+    // point lists
+    int32_t* map;      // [N] slot of each grid point, or -1
+    int32_t* pts;      // [ucap] grid index of each slot
+    int32_t* cnt;      // [ucap] pairs per slot
+    int32_t* ion;      // [ucap][NL_KMAX]
+    void* pl;          // [ucap][NL_KMAX] projector values
+    int32_t* nslots;   // [1]
+    int32_t* flag;     // [1] set when a point is covered by more than NL_KMAX spheres
+    int32_t* blk;      // [scan blocks + 1] scratch of the slot numbering
+    int64_t ucap;
 };
 
 enum StencilMode : int {
@@ -69,13 +78,6 @@ struct StencilArgs {
     int nyt, nzc;            // tiles along y, chunks along z
     T kin;                   // -1/(2 h^2)
     T alpha;                 // Horner coefficient: c_k = i*alpha, alpha = -tau/k
-    // nonlocal scatter: cnl[J*n_orb + A] = E_KB * c_JA ; nullptr = no projectors
-    const cx_t<T>* cnl;
-    const uint32_t* mask;
-    int words;
-    const T* pbox;           // projector values on each ion's candidate box
-    const int32_t* start;    // box origin per ion
-    int side[3];
     double* partial;         // [n_orb][nyt*nzc] norm or expectation partials, or nullptr
 };
 
@@ -83,11 +85,17 @@ struct StencilArgs {
 // All launchers enqueue on `s` and return hipGetLastError().
 template <typename T>
 hipError_t launch_stencil(const StencilArgs<T>& a, int mode, bool want_norm,
-                          int ty, hipStream_t s);
+                          int ty, int px, hipStream_t s);
 
 template <typename T>
 hipError_t launch_kb_tables(const double* pos, int n_ions, int nx, int ny, int nz,
                             const KbGeom& g, KbTables t, hipStream_t s);
+
+// out_A(r) += (gr + i gi) * sum_{J covers r} p_J(r) cnl[J*n_orb + A], at the
+// projector points only; dnorm (nullable): [n_orb][FIX_XB] change of |out_A|^2
+template <typename T>
+hipError_t launch_kb_fixup(cx_t<T>* out, int64_t stride, int n_orb, KbTables t,
+                           const cx_t<T>* cnl, double gr, double gi, double* dnorm, hipStream_t s);
 
 // cnl[J*n_orb + A] = ekb * h^3 sum_k p_J(k) u_A(idx_J(k))
 template <typename T>

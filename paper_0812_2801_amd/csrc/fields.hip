@@ -411,6 +411,8 @@ __global__ void __launch_bounds__(256) report_kernel(FinalizeArgs a) {
         for (int A = tid; A < a.n_orb; A += 256) {
             double s = 0.0;
             for (int k = 0; k < a.norm_tiles; ++k) s += a.norm_part[(int64_t)A * a.norm_tiles + k];
+            if (a.fix_part != nullptr)
+                for (int k = 0; k < a.fix_tiles; ++k) s += a.fix_part[(int64_t)A * a.fix_tiles + k];
             s *= a.dv;
             if (!isfinite(s)) bad = 1;
             const double dev = fabs(s - 1.0);
@@ -435,6 +437,7 @@ __global__ void __launch_bounds__(256) report_kernel(FinalizeArgs a) {
         a.rep[SLOT_NORM_DEV] = mx[0];
         if (bd[0]) a.rep[SLOT_UNSTABLE] = 1.0;
     }
+    if (tid == 0 && a.nl_flag != nullptr && *a.nl_flag != 0) a.rep[SLOT_UNSTABLE] = 2.0;
     __syncthreads();
     if (!a.energy) return;
     // sequential partial sums in fixed order

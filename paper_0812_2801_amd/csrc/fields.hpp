@@ -13,8 +13,11 @@ enum ReportSlot : int {
 struct FinalizeArgs {
     double* rep;                 // [SLOT_COUNT]
     const double* norm_part;     // [n_orb][norm_tiles] or nullptr
+    const double* fix_part;      // [n_orb][fix_tiles] nonlocal change of the norm, or nullptr
+    const int32_t* nl_flag;      // nonzero: a grid point lies in too many projector spheres
     int n_orb;
     int norm_tiles;
+    int fix_tiles;
     double norm_tol;
     double dv;                   // h^3
     double occ;

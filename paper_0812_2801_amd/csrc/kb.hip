@@ -16,7 +16,6 @@ template <typename T>
 __global__ void __launch_bounds__(256) kb_tables_kernel(const double* __restrict__ pos,
                                                         int nx, int ny, int nz, KbGeom g, int m,
                                                         int32_t* __restrict__ idx, T* __restrict__ pv,
-                                                        T* __restrict__ pbox, int32_t* __restrict__ bstart,
                                                         int32_t* __restrict__ count, int kcap) {
     __shared__ int wsum[4];
     __shared__ int base_off;
@@ -37,11 +36,6 @@ __global__ void __launch_bounds__(256) kb_tables_kernel(const double* __restrict
     }
     const int total = min(side[0] * side[1] * side[2], kcap);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    if (tid < 3) {
-        int s0 = start[tid] % n3[tid];
-        if (s0 < 0) s0 += n3[tid];
-        bstart[3 * J + tid] = s0;
-    }
     if (tid == 0) base_off = 0;
     __syncthreads();
     for (int c0 = 0; c0 < total; c0 += 256) {
@@ -60,7 +54,6 @@ __global__ void __launch_bounds__(256) kb_tables_kernel(const double* __restrict
             d2 = kb_d2(g, gx, gy, gz, rx, ry, rz, dx, dy, dz);
             inside = d2 < g.rcut2;
             lin = (gz * ny + gy) * nx + gx;
-            pbox[(int64_t)J * kcap + c] = inside ? (T)kb_value(g, d2) : (T)0;
         }
         const unsigned long long bal = __ballot(inside);
         const int before = __popcll(bal & ((1ull << lane) - 1ull));
@@ -82,48 +75,211 @@ __global__ void __launch_bounds__(256) kb_tables_kernel(const double* __restrict
     if (tid == 0) count[J] = base_off < kcap ? base_off : kcap;
 }
 
-// Ions whose sphere reaches the rows [y0, y0+TY) of plane z (any x): bit J of
-// mask[(z*nyt + ytile)*words + J/32].  Conservative by a small slack; the
-// stencil re-checks each point exactly.
-__global__ void kb_mask_kernel(const double* __restrict__ pos, int n_ions, int ny, int nz,
-                               int ty, int nyt, int words, KbGeom g, uint32_t* __restrict__ mask) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = (int64_t)nz * nyt * n_ions;
-    if (t >= total) return;
-    const int J = (int)(t % n_ions);
-    const int64_t row = t / n_ions;              // z*nyt + ytile
-    const int ytile = (int)(row % nyt);
-    const int z = (int)(row / nyt);
-    const double dz = min_image(g.h * (double)z - pos[3 * J + 2], g.L[2]);
-    const double dz2 = dz * dz;
-    if (dz2 >= g.rcut2 + 1e-9) return;
-    double dymin2 = 1e300;
-    for (int k = 0; k < ty; ++k) {
-        const double dy = min_image(g.h * (double)(ytile * ty + k) - pos[3 * J + 1], g.L[1]);
-        dymin2 = fmin(dymin2, dy * dy);
-    }
-    if (dz2 + dymin2 < g.rcut2 + 1e-9)
-        atomicOr(&mask[row * words + (J >> 5)], 1u << (J & 31));
+// ------------------------------------------------------------ point lists
+// The union of the projector spheres, by grid point.  Slots are numbered in
+// increasing grid index; the (ion, value) pairs of a slot are sorted by ion,
+// so every sum over them runs in a fixed order.
+__global__ void fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
-__global__ void zero_u32_kernel(uint32_t* __restrict__ p, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0u;
+__global__ void nl_mark_kernel(const int32_t* __restrict__ idx, const int32_t* __restrict__ count,
+                               int kcap, int32_t* __restrict__ map) {
+    const int J = blockIdx.y;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < count[J]) map[idx[(int64_t)J * kcap + k]] = 0;
+}
+
+constexpr int SCAN_B = 1024;     // grid points per numbering block (256 threads x 4)
+
+__global__ void __launch_bounds__(256) nl_count_kernel(const int32_t* __restrict__ map, int64_t N,
+                                                       int32_t* __restrict__ blk) {
+    __shared__ int ws[4];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_B + threadIdx.x * 4;
+    int c = 0;
+    for (int i = 0; i < 4; ++i)
+        if (base + i < N && map[base + i] == 0) ++c;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) blk[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+// exclusive scan of the block counts (one workgroup); total into *nslots
+__global__ void __launch_bounds__(256) nl_scan_blocks_kernel(int32_t* __restrict__ blk, int nblk,
+                                                             int32_t* __restrict__ nslots) {
+    __shared__ int carry;
+    __shared__ int ws[4];
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int b0 = 0; b0 < nblk; b0 += 256) {
+        const int i = b0 + threadIdx.x;
+        const int v = i < nblk ? blk[i] : 0;
+        int x = v;                                   // inclusive scan within the wave
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) ws[wv] = x;
+        __syncthreads();
+        int before = carry;
+        for (int w = 0; w < wv; ++w) before += ws[w];
+        if (i < nblk) blk[i] = before + x - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += ws[0] + ws[1] + ws[2] + ws[3];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *nslots = carry;
+}
+
+__global__ void __launch_bounds__(256) nl_number_kernel(int32_t* __restrict__ map, int64_t N,
+                                                        const int32_t* __restrict__ blk,
+                                                        int32_t* __restrict__ pts) {
+    __shared__ int ws[4];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_B + threadIdx.x * 4;
+    int f[4], c = 0;
+    for (int i = 0; i < 4; ++i) {
+        f[i] = (base + i < N && map[base + i] == 0) ? 1 : 0;
+        c += f[i];
+    }
+    int x = c;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) ws[wv] = x;
+    __syncthreads();
+    int slot = blk[blockIdx.x] + x - c;
+    for (int w = 0; w < wv; ++w) slot += ws[w];
+    for (int i = 0; i < 4; ++i)
+        if (f[i]) {
+            map[base + i] = slot;
+            pts[slot] = (int32_t)(base + i);
+            ++slot;
+        }
+}
+
+template <typename T>
+__global__ void nl_fill_kernel(const int32_t* __restrict__ idx, const T* __restrict__ pv,
+                               const int32_t* __restrict__ count, int kcap,
+                               const int32_t* __restrict__ map, int32_t* __restrict__ cnt,
+                               int32_t* __restrict__ ion, T* __restrict__ pl,
+                               int32_t* __restrict__ flag) {
+    const int J = blockIdx.y;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count[J]) return;
+    const int64_t e = (int64_t)J * kcap + k;
+    const int s = map[idx[e]];
+    const int pos = atomicAdd(&cnt[s], 1);
+    if (pos < NL_KMAX) {
+        ion[(int64_t)s * NL_KMAX + pos] = J;
+        pl[(int64_t)s * NL_KMAX + pos] = pv[e];
+    } else {
+        atomicOr(flag, 1);
+    }
+}
+
+template <typename T>
+__global__ void nl_sort_kernel(const int32_t* __restrict__ nslots, int32_t* __restrict__ cnt,
+                               int32_t* __restrict__ ion, T* __restrict__ pl) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= *nslots) return;
+    const int n = min(cnt[s], NL_KMAX);
+    cnt[s] = n;
+    int32_t* ji = ion + (int64_t)s * NL_KMAX;
+    T* jp = pl + (int64_t)s * NL_KMAX;
+    for (int i = 1; i < n; ++i) {
+        const int kj = ji[i];
+        const T kp = jp[i];
+        int j = i - 1;
+        while (j >= 0 && ji[j] > kj) {
+            ji[j + 1] = ji[j];
+            jp[j + 1] = jp[j];
+            --j;
+        }
+        ji[j + 1] = kj;
+        jp[j + 1] = kp;
+    }
 }
 
 template <typename T>
 hipError_t launch_kb_tables(const double* pos, int n_ions, int nx, int ny, int nz,
                             const KbGeom& g, KbTables t, hipStream_t s) {
     if (n_ions == 0) return hipSuccess;
+    const int64_t N = (int64_t)nx * ny * nz;
+    const int64_t nblk = (N + SCAN_B - 1) / SCAN_B;
     kb_tables_kernel<T><<<n_ions, 256, 0, s>>>(pos, nx, ny, nz, g, t.m, t.idx,
-                                               reinterpret_cast<T*>(t.p), reinterpret_cast<T*>(t.pbox),
-                                               t.start, t.count, t.kcap);
-    const int nyt = ny / t.ty;
-    const int64_t mw = (int64_t)nz * nyt * t.words;
-    zero_u32_kernel<<<(unsigned)((mw + 255) / 256), 256, 0, s>>>(t.mask, mw);
-    const int64_t total = (int64_t)nz * nyt * n_ions;
-    kb_mask_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(pos, n_ions, ny, nz, t.ty, nyt,
-                                                                   t.words, g, t.mask);
+                                               reinterpret_cast<T*>(t.p), t.count, t.kcap);
+    fill_i32_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(t.map, N, -1);
+    fill_i32_kernel<<<(unsigned)((t.ucap + 255) / 256), 256, 0, s>>>(t.cnt, t.ucap, 0);
+    fill_i32_kernel<<<1, 64, 0, s>>>(t.flag, 1, 0);
+    dim3 eg((t.kcap + 255) / 256, n_ions);
+    nl_mark_kernel<<<eg, 256, 0, s>>>(t.idx, t.count, t.kcap, t.map);
+    nl_count_kernel<<<(unsigned)nblk, 256, 0, s>>>(t.map, N, t.blk);
+    nl_scan_blocks_kernel<<<1, 256, 0, s>>>(t.blk, (int)nblk, t.nslots);
+    nl_number_kernel<<<(unsigned)nblk, 256, 0, s>>>(t.map, N, t.blk, t.pts);
+    nl_fill_kernel<T><<<eg, 256, 0, s>>>(t.idx, reinterpret_cast<const T*>(t.p), t.count, t.kcap, t.map,
+                                         t.cnt, t.ion, reinterpret_cast<T*>(t.pl), t.flag);
+    nl_sort_kernel<T><<<(unsigned)((t.ucap + 255) / 256), 256, 0, s>>>(t.nslots, t.cnt, t.ion,
+                                                                       reinterpret_cast<T*>(t.pl));
+    return hipGetLastError();
+}
+
+// out_A(r) += g * sum_k pl * cnl[ion*n_orb + A] over the slots of the
+// projector spheres.  Grid (FIX_XB, n_orb): neighbouring lanes take
+// neighbouring slots of one orbital.  With dnorm, the change of the
+// orbital's squared norm, sum |out + d|^2 - |out|^2, is returned per block.
+template <typename T>
+__global__ void __launch_bounds__(256) kb_fixup_kernel(cx_t<T>* __restrict__ out, int64_t stride,
+                                                       int n_orb, const int32_t* __restrict__ nslots,
+                                                       const int32_t* __restrict__ pts,
+                                                       const int32_t* __restrict__ cnt,
+                                                       const int32_t* __restrict__ ion,
+                                                       const T* __restrict__ pl,
+                                                       const cx_t<T>* __restrict__ cnl, T gr, T gi,
+                                                       double* __restrict__ dnorm) {
+    __shared__ double red[4];
+    const int A = blockIdx.y;
+    const int ns = *nslots;
+    cx_t<T>* oa = out + (int64_t)A * stride;
+    double dn = 0.0;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < ns; s += gridDim.x * blockDim.x) {
+        const int n = cnt[s];
+        T sr = 0, si = 0;
+        for (int k = 0; k < n; ++k) {
+            const T w = pl[(int64_t)s * NL_KMAX + k];
+            const cx_t<T> c = cnl[(int64_t)ion[(int64_t)s * NL_KMAX + k] * n_orb + A];
+            sr += w * c.x;
+            si += w * c.y;
+        }
+        cx_t<T>* o = oa + pts[s];
+        const cx_t<T> old = *o;
+        cx_t<T> val = old;
+        val.x += gr * sr - gi * si;
+        val.y += gr * si + gi * sr;
+        *o = val;
+        if (dnorm != nullptr)
+            dn += ((double)val.x * val.x + (double)val.y * val.y) -
+                  ((double)old.x * old.x + (double)old.y * old.y);
+    }
+    if (dnorm != nullptr) {
+        for (int o = 32; o > 0; o >>= 1) dn += __shfl_xor(dn, o, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dn;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            dnorm[(int64_t)A * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+    }
+}
+
+template <typename T>
+hipError_t launch_kb_fixup(cx_t<T>* out, int64_t stride, int n_orb, KbTables t,
+                           const cx_t<T>* cnl, double gr, double gi, double* dnorm, hipStream_t s) {
+    dim3 grid(FIX_XB, n_orb);
+    kb_fixup_kernel<T><<<grid, 256, 0, s>>>(out, stride, n_orb, t.nslots, t.pts, t.cnt, t.ion,
+                                            reinterpret_cast<const T*>(t.pl), cnl, (T)gr, (T)gi, dnorm);
     return hipGetLastError();
 }
 
@@ -247,6 +403,8 @@ hipError_t launch_kb_forces(const cx_t<T>* psi, int64_t stride, int n_orb, int n
 
 template hipError_t launch_kb_tables<double>(const double*, int, int, int, int, const KbGeom&, KbTables, hipStream_t);
 template hipError_t launch_kb_tables<float>(const double*, int, int, int, int, const KbGeom&, KbTables, hipStream_t);
+template hipError_t launch_kb_fixup<double>(cx_t<double>*, int64_t, int, KbTables, const cx_t<double>*, double, double, double*, hipStream_t);
+template hipError_t launch_kb_fixup<float>(cx_t<float>*, int64_t, int, KbTables, const cx_t<float>*, double, double, double*, hipStream_t);
 template hipError_t launch_kb_gather<double>(const cx_t<double>*, int64_t, int, int, KbTables, double, cx_t<double>*, hipStream_t);
 template hipError_t launch_kb_gather<float>(const cx_t<float>*, int64_t, int, int, KbTables, double, cx_t<float>*, hipStream_t);
 template hipError_t launch_kb_forces<double>(const cx_t<double>*, int64_t, int, int, KbTables, const double*, const KbGeom&, int, int, double, double, double*, double*, hipStream_t);

@@ -10,10 +10,8 @@
 // owns PX consecutive x-points of one row.  The nine z-neighbours of the
 // thread's points live in a register queue; the current plane of the slab
 // plus a 4-row y-halo is staged in LDS, x-periodicity is resolved in LDS.
-// The nonlocal part is added in the same pass: the ions whose projector
-// sphere reaches the (plane, slab) are read from a bitmask and each point
-// reads its projector value from the ion's dense candidate box (written by
-// the table build, zero outside the sphere) and adds E_KB p c_J.
+// The nonlocal part E_KB sum_J p_J c_J is added afterwards at the projector
+// points only (kb.hip), so the stencil loop carries no data-dependent loads.
 #include "common.hpp"
 #include "geometry.hpp"
 
@@ -54,11 +52,44 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+template <typename T, int PX>
+__device__ __forceinline__ void load_real(const T* __restrict__ p, T* r) {
+    if constexpr (sizeof(T) == 4 && PX == 2) {
+        const float2 t = *reinterpret_cast<const float2*>(p);
+        r[0] = t.x;
+        r[1] = t.y;
+    } else if constexpr (sizeof(T) == 4 && PX == 4) {
+        const float4 t = *reinterpret_cast<const float4*>(p);
+        r[0] = t.x; r[1] = t.y; r[2] = t.z; r[3] = t.w;
+    } else {
+#pragma unroll
+        for (int i = 0; i < PX; ++i) r[i] = p[i];
+    }
+}
+
+#ifndef STENCIL_PD
+#define STENCIL_PD 1
+#endif
+
+// Software pipeline with one barrier per plane.  Global loads run PD planes
+// ahead of the compute: at plane z the thread issues the loads of plane z+PD
+// (its y-halo run, psi0 and v_eff) and of plane z+4+PD of its z-queue, all
+// into register queues; plane z+1 is staged into the second LDS buffer after
+// plane z has been computed from the first.  The loop body issues no load
+// whose address depends on another load, so the only waits are for the
+// queued planes.  Offsets inside one orbital are 32-bit.
 template <typename T, int PX, int TY, int MODE, bool NORM>
-__global__ void __launch_bounds__(1024) stencil_kernel(StencilArgs<T> a) {
+__global__ void __launch_bounds__(1024)
+stencil_kernel(const cx_t<T>* __restrict__ u_all, const cx_t<T>* __restrict__ p0_all,
+               cx_t<T>* __restrict__ out_all, const T* __restrict__ v,
+               double* __restrict__ partial, StencilArgs<T> a) {
     using C = cx_t<T>;
+    constexpr int D = STENCIL_PD;
+    constexpr int HJ = (8 + TY - 1) / TY;          // halo runs per thread
+    constexpr bool HORNER = MODE == MODE_HORNER;
+    constexpr bool NEEDV = MODE != MODE_EXPECT_T;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C* tile = reinterpret_cast<C*>(smem_raw);     // [(TY+8)][nx]
+    C* tiles = reinterpret_cast<C*>(smem_raw);     // 2 x [(TY+8)][nx]
     __shared__ double red[16];
 
     const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -76,95 +107,89 @@ __global__ void __launch_bounds__(1024) stencil_kernel(StencilArgs<T> a) {
     const int x0 = tx * PX;
     const int z0 = zc * a.zchunk;
     const int z1 = z0 + a.zchunk;
-    const int64_t plane = (int64_t)nx * ny;
-    const int64_t rowoff = (int64_t)y * nx + x0;
+    const int plane = nx * ny;
+    const int rowoff = y * nx + x0;
+    const int tile_elems = (TY + 8) * nx;
 
-    const C* __restrict__ u = a.u + (int64_t)A * a.stride;
-    const C* __restrict__ p0 = a.psi0 + (int64_t)A * a.stride;
-    C* __restrict__ out = a.out + (int64_t)A * a.stride;
+    const C* __restrict__ u = u_all + (int64_t)A * a.stride;
+    const C* __restrict__ p0 = p0_all + (int64_t)A * a.stride;
+    C* __restrict__ out = out_all + (int64_t)A * a.stride;
 
     const T c0 = (T)(3.0 * FD_C0);
     const T cm[4] = {(T)FD_C1, (T)FD_C2, (T)FD_C3, (T)FD_C4};
 
-    C q[9][PX];
+    // LDS offsets of the x-neighbours (periodic wrap resolved once)
+    int xo[PX + 8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int zz = wrap1(z0 - 4 + k, nz);
-        load_run<T, PX>(u + zz * plane + rowoff, q[k]);
+    for (int i = 0; i < PX + 8; ++i) xo[i] = (ty + 4) * nx + wrap1(x0 - 4 + i, nx);
+    const int yo = (ty + 4) * nx + x0;
+
+    // this thread's y-halo jobs: (LDS offset, global row offset)
+    const int n_halo = 8 * nxt;
+    int h_lds[HJ], h_off[HJ];
+    bool h_ok[HJ];
+#pragma unroll
+    for (int i = 0; i < HJ; ++i) {
+        const int j = tid + i * (int)blockDim.x;
+        h_ok[i] = j < n_halo;
+        const int r = h_ok[i] ? j / nxt : 0;
+        const int xr = h_ok[i] ? (j - r * nxt) * PX : 0;
+        const int lr = r < 4 ? r : TY + r;
+        const int gy = wrap1(r < 4 ? y0 - 4 + r : y0 + TY + (r - 4), ny);
+        h_lds[i] = lr * nx + xr;
+        h_off[i] = gy * nx + xr;
     }
 
+    // register queues: q = planes z-4 .. z+4+D (the last one in flight),
+    // hq/pq/vq = planes z .. z+D
+    C q[9 + D][PX];
+    C hq[D + 1][HJ][PX];
+    C pq[D + 1][PX];
+    T vq[D + 1][PX];
+#pragma unroll
+    for (int k = 0; k < 8 + D; ++k) load_run<T, PX>(u + wrap1(z0 - 4 + k, nz) * plane + rowoff, q[k]);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        if (z0 + d < z1) {
+            const int zo = (z0 + d) * plane;
+#pragma unroll
+            for (int i = 0; i < HJ; ++i)
+                if (h_ok[i]) load_run<T, PX>(u + zo + h_off[i], hq[d][i]);
+            if constexpr (HORNER) load_run<T, PX>(p0 + zo + rowoff, pq[d]);
+            if constexpr (NEEDV) load_real<T, PX>(v + zo + rowoff, vq[d]);
+        }
+    }
+    store_run<T, PX>(tiles + yo, q[4]);
+#pragma unroll
+    for (int i = 0; i < HJ; ++i)
+        if (h_ok[i]) store_run<T, PX>(tiles + h_lds[i], hq[0][i]);
+    __syncthreads();
+
     double acc = 0.0;
-    const int n_halo = 8 * nxt;
-
     for (int z = z0; z < z1; ++z) {
-        load_run<T, PX>(u + wrap1(z + 4, nz) * plane + rowoff, q[8]);
-        __syncthreads();
-        store_run<T, PX>(tile + (ty + 4) * nx + x0, q[4]);
-        for (int j = tid; j < n_halo; j += blockDim.x) {
-            const int r = j / nxt;
-            const int xr = (j - r * nxt) * PX;
-            const int lr = r < 4 ? r : TY + r;
-            const int gy = wrap1(r < 4 ? y0 - 4 + r : y0 + TY + (r - 4), ny);
-            C tmp[PX];
-            load_run<T, PX>(u + z * plane + (int64_t)gy * nx + xr, tmp);
-            store_run<T, PX>(tile + lr * nx + xr, tmp);
-        }
-        __syncthreads();
-
-        // nonlocal contribution of the projectors reaching this (plane, slab)
-        C nl[PX];
+        const int buf = (z - z0) & 1;
+        if (z + D < z1) {
+            const int zo = (z + D) * plane;
+            load_run<T, PX>(u + wrap1(z + 4 + D, nz) * plane + rowoff, q[8 + D]);
 #pragma unroll
-        for (int p = 0; p < PX; ++p) nl[p] = C{(T)0, (T)0};
-        if constexpr (MODE != MODE_EXPECT_T) {
-            if (a.cnl != nullptr) {
-                const uint32_t* mrow = a.mask + ((int64_t)z * a.nyt + ytile) * a.words;
-                for (int w = 0; w < a.words; ++w) {
-                    uint32_t bits = mrow[w];
-                    while (bits) {
-                        const int bit = __builtin_ctz(bits);
-                        bits &= bits - 1;
-                        const int J = w * 32 + bit;
-                        int oy = y - a.start[3 * J + 1];
-                        if (oy < 0) oy += ny;
-                        int oz = z - a.start[3 * J + 2];
-                        if (oz < 0) oz += nz;
-                        if (oy >= a.side[1] || oz >= a.side[2]) continue;
-                        const C cj = a.cnl[(int64_t)J * a.n_orb + A];
-                        const T* pb = a.pbox + ((int64_t)J * a.side[2] + oz) * a.side[1] * a.side[0] +
-                                      (int64_t)oy * a.side[0];
-                        const int sx = a.start[3 * J];
-#pragma unroll
-                        for (int p = 0; p < PX; ++p) {
-                            int ox = x0 + p - sx;
-                            if (ox < 0) ox += nx;
-                            if (ox < a.side[0]) {
-                                const T w8 = pb[ox];
-                                nl[p].x += w8 * cj.x;
-                                nl[p].y += w8 * cj.y;
-                            }
-                        }
-                    }
-                }
-            }
+            for (int i = 0; i < HJ; ++i)
+                if (h_ok[i]) load_run<T, PX>(u + zo + h_off[i], hq[D][i]);
+            if constexpr (HORNER) load_run<T, PX>(p0 + zo + rowoff, pq[D]);
+            if constexpr (NEEDV) load_real<T, PX>(v + zo + rowoff, vq[D]);
         }
+        const C* tile = tiles + buf * tile_elems;
 
         C res[PX];
-        const C* trow = tile + (ty + 4) * nx;
-        // x-neighbours of the thread's run: one window of PX+8 points
-        C wnd[PX + 8];
-#pragma unroll
-        for (int i = 0; i < PX + 8; ++i) wnd[i] = trow[wrap1(x0 - 4 + i, nx)];
 #pragma unroll
         for (int p = 0; p < PX; ++p) {
-            const int xx = x0 + p;
             const C ctr = q[4][p];
             T sre = c0 * ctr.x, sim = c0 * ctr.y;
 #pragma unroll
             for (int m = 1; m <= 4; ++m) {
-                const C xp = wnd[4 + p + m];
-                const C xm = wnd[4 + p - m];
-                const C yp = trow[m * nx + xx];
-                const C ym = trow[-m * nx + xx];
+                const C xp = tile[xo[4 + p + m]];
+                const C xm = tile[xo[4 + p - m]];
+                const C yp = tile[yo + p + m * nx];
+                const C ym = tile[yo + p - m * nx];
                 const C zp = q[4 + m][p];
                 const C zm = q[4 - m][p];
                 sre += cm[m - 1] * (((xp.x + xm.x) + (yp.x + ym.x)) + (zp.x + zm.x));
@@ -174,15 +199,13 @@ __global__ void __launch_bounds__(1024) stencil_kernel(StencilArgs<T> a) {
             if constexpr (MODE == MODE_EXPECT_T) {
                 acc += (double)ctr.x * (double)tre + (double)ctr.y * (double)tim;
             } else {
-                const T vv = a.v[z * plane + rowoff + p];
-                const T hre = tre + vv * ctr.x + nl[p].x;
-                const T him = tim + vv * ctr.y + nl[p].y;
+                const T vv = vq[0][p];
+                const T hre = tre + vv * ctr.x;
+                const T him = tim + vv * ctr.y;
                 if constexpr (MODE == MODE_APPLY) {
                     res[p] = C{hre, him};
                 } else {
-                    C base;
-                    if constexpr (MODE == MODE_HORNER_FIRST) base = ctr;
-                    else base = p0[z * plane + rowoff + p];
+                    const C base = HORNER ? pq[0][p] : ctr;
                     res[p] = C{base.x - a.alpha * him, base.y + a.alpha * hre};
                 }
                 if constexpr (NORM)
@@ -191,10 +214,28 @@ __global__ void __launch_bounds__(1024) stencil_kernel(StencilArgs<T> a) {
         }
         if constexpr (MODE != MODE_EXPECT_T) store_run<T, PX>(out + z * plane + rowoff, res);
 
+        if (z + 1 < z1) {
+            C* nt = tiles + (buf ^ 1) * tile_elems;
+            store_run<T, PX>(nt + yo, q[5]);
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
+            for (int i = 0; i < HJ; ++i)
+                if (h_ok[i]) store_run<T, PX>(nt + h_lds[i], hq[1][i]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 8 + D; ++k)
 #pragma unroll
             for (int p = 0; p < PX; ++p) q[k][p] = q[k + 1][p];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+#pragma unroll
+            for (int p = 0; p < PX; ++p) {
+#pragma unroll
+                for (int i = 0; i < HJ; ++i) hq[d][i][p] = hq[d + 1][i][p];
+                if constexpr (HORNER) pq[d][p] = pq[d + 1][p];
+                if constexpr (NEEDV) vq[d][p] = vq[d + 1][p];
+            }
+        }
     }
 
     if constexpr (NORM || MODE == MODE_EXPECT_T) {
@@ -206,7 +247,7 @@ __global__ void __launch_bounds__(1024) stencil_kernel(StencilArgs<T> a) {
             double s = 0.0;
             const int nw = (blockDim.x + 63) >> 6;
             for (int i = 0; i < nw; ++i) s += red[i];
-            a.partial[(int64_t)A * (a.nyt * a.nzc) + zc * a.nyt + ytile] = s;
+            partial[(int64_t)A * (a.nyt * a.nzc) + zc * a.nyt + ytile] = s;
         }
     }
 }
@@ -216,21 +257,21 @@ static hipError_t launch_ty(const StencilArgs<T>& a, int mode, bool norm, hipStr
     const int nxt = a.nx / PX;
     dim3 block(nxt * TY);
     dim3 grid((unsigned)((int64_t)a.n_orb * a.nyt * a.nzc));
-    const size_t lds = (size_t)(TY + 8) * a.nx * sizeof(cx_t<T>);
+    const size_t lds = 2 * (size_t)(TY + 8) * a.nx * sizeof(cx_t<T>);
     switch (mode) {
     case MODE_APPLY:
-        stencil_kernel<T, PX, TY, MODE_APPLY, false><<<grid, block, lds, s>>>(a);
+        stencil_kernel<T, PX, TY, MODE_APPLY, false><<<grid, block, lds, s>>>(a.u, a.psi0, a.out, a.v, a.partial, a);
         break;
     case MODE_HORNER:
-        if (norm) stencil_kernel<T, PX, TY, MODE_HORNER, true><<<grid, block, lds, s>>>(a);
-        else stencil_kernel<T, PX, TY, MODE_HORNER, false><<<grid, block, lds, s>>>(a);
+        if (norm) stencil_kernel<T, PX, TY, MODE_HORNER, true><<<grid, block, lds, s>>>(a.u, a.psi0, a.out, a.v, a.partial, a);
+        else stencil_kernel<T, PX, TY, MODE_HORNER, false><<<grid, block, lds, s>>>(a.u, a.psi0, a.out, a.v, a.partial, a);
         break;
     case MODE_HORNER_FIRST:
-        if (norm) stencil_kernel<T, PX, TY, MODE_HORNER_FIRST, true><<<grid, block, lds, s>>>(a);
-        else stencil_kernel<T, PX, TY, MODE_HORNER_FIRST, false><<<grid, block, lds, s>>>(a);
+        if (norm) stencil_kernel<T, PX, TY, MODE_HORNER_FIRST, true><<<grid, block, lds, s>>>(a.u, a.psi0, a.out, a.v, a.partial, a);
+        else stencil_kernel<T, PX, TY, MODE_HORNER_FIRST, false><<<grid, block, lds, s>>>(a.u, a.psi0, a.out, a.v, a.partial, a);
         break;
     case MODE_EXPECT_T:
-        stencil_kernel<T, PX, TY, MODE_EXPECT_T, false><<<grid, block, lds, s>>>(a);
+        stencil_kernel<T, PX, TY, MODE_EXPECT_T, false><<<grid, block, lds, s>>>(a.u, a.psi0, a.out, a.v, a.partial, a);
         break;
     default:
         return hipErrorInvalidValue;
@@ -251,14 +292,17 @@ static hipError_t launch_px(const StencilArgs<T>& a, int mode, bool norm, int ty
 }
 
 template <typename T>
-hipError_t launch_stencil(const StencilArgs<T>& a, int mode, bool want_norm, int ty,
+hipError_t launch_stencil(const StencilArgs<T>& a, int mode, bool want_norm, int ty, int px,
                           hipStream_t s) {
-    constexpr int PXW = sizeof(T) == 4 ? 2 : 1;
-    if (a.nx % PXW == 0) return launch_px<T, PXW>(a, mode, want_norm, ty, s);
-    return launch_px<T, 1>(a, mode, want_norm, ty, s);
+    if (a.nx % px) return hipErrorInvalidValue;
+    switch (px) {
+    case 1: return launch_px<T, 1>(a, mode, want_norm, ty, s);
+    case 2: return launch_px<T, 2>(a, mode, want_norm, ty, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
-template hipError_t launch_stencil<double>(const StencilArgs<double>&, int, bool, int, hipStream_t);
-template hipError_t launch_stencil<float>(const StencilArgs<float>&, int, bool, int, hipStream_t);
+template hipError_t launch_stencil<double>(const StencilArgs<double>&, int, bool, int, int, hipStream_t);
+template hipError_t launch_stencil<float>(const StencilArgs<float>&, int, bool, int, int, hipStream_t);
 
 }  // namespace me

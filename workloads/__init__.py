@@ -140,6 +140,8 @@ def ion_positions(cfg: Config, rng: Optional[np.random.Generator] = None) -> np.
     if rng is None:
         rng = rngs(cfg)[0]
     L = cfg.L
+    if cfg.n_ions == 0:
+        return np.zeros((0, 3))
     if cfg.placement == "pair":
         base = np.array([[0.25, 0.5, 0.5], [0.75, 0.5, 0.5]]) * L
         base = base[: cfg.n_ions]
