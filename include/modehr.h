@@ -95,7 +95,7 @@ typedef struct {
     int32_t taylor_order;  /* order of the Taylor exponential (1..8; 4 in the method) */
     int32_t precision;     /* me_precision */
     int32_t freeze_ions;   /* nonzero: ions do not move (forces still computed) */
-    int32_t reserved;      /* must be 0 */
+    int32_t enable_adjoint;/* nonzero: reserve the adjoint buffers (requires freeze_ions) */
 } me_params;
 
 /* Diagnostics of the current state.  Energies in hartree. */
@@ -182,6 +182,43 @@ me_status me_get_potential(me_system* sys, int32_t which, double* v_dev);
 /* Add a static local potential dv_dev[N] (FP64, device; copied) to V_loc, or
  * clear it with NULL.  Takes effect for the next me_set_state. */
 me_status me_set_static_potential(me_system* sys, const double* dv_dev);
+
+/* ---------------------------------------------------------------- adjoint
+ * Discrete adjoint of an AETRS trajectory with frozen ions (an extension; the
+ * paper gives no gradient method).  The controls are a per-step uniform-field
+ * amplitude eps_n, entering v_eff as eps_n (x - L/2) in both exponentials of
+ * step n, and a static local potential dV; the objective J depends on the
+ * final density (by default the dipole J = h^3 sum (x - L/2) rho(T)).
+ * Reverse mode: me_adjoint_begin at the final time, then for n = N-1 .. 0
+ * load the state at the start of step n (me_load_checkpoint, from the
+ * caller's checkpoints and recomputation) and call me_adjoint_step.  Each
+ * call recomputes step n keeping its Horner stages, reverses them
+ * (ubar_k = conj(c_k) H ubar_{k-1}, H Hermitian) together with the density
+ * and the Hartree-exchange potential (including the extrapolated history),
+ * and accumulates dJ/d(dV).  Requires enable_adjoint (and freeze_ions). */
+
+/* Bytes of one checkpoint: orbitals, v_Hxc history, ions, step counter. */
+me_status me_checkpoint_size(const me_system* sys, size_t* bytes);
+/* Copy the current state into buf_dev (device, me_checkpoint_size bytes). */
+me_status me_save_checkpoint(me_system* sys, void* buf_dev);
+/* Make the state saved in buf_dev current (rebuilds V_loc and the projector
+ * tables at its positions; synchronises).  ME_EINVAL if it belongs to a
+ * system of another shape. */
+me_status me_load_checkpoint(me_system* sys, const void* buf_dev);
+/* Static potential from an m^3 periodic coarse grid (device, FP64) by
+ * trilinear interpolation (n divisible by m), or cleared with NULL. */
+me_status me_set_static_potential_coarse(me_system* sys, const double* coarse_dev, int32_t m);
+/* d_host[0] = h^3 sum (x - L/2) rho of the current density (synchronises). */
+me_status me_dipole(me_system* sys, double* d_host);
+/* Start a reverse sweep at the final time with rhobar_dev = dJ/drho(T)
+ * (device [N] FP64), or NULL for the dipole objective. */
+me_status me_adjoint_begin(me_system* sys, const double* rhobar_dev);
+/* Reverse the step whose starting state is current; ctrl_n: its field
+ * amplitude; g_ctrl_n (host) receives dJ/d eps_n (synchronises). */
+me_status me_adjoint_step(me_system* sys, double ctrl_n, double* g_ctrl_n);
+/* dJ/d(dV) accumulated so far: on the grid (g_fine_dev [N]) and/or by the
+ * transpose of the trilinear interpolation on an m^3 grid (g_coarse_dev). */
+me_status me_adjoint_grad_v(me_system* sys, double* g_fine_dev, double* g_coarse_dev, int32_t m);
 
 /* Per-kernel timing.  me_timing_enable(sys, 1) brackets every launch of the
  * Horner-stage stencil kernel with HIP events on the handle's stream;

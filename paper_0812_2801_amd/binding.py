@@ -25,6 +25,9 @@ SYMBOLS = [
     "me_get_state", "me_apply_H", "me_propagate_step", "me_report", "me_density",
     "me_forces", "me_get_ions", "me_get_potential", "me_set_static_potential",
     "me_timing_enable", "me_timing_read", "me_last_error", "me_strerror",
+    "me_checkpoint_size", "me_save_checkpoint", "me_load_checkpoint",
+    "me_set_static_potential_coarse", "me_dipole", "me_adjoint_begin", "me_adjoint_step",
+    "me_adjoint_grad_v",
 ]
 
 
@@ -36,7 +39,7 @@ class Params(ctypes.Structure):
         ("loc_a", c_double), ("kb_sigma", c_double), ("kb_rcut", c_double),
         ("kb_energy", c_double), ("n_orb", c_int32), ("occ", c_double),
         ("mu", c_double), ("dt", c_double), ("taylor_order", c_int32),
-        ("precision", c_int32), ("freeze_ions", c_int32), ("reserved", c_int32),
+        ("precision", c_int32), ("freeze_ions", c_int32), ("enable_adjoint", c_int32),
     ]
 
 
@@ -88,6 +91,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.me_set_static_potential.argtypes = [c_void_p, c_void_p]
     lib.me_timing_enable.argtypes = [c_void_p, c_int32]
     lib.me_timing_read.argtypes = [c_void_p, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]
+    lib.me_checkpoint_size.argtypes = [c_void_p, POINTER(c_size_t)]
+    lib.me_save_checkpoint.argtypes = [c_void_p, c_void_p]
+    lib.me_load_checkpoint.argtypes = [c_void_p, c_void_p]
+    lib.me_set_static_potential_coarse.argtypes = [c_void_p, c_void_p, c_int32]
+    lib.me_dipole.argtypes = [c_void_p, POINTER(c_double)]
+    lib.me_adjoint_begin.argtypes = [c_void_p, c_void_p]
+    lib.me_adjoint_step.argtypes = [c_void_p, c_double, POINTER(c_double)]
+    lib.me_adjoint_grad_v.argtypes = [c_void_p, c_void_p, c_void_p, c_int32]
     for s in SYMBOLS:
         if s not in ("me_last_error", "me_strerror"):
             getattr(lib, s).restype = c_int32
@@ -101,7 +112,7 @@ def _dptr(a: np.ndarray):
 
 def make_params(*, n, h, pos, mass, zval, n_orb, mu, dt, vel=None, loc_a=0.5,
                 kb_sigma=0.4, kb_rcut=1.2, kb_energy=2.0, occ=2.0, taylor_order=4,
-                precision="f64", freeze_ions=False):
+                precision="f64", freeze_ions=False, enable_adjoint=False):
     """Params plus the host arrays it points to (keep both alive)."""
     pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
     mass = np.ascontiguousarray(mass, dtype=np.float64).ravel()
@@ -125,7 +136,7 @@ def make_params(*, n, h, pos, mass, zval, n_orb, mu, dt, vel=None, loc_a=0.5,
     p.taylor_order = taylor_order
     p.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     p.freeze_ions = int(bool(freeze_ions))
-    p.reserved = 0
+    p.enable_adjoint = int(bool(enable_adjoint))
     return p, keep
 
 
@@ -261,6 +272,58 @@ class System:
         dv = self.torch.as_tensor(dv, dtype=self.torch.float64).to(self.device).reshape(-1).contiguous()
         self._dv = dv
         self._check(self.lib.me_set_static_potential(self.h, c_void_p(dv.data_ptr())))
+
+    # -------------------------------------------------------------- adjoint
+    def checkpoint_size(self) -> int:
+        out = c_size_t(0)
+        self._check(self.lib.me_checkpoint_size(self.h, ctypes.byref(out)))
+        return out.value
+
+    def new_checkpoint(self):
+        return self.torch.empty(self.checkpoint_size(), dtype=self.torch.uint8, device=self.device)
+
+    def save_checkpoint(self, buf):
+        self._check(self.lib.me_save_checkpoint(self.h, c_void_p(buf.data_ptr())))
+
+    def load_checkpoint(self, buf):
+        self._check(self.lib.me_load_checkpoint(self.h, c_void_p(buf.data_ptr())))
+
+    def set_static_potential_coarse(self, coarse):
+        if coarse is None:
+            self._check(self.lib.me_set_static_potential_coarse(self.h, None, c_int32(1)))
+            return
+        c = self.torch.as_tensor(coarse, dtype=self.torch.float64).to(self.device).contiguous()
+        self._coarse = c
+        self._check(self.lib.me_set_static_potential_coarse(self.h, c_void_p(c.data_ptr()),
+                                                            c_int32(c.shape[0])))
+
+    def dipole(self) -> float:
+        d = c_double(0)
+        self._check(self.lib.me_dipole(self.h, ctypes.byref(d)))
+        return d.value
+
+    def adjoint_begin(self, rhobar=None):
+        ptr = None
+        if rhobar is not None:
+            rhobar = self.torch.as_tensor(rhobar, dtype=self.torch.float64).to(self.device).contiguous()
+            self._rhobar = rhobar
+            ptr = c_void_p(rhobar.data_ptr())
+        self._check(self.lib.me_adjoint_begin(self.h, ptr))
+
+    def adjoint_step(self, ctrl: float) -> float:
+        g = c_double(0)
+        self._check(self.lib.me_adjoint_step(self.h, c_double(ctrl), ctypes.byref(g)))
+        return g.value
+
+    def adjoint_grad_v(self, m: Optional[int] = None):
+        t = self.torch
+        if m is None:
+            out = t.empty(self.N, dtype=t.float64, device=self.device)
+            self._check(self.lib.me_adjoint_grad_v(self.h, c_void_p(out.data_ptr()), None, c_int32(0)))
+        else:
+            out = t.empty((m, m, m), dtype=t.float64, device=self.device)
+            self._check(self.lib.me_adjoint_grad_v(self.h, None, c_void_p(out.data_ptr()), c_int32(m)))
+        return out
 
     def timing_enable(self, on: bool = True):
         self._check(self.lib.me_timing_enable(self.h, c_int32(1 if on else 0)))

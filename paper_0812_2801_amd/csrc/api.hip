@@ -18,6 +18,7 @@
 #include "../../include/modehr.h"
 #include "common.hpp"
 #include "fields.hpp"
+#include "adjoint.hpp"
 
 using namespace me;
 
@@ -90,6 +91,8 @@ struct Geometry {
     int64_t nblk256;  // 256-point blocks of the grid
     size_t fft_work;
     int ewald_ng;
+    bool adjoint;
+    int taylor;
 };
 
 int env_int(const char* name, int dflt) {
@@ -151,7 +154,7 @@ me_status validate(const me_params* p, std::string& err) {
     if (!(p->mu > 0) || !std::isfinite(p->dt) || p->dt == 0.0) { err = "mu must be positive and dt nonzero"; return ME_EINVAL; }
     if (p->taylor_order < 1 || p->taylor_order > MAX_TAYLOR) { err = "taylor_order must be in [1, 8]"; return ME_EINVAL; }
     if (p->precision < ME_F64 || p->precision > ME_F32_BF16X3) { err = "unknown precision"; return ME_EINVAL; }
-    if (p->reserved != 0) { err = "reserved must be 0"; return ME_EINVAL; }
+    if (p->enable_adjoint && !p->freeze_ions) { err = "the adjoint needs frozen ions"; return ME_EUNSUPPORTED; }
     const bool f64 = p->precision == ME_F64;
     const int px = choose_px(p->n[0], f64);
     if (choose_ty(p->n[0], p->n[1], px, f64 ? 16 : 8) < 0) { err = "grid x extent too large for one workgroup row"; return ME_EUNSUPPORTED; }
@@ -186,6 +189,8 @@ Geometry make_geometry(const me_params* p) {
     g.floc_chunks = local_force_chunks(g.N);
     g.nblk256 = (g.N + 255) / 256;
     g.fft_work = (size_t)(2 * g.nhalf) * 16;
+    g.adjoint = p->enable_adjoint != 0;
+    g.taylor = p->taylor_order;
     return g;
 }
 
@@ -204,7 +209,12 @@ struct Layout {
     int32_t* tcount[2];
     double *fnl, *enl_part, *floc_part, *fion, *eion_part, *erec_part;
     double *ewald_gv, *ewald_wv;
-    double *norm_part, *fix_part, *kin_part, *hxc_part, *loc_part, *rep;
+    double *norm_part, *fix_part, *kin_part, *hxc_part, *loc_part, *rep, *scal0;
+    // adjoint (frozen ions): forward intermediates of both exponentials, the
+    // half-step and next orbitals, adjoint orbitals, and FP64 grid buffers
+    void* inter[2][MAX_TAYLOR];
+    void *psi_half, *psi_next, *lamA, *lamB, *ubA, *ubB;
+    double *vbar[4], *wbar1, *wbar2, *gfine, *rhobar_T, *rhobar, *hv, *dpart, *scal;
     size_t total;
 };
 
@@ -264,6 +274,26 @@ static Layout carve(const Geometry& g, char* base) {
     L.hxc_part = c.take<double>((size_t)g.nblk256 * 3 * 8);
     L.loc_part = c.take<double>((size_t)g.nblk256 * 8);
     L.rep = c.take<double>(SLOT_COUNT * 8);
+    L.scal0 = c.take<double>(64);
+    if (g.adjoint) {
+        for (int e = 0; e < 2; ++e)
+            for (int k = 0; k < g.taylor - 1; ++k) L.inter[e][k] = c.take<void>(orb);
+        L.psi_half = c.take<void>(orb);
+        L.psi_next = c.take<void>(orb);
+        L.lamA = c.take<void>(orb);
+        L.lamB = c.take<void>(orb);
+        L.ubA = c.take<void>(orb);
+        L.ubB = c.take<void>(orb);
+        for (int i = 0; i < 4; ++i) L.vbar[i] = c.take<double>(g.N * 8);
+        L.wbar1 = c.take<double>(g.N * 8);
+        L.wbar2 = c.take<double>(g.N * 8);
+        L.gfine = c.take<double>(g.N * 8);
+        L.rhobar_T = c.take<double>(g.N * 8);
+        L.rhobar = c.take<double>(g.N * 8);
+        L.hv = c.take<double>(g.N * 8);
+        L.dpart = c.take<double>((size_t)g.nblk256 * 8);
+        L.scal = c.take<double>(64);
+    }
     L.total = c.off;
     return L;
 }
@@ -291,6 +321,9 @@ struct me_system {
     std::vector<double> ev_bytes;
     std::vector<hipEvent_t> ev_pool;
     double rep_host[SLOT_COUNT];
+    // adjoint bookkeeping
+    bool adj_ready = false;
+    bool adj_pending_final = false;
 };
 
 namespace {
@@ -447,6 +480,22 @@ StencilArgs<T> base_args(me_system* sys, const T* v, int n_orb) {
     return a;
 }
 
+// c_JA of the orbitals u (E_KB h^3 included) into w.cnl, by the precision's
+// contraction: plain FP64 / FP32, or split-bf16 MFMA
+template <typename T>
+me_status gather(me_system* sys, const cx_t<T>* u, int64_t stride, int n_orb, int t, double ekb_h3) {
+    if constexpr (sizeof(T) == 4) {
+        if (sys->prm.precision == ME_F32_BF16X3) {
+            HIPCHK(launch_kb_gather_bf16x3(u, stride, n_orb, sys->g.n_ions, tables(sys, t), ekb_h3,
+                                           (float2*)sys->w.cnl, sys->stream));
+            return ME_OK;
+        }
+    }
+    HIPCHK(launch_kb_gather<T>(u, stride, n_orb, sys->g.n_ions, tables(sys, t), ekb_h3, (cx_t<T>*)sys->w.cnl,
+                               sys->stream));
+    return ME_OK;
+}
+
 // One Taylor exponential psi <- T_K(tau, H) psi, Horner form:
 // u_K = psi, u_{k-1} = psi + (-i tau/k) H u_k, result u_0 written over psi.
 template <typename T>
@@ -464,8 +513,7 @@ me_status exponential(me_system* sys, const T* veff, int t, bool last) {
         // the last stage overwrites psi in place (each point reads its own
         // psi0 only), except for K = 1 where it also reads psi's neighbours
         C* out = (k == 1 && K > 1) ? psi : bufs[nb];
-        HIPCHK(launch_kb_gather<T>(u, g.stride, g.n_orb, g.n_ions, tables(sys, t), ekb_h3, (C*)sys->w.cnl,
-                                   sys->stream));
+        CHK(gather<T>(sys, u, g.stride, g.n_orb, t, ekb_h3));
         StencilArgs<T> a = base_args<T>(sys, veff, g.n_orb);
         a.u = u;
         a.psi0 = psi;
@@ -600,6 +648,139 @@ me_status read_report(me_system* sys, me_step_report* rep) {
         return ME_EUNSTABLE;
     }
     return ME_OK;
+}
+
+// Forward exponential keeping every Horner stage: inter[j-1] = u_j for
+// j = 1..K-1 (u_K = psi_in), result u_0 in out (psi_in untouched).
+template <typename T>
+me_status exponential_store(me_system* sys, const T* veff, int t, const cx_t<T>* psi_in, void* const* inter,
+                            cx_t<T>* out) {
+    using C = cx_t<T>;
+    const Geometry& g = sys->g;
+    const double tau = sys->prm.dt / (2.0 * sys->prm.mu);
+    const int K = sys->prm.taylor_order;
+    const double ekb_h3 = sys->prm.kb_energy * sys->prm.h * sys->prm.h * sys->prm.h;
+    const C* u = psi_in;
+    for (int k = K; k >= 1; --k) {
+        C* o = k == 1 ? out : (C*)inter[k - 2];
+        CHK(gather<T>(sys, u, g.stride, g.n_orb, t, ekb_h3));
+        StencilArgs<T> a = base_args<T>(sys, veff, g.n_orb);
+        a.u = u;
+        a.psi0 = psi_in;
+        a.out = o;
+        a.alpha = (T)(-tau / k);
+        HIPCHK(launch_stencil<T>(a, k == K ? MODE_HORNER_FIRST : MODE_HORNER, false, g.ty, g.px, sys->stream));
+        if (g.n_ions > 0)
+            HIPCHK(launch_kb_fixup<T>(o, g.stride, g.n_orb, tables(sys, t), (const C*)sys->w.cnl, 0.0, -tau / k,
+                                      nullptr, sys->stream));
+        u = o;
+    }
+    return ME_OK;
+}
+
+// Reverse of one exponential: lam_out = psi_in-bar given lam_in = output-bar,
+// wbar += dJ/dv_eff of this exponential.
+template <typename T>
+me_status reverse_exponential(me_system* sys, const T* veff, int t, const cx_t<T>* psi_in, void* const* inter,
+                              const cx_t<T>* lam_in, cx_t<T>* lam_out, double* wbar) {
+    using C = cx_t<T>;
+    const Geometry& g = sys->g;
+    const double tau = sys->prm.dt / (2.0 * sys->prm.mu);
+    const int K = sys->prm.taylor_order;
+    const double ekb_h3 = sys->prm.kb_energy * sys->prm.h * sys->prm.h * sys->prm.h;
+    C* ubs[2] = {(C*)sys->w.ubA, (C*)sys->w.ubB};
+    const C* ub = lam_in;
+    for (int k = 1; k <= K; ++k) {
+        const C* uk = k == K ? psi_in : (const C*)inter[k - 1];
+        HIPCHK(launch_cross_accum<T>(ub, uk, lam_out, g.stride, g.n_orb, g.N, -tau / k, k == 1, wbar, sys->stream));
+        // ubar_k = conj(c_k) H ubar_{k-1} = (i tau/k) H ubar_{k-1}
+        C* nb = ubs[k & 1];
+        CHK(gather<T>(sys, ub, g.stride, g.n_orb, t, ekb_h3));
+        StencilArgs<T> a = base_args<T>(sys, veff, g.n_orb);
+        a.u = ub;
+        a.psi0 = ub;
+        a.out = nb;
+        a.alpha = (T)(tau / k);
+        HIPCHK(launch_stencil<T>(a, MODE_SCALED, false, g.ty, g.px, sys->stream));
+        if (g.n_ions > 0)
+            HIPCHK(launch_kb_fixup<T>(nb, g.stride, g.n_orb, tables(sys, t), (const C*)sys->w.cnl, 0.0, tau / k,
+                                      nullptr, sys->stream));
+        ub = nb;
+    }
+    HIPCHK(launch_accum<T>(ub, lam_out, g.stride, g.n_orb, g.N, sys->stream));
+    return ME_OK;
+}
+
+// rhobar = Hartree(vbar) + f_x(rho) vbar (+ extra): the adjoint of v_Hxc[rho]
+me_status vhxc_adjoint(me_system* sys, const double* vbar, const double* rho, const double* extra) {
+    const Geometry& g = sys->g;
+    const double L[3] = {g.nx * sys->prm.h, g.ny * sys->prm.h, g.nz * sys->prm.h};
+    HIPCHK(hipMemcpyAsync(sys->w.hv, vbar, g.N * 8, hipMemcpyDeviceToDevice, sys->stream));
+    CHK(fft_r2c(sys, sys->w.hv, sys->w.rhok));
+    HIPCHK(launch_hartree_spectrum(sys->w.rhok, g.nx, g.ny, g.nz, L, sys->w.spec, sys->stream));
+    CHK(fft_c2r(sys, sys->w.spec, sys->w.hv));
+    HIPCHK(launch_vhxc_adjoint(sys->w.hv, vbar, rho, extra, g.N, sys->w.rhobar, sys->stream));
+    return ME_OK;
+}
+
+// Reverse of one frozen-ion step n (state at the start of the step loaded).
+template <typename T>
+me_status adjoint_step_impl(me_system* sys, double eps, double* g_eps) {
+    using C = cx_t<T>;
+    const Geometry& g = sys->g;
+    const int64_t n = sys->step;
+    const int t = sys->tab_cur;
+    // effective potentials of both exponentials (frozen ions: V_loc is the same)
+    HIPCHK(hipMemcpyAsync(sys->w.vloc_next, sys->w.vloc_cur, g.N * 8, hipMemcpyDeviceToDevice, sys->stream));
+    CHK(make_veff(sys, eps, true));
+    const T* w1 = (const T*)sys->w.veff0;
+    const T* w2 = (const T*)sys->w.veff1;
+    // forward recompute with every stage kept
+    CHK(exponential_store<T>(sys, w1, t, (const C*)sys->w.psi, sys->w.inter[0], (C*)sys->w.psi_half));
+    CHK(exponential_store<T>(sys, w2, t, (const C*)sys->w.psi_half, sys->w.inter[1], (C*)sys->w.psi_next));
+    HIPCHK(launch_density<T>((const C*)sys->w.psi_next, g.stride, g.n_orb, g.N, sys->prm.occ, sys->w.rho,
+                             sys->stream));
+    // rho(n+1)-bar from v_Hxc(n+1)-bar (and the objective at the final time)
+    double* vb_next = sys->w.vbar[(n + 1) & 3];
+    CHK(vhxc_adjoint(sys, vb_next, sys->w.rho, sys->adj_pending_final ? sys->w.rhobar_T : nullptr));
+    sys->adj_pending_final = false;
+    HIPCHK(launch_lambda_update<T>((C*)sys->w.lamA, (const C*)sys->w.psi_next, sys->w.rhobar, g.stride, g.n_orb,
+                                   g.N, sys->prm.occ, sys->stream));
+    HIPCHK(launch_zero(vb_next, g.N, sys->stream));
+    // reverse the second then the first exponential
+    HIPCHK(launch_zero(sys->w.wbar1, g.N, sys->stream));
+    HIPCHK(launch_zero(sys->w.wbar2, g.N, sys->stream));
+    CHK(reverse_exponential<T>(sys, w2, t, (const C*)sys->w.psi_half, sys->w.inter[1], (const C*)sys->w.lamA,
+                               (C*)sys->w.lamB, sys->w.wbar2));
+    CHK(reverse_exponential<T>(sys, w1, t, (const C*)sys->w.psi, sys->w.inter[0], (const C*)sys->w.lamB,
+                               (C*)sys->w.lamA, sys->w.wbar1));
+    // the first exponential used v_n, the second the extrapolation of v_n, v_{n-1}, v_{n-2}
+    HIPCHK(launch_axpy(sys->w.vbar[n & 3], sys->w.wbar1, 1.0, g.N, sys->stream));
+    const int lv = sys->hist_count;
+    const double a3[3] = {3.0, -3.0, 1.0}, a2[2] = {2.0, -1.0}, a1[1] = {1.0};
+    const double* ac = lv >= 3 ? a3 : (lv == 2 ? a2 : a1);
+    for (int j = 0; j < std::min(lv, 3); ++j)
+        HIPCHK(launch_axpy(sys->w.vbar[(n - j + 4) & 3], sys->w.wbar2, ac[j], g.N, sys->stream));
+    // both exponentials see eps (x - L/2) and the static potential
+    HIPCHK(launch_axpy(sys->w.wbar2, sys->w.wbar1, 1.0, g.N, sys->stream));
+    HIPCHK(launch_axpy(sys->w.gfine, sys->w.wbar2, 1.0, g.N, sys->stream));
+    HIPCHK(launch_field_dot(sys->w.wbar2, g.nx, g.N, sys->prm.h, Lx(sys), sys->w.dpart, sys->w.scal, 1.0,
+                            sys->stream));
+    HIPCHK(hipMemcpyAsync(g_eps, sys->w.scal, 8, hipMemcpyDeviceToHost, sys->stream));
+    HIPCHK(hipStreamSynchronize(sys->stream));
+    return ME_OK;
+}
+
+struct CkptHeader {
+    int64_t step;
+    int32_t hist_count, hist_newest, n_orb, n_ions;
+    int64_t N;
+    int64_t magic;
+};
+
+size_t ckpt_bytes(const Geometry& g) {
+    return 256 + align_up((size_t)g.n_orb * g.stride * g.bc) + align_up(3 * (size_t)g.N * 8) +
+           align_up(9 * (size_t)std::max(1, g.n_ions) * 8);
 }
 
 me_status initial_fields(me_system* sys) {
@@ -888,8 +1069,7 @@ me_status me_apply_H(me_system* sys, const void* psi_in_dev, void* hpsi_out_dev,
         } else {
             const float2* in = (const float2*)psi_in_dev + (size_t)o0 * orb_stride;
             float2* outp = (float2*)hpsi_out_dev + (size_t)o0 * orb_stride;
-            HIPCHK(launch_kb_gather<float>(in, orb_stride, nb, g.n_ions, tables(sys, sys->tab_cur), ekb_h3,
-                                           (float2*)sys->w.cnl, sys->stream));
+            CHK(gather<float>(sys, in, orb_stride, nb, sys->tab_cur, ekb_h3));
             StencilArgs<float> a = base_args<float>(sys, (const float*)sys->w.veff0, nb);
             a.u = in; a.psi0 = in; a.out = outp; a.stride = orb_stride;
             a.zchunk = g.nz; a.nzc = 1;
@@ -1011,6 +1191,139 @@ me_status me_timing_read(me_system* sys, int64_t* launches, double* total_ms, do
     *launches = (int64_t)sys->ev.size();
     *total_ms = ms;
     *total_bytes = by;
+    return ME_OK;
+}
+
+me_status me_checkpoint_size(const me_system* sys, size_t* bytes) {
+    if (!sys || !bytes) return ME_EINVAL;
+    *bytes = ckpt_bytes(sys->g);
+    return ME_OK;
+}
+
+me_status me_save_checkpoint(me_system* sys, void* buf_dev) {
+    if (!sys || !buf_dev) return ME_EINVAL;
+    if (!sys->has_state) { sys->err = "no state"; return ME_ESTATE; }
+    const Geometry& g = sys->g;
+    char* b = (char*)buf_dev;
+    CkptHeader hd{sys->step, sys->hist_count, sys->hist_newest, g.n_orb, g.n_ions, g.N, 0x4d4f444548524331LL};
+    HIPCHK(hipMemcpyAsync(b, &hd, sizeof(hd), hipMemcpyHostToDevice, sys->stream));
+    size_t off = 256;
+    const size_t ob = (size_t)g.n_orb * g.stride * g.bc;
+    HIPCHK(hipMemcpyAsync(b + off, sys->w.psi, ob, hipMemcpyDeviceToDevice, sys->stream));
+    off += align_up(ob);
+    for (int i = 0; i < 3; ++i)
+        HIPCHK(hipMemcpyAsync(b + off + (size_t)i * g.N * 8, sys->w.hist[i], g.N * 8, hipMemcpyDeviceToDevice,
+                              sys->stream));
+    off += align_up(3 * (size_t)g.N * 8);
+    const size_t i3 = 3 * (size_t)std::max(1, g.n_ions) * 8;
+    HIPCHK(hipMemcpyAsync(b + off, sys->w.pos, i3, hipMemcpyDeviceToDevice, sys->stream));
+    HIPCHK(hipMemcpyAsync(b + off + i3, sys->w.vel, i3, hipMemcpyDeviceToDevice, sys->stream));
+    HIPCHK(hipMemcpyAsync(b + off + 2 * i3, sys->w.frc, i3, hipMemcpyDeviceToDevice, sys->stream));
+    HIPCHK(hipStreamSynchronize(sys->stream));   // the header lives on the host stack
+    return ME_OK;
+}
+
+me_status me_load_checkpoint(me_system* sys, const void* buf_dev) {
+    if (!sys || !buf_dev) return ME_EINVAL;
+    const Geometry& g = sys->g;
+    const char* b = (const char*)buf_dev;
+    CkptHeader hd{};
+    HIPCHK(hipMemcpyAsync(&hd, b, sizeof(hd), hipMemcpyDeviceToHost, sys->stream));
+    HIPCHK(hipStreamSynchronize(sys->stream));
+    if (hd.magic != 0x4d4f444548524331LL || hd.n_orb != g.n_orb || hd.n_ions != g.n_ions || hd.N != g.N) {
+        sys->err = "checkpoint does not belong to a system of this shape";
+        return ME_EINVAL;
+    }
+    size_t off = 256;
+    const size_t ob = (size_t)g.n_orb * g.stride * g.bc;
+    HIPCHK(hipMemcpyAsync(sys->w.psi, b + off, ob, hipMemcpyDeviceToDevice, sys->stream));
+    off += align_up(ob);
+    for (int i = 0; i < 3; ++i)
+        HIPCHK(hipMemcpyAsync(sys->w.hist[i], b + off + (size_t)i * g.N * 8, g.N * 8, hipMemcpyDeviceToDevice,
+                              sys->stream));
+    off += align_up(3 * (size_t)g.N * 8);
+    const size_t i3 = 3 * (size_t)std::max(1, g.n_ions) * 8;
+    HIPCHK(hipMemcpyAsync(sys->w.pos, b + off, i3, hipMemcpyDeviceToDevice, sys->stream));
+    HIPCHK(hipMemcpyAsync(sys->w.vel, b + off + i3, i3, hipMemcpyDeviceToDevice, sys->stream));
+    HIPCHK(hipMemcpyAsync(sys->w.frc, b + off + 2 * i3, i3, hipMemcpyDeviceToDevice, sys->stream));
+    sys->step = hd.step;
+    sys->hist_count = hd.hist_count;
+    sys->hist_newest = hd.hist_newest;
+    // ion-dependent fields at the restored positions
+    CHK(build_tables(sys, sys->w.pos, sys->tab_cur));
+    CHK(ion_fields(sys, sys->w.pos, sys->w.vloc_cur));
+    if (sys->g.f64)
+        HIPCHK(launch_density<double>((const double2*)sys->w.psi, g.stride, g.n_orb, g.N, sys->prm.occ, sys->w.rho,
+                                      sys->stream));
+    else
+        HIPCHK(launch_density<float>((const float2*)sys->w.psi, g.stride, g.n_orb, g.N, sys->prm.occ, sys->w.rho,
+                                     sys->stream));
+    HIPCHK(hipMemsetAsync(sys->w.rep, 0, SLOT_COUNT * 8, sys->stream));
+    sys->has_state = true;
+    return ME_OK;
+}
+
+me_status me_set_static_potential_coarse(me_system* sys, const double* coarse_dev, int32_t m) {
+    if (!sys || m < 1 || sys->g.nx % m) return ME_EINVAL;
+    if (!coarse_dev) return me_set_static_potential(sys, nullptr);
+    HIPCHK(launch_coarse_to_fine(coarse_dev, m, sys->g.nx, sys->w.vstatic, sys->stream));
+    sys->static_set = true;
+    return ME_OK;
+}
+
+me_status me_dipole(me_system* sys, double* d_host) {
+    if (!sys || !d_host) return ME_EINVAL;
+    if (!sys->has_state) { sys->err = "no state"; return ME_ESTATE; }
+    const Geometry& g = sys->g;
+    const double h3 = sys->prm.h * sys->prm.h * sys->prm.h;
+    // the E_loc partial buffer is free between steps
+    HIPCHK(launch_field_dot(sys->w.rho, g.nx, g.N, sys->prm.h, Lx(sys), sys->w.loc_part, sys->w.scal0, h3,
+                            sys->stream));
+    HIPCHK(hipMemcpyAsync(d_host, sys->w.scal0, 8, hipMemcpyDeviceToHost, sys->stream));
+    HIPCHK(hipStreamSynchronize(sys->stream));
+    return ME_OK;
+}
+
+me_status me_adjoint_begin(me_system* sys, const double* rhobar_dev) {
+    if (!sys) return ME_EINVAL;
+    if (!sys->g.adjoint) { sys->err = "system created without enable_adjoint"; return ME_EUNSUPPORTED; }
+    const Geometry& g = sys->g;
+    const size_t ob = (size_t)g.n_orb * g.stride * g.bc;
+    HIPCHK(hipMemsetAsync(sys->w.lamA, 0, ob, sys->stream));
+    for (int i = 0; i < 4; ++i) HIPCHK(launch_zero(sys->w.vbar[i], g.N, sys->stream));
+    HIPCHK(launch_zero(sys->w.gfine, g.N, sys->stream));
+    if (rhobar_dev)
+        HIPCHK(hipMemcpyAsync(sys->w.rhobar_T, rhobar_dev, g.N * 8, hipMemcpyDeviceToDevice, sys->stream));
+    else
+        HIPCHK(launch_dipole_rhobar(sys->w.rhobar_T, g.nx, g.N, sys->prm.h, Lx(sys), sys->stream));
+    sys->adj_ready = true;
+    sys->adj_pending_final = true;
+    return ME_OK;
+}
+
+me_status me_adjoint_step(me_system* sys, double ctrl_n, double* g_ctrl_n) {
+    if (!sys || !g_ctrl_n) return ME_EINVAL;
+    if (!sys->g.adjoint || !sys->adj_ready) { sys->err = "call me_adjoint_begin first"; return ME_ESTATE; }
+    if (!sys->has_state) { sys->err = "load the state of the step first"; return ME_ESTATE; }
+    if (!std::isfinite(ctrl_n)) { sys->err = "control amplitude must be finite"; return ME_EINVAL; }
+    try {
+        return sys->g.f64 ? adjoint_step_impl<double>(sys, ctrl_n, g_ctrl_n)
+                          : adjoint_step_impl<float>(sys, ctrl_n, g_ctrl_n);
+    } catch (...) {
+        sys->err = "internal error";
+        return ME_EDEVICE;
+    }
+}
+
+me_status me_adjoint_grad_v(me_system* sys, double* g_fine_dev, double* g_coarse_dev, int32_t m) {
+    if (!sys) return ME_EINVAL;
+    if (!sys->g.adjoint || !sys->adj_ready) { sys->err = "no adjoint run"; return ME_ESTATE; }
+    if (g_fine_dev)
+        HIPCHK(hipMemcpyAsync(g_fine_dev, sys->w.gfine, sys->g.N * 8, hipMemcpyDeviceToDevice, sys->stream));
+    if (g_coarse_dev) {
+        if (m < 1 || sys->g.nx % m) return ME_EINVAL;
+        HIPCHK(launch_fine_to_coarse(sys->w.gfine, m, sys->g.nx, g_coarse_dev, sys->stream));
+    }
     return ME_OK;
 }
 

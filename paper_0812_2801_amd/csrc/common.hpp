@@ -62,7 +62,8 @@ enum StencilMode : int {
     MODE_APPLY = 0,        // out = H u
     MODE_HORNER = 1,       // out = psi0 + i*alpha*(H u)
     MODE_HORNER_FIRST = 2, // as HORNER with psi0 == u
-    MODE_EXPECT_T = 3      // partial[A][tile] = sum Re(conj(u) T u); no output
+    MODE_EXPECT_T = 3,     // partial[A][tile] = sum Re(conj(u) T u); no output
+    MODE_SCALED = 4        // out = i*alpha*(H u)   (adjoint stages)
 };
 
 template <typename T>
@@ -101,6 +102,11 @@ hipError_t launch_kb_fixup(cx_t<T>* out, int64_t stride, int n_orb, KbTables t,
 template <typename T>
 hipError_t launch_kb_gather(const cx_t<T>* u, int64_t stride, int n_orb, int n_ions,
                             KbTables t, double ekb_h3, cx_t<T>* cnl, hipStream_t s);
+
+// the same contraction for FP32 orbitals as split-bf16 (bf16x3) MFMA with
+// FP32 accumulation
+hipError_t launch_kb_gather_bf16x3(const float2* u, int64_t stride, int n_orb, int n_ions, KbTables t,
+                                   double ekb_h3, float2* cnl, hipStream_t s);
 
 // nonlocal forces and energy, FP64 accumulation:
 // fnl[J][3] = -2 f E_KB sum_A Re(conj(c_JA) d_JA); enl_part[J] = f E_KB sum_A |c_JA|^2

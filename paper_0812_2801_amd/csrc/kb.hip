@@ -328,6 +328,84 @@ hipError_t launch_kb_gather(const cx_t<T>* u, int64_t stride, int n_orb, int n_i
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ split-bf16 MFMA contraction
+// The same contraction as a matrix product on the matrix cores:
+// D[16 x 16] += A[16 x 32] B[32 x 16] with v_mfma_f32_16x16x32_bf16, where
+// A rows are 8 orbitals x (re, im) gathered at 32 projector points and B
+// column 0 holds the projector values (the other columns are zero: one
+// s-channel projector per ion leaves most of the tile empty).  Each FP32
+// operand is split into bf16 hi + lo parts and the product is accumulated in
+// FP32 as hi*hi + hi*lo + lo*hi.  Fragment layout of the 16x16x32 bf16
+// instruction: lane l holds A row l%16, k = 8(l/16)..+7; B column l%16 with
+// the same k; D column l%16, rows 4(l/16)..+3.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+    hi = (__bf16)x;
+    lo = (__bf16)(x - (float)hi);
+}
+
+__global__ void __launch_bounds__(256) kb_gather_bf16x3_kernel(const float2* __restrict__ u, int64_t stride,
+                                                               int n_orb, const int32_t* __restrict__ idx,
+                                                               const float* __restrict__ pv,
+                                                               const int32_t* __restrict__ count, int kcap,
+                                                               float scale, float2* __restrict__ cnl) {
+    const int J = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int A0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 8;     // first orbital of this wave
+    if (A0 >= n_orb) return;
+    const int K = count[J];
+    const int32_t* ix = idx + (int64_t)J * kcap;
+    const float* pp = pv + (int64_t)J * kcap;
+    const int m = lane & 15;
+    const int kq = lane >> 4;
+    const int a = A0 + (m >> 1);
+    const bool a_ok = a < n_orb;
+    const float2* ua = u + (int64_t)(a_ok ? a : A0) * stride;
+    f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        bf16x8_t ah, al, bh, bl;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = k0 + 8 * kq + i;
+            float av = 0.f, bv = 0.f;
+            if (k < K) {
+                if (a_ok) {
+                    const float2 z = ua[ix[k]];
+                    av = (m & 1) ? z.y : z.x;
+                }
+                if (m == 0) bv = pp[k];
+            }
+            __bf16 h, l;
+            split_bf16(av, h, l);
+            ah[i] = h;
+            al[i] = l;
+            split_bf16(bv, h, l);
+            bh[i] = h;
+            bl[i] = l;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+    }
+    if (m == 0) {
+        // rows 4kq .. 4kq+3 of column 0: orbitals A0 + 2kq and A0 + 2kq + 1, (re, im) each
+        const int a1 = A0 + 2 * kq;
+        if (a1 < n_orb) cnl[(int64_t)J * n_orb + a1] = make_float2(scale * acc[0], scale * acc[1]);
+        if (a1 + 1 < n_orb) cnl[(int64_t)J * n_orb + a1 + 1] = make_float2(scale * acc[2], scale * acc[3]);
+    }
+}
+
+hipError_t launch_kb_gather_bf16x3(const float2* u, int64_t stride, int n_orb, int n_ions, KbTables t,
+                                   double ekb_h3, float2* cnl, hipStream_t s) {
+    if (n_ions == 0) return hipSuccess;
+    dim3 grid((n_orb + 31) / 32, n_ions);
+    kb_gather_bf16x3_kernel<<<grid, 256, 0, s>>>(u, stride, n_orb, t.idx, reinterpret_cast<const float*>(t.p),
+                                                 t.count, t.kcap, (float)ekb_h3, cnl);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ forces
 // One workgroup per ion; each wave takes every fourth orbital.  Everything
 // is accumulated in FP64: c = sum p psi, d = sum (r-R)/s^2 p psi (per axis),

@@ -204,6 +204,8 @@ stencil_kernel(const cx_t<T>* __restrict__ u_all, const cx_t<T>* __restrict__ p0
                 const T him = tim + vv * ctr.y;
                 if constexpr (MODE == MODE_APPLY) {
                     res[p] = C{hre, him};
+                } else if constexpr (MODE == MODE_SCALED) {
+                    res[p] = C{-a.alpha * him, a.alpha * hre};
                 } else {
                     const C base = HORNER ? pq[0][p] : ctr;
                     res[p] = C{base.x - a.alpha * him, base.y + a.alpha * hre};
@@ -272,6 +274,9 @@ static hipError_t launch_ty(const StencilArgs<T>& a, int mode, bool norm, hipStr
         break;
     case MODE_EXPECT_T:
         stencil_kernel<T, PX, TY, MODE_EXPECT_T, false><<<grid, block, lds, s>>>(a.u, a.psi0, a.out, a.v, a.partial, a);
+        break;
+    case MODE_SCALED:
+        stencil_kernel<T, PX, TY, MODE_SCALED, false><<<grid, block, lds, s>>>(a.u, a.psi0, a.out, a.v, a.partial, a);
         break;
     default:
         return hipErrorInvalidValue;

@@ -59,7 +59,7 @@ def test_workspace_size_is_pure_host_and_scales(lib):
 @pytest.mark.parametrize("field,value,status", [
     ("n_orb", 0, 1), ("h", -0.3, 1), ("mu", 0.0, 1), ("dt", 0.0, 1),
     ("taylor_order", 0, 1), ("taylor_order", 9, 1), ("precision", 7, 1),
-    ("kb_rcut", 2.5, 1), ("reserved", 1, 1),
+    ("kb_rcut", 2.5, 1), ("enable_adjoint", 1, 6),
 ])
 def test_invalid_parameters_are_rejected(lib, field, value, status):
     from paper_0812_2801_amd import binding as B

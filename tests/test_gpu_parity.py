@@ -24,7 +24,7 @@ def _veff(m, st):
 
 
 @pytest.mark.parametrize("name,cfg", SMALL)
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32_bf16x3"])
 def test_apply_H_matches_oracle(name, cfg, prec):
     note(f"apply_H {name} {prec}")
     sysm, m, st, inp, cfg = make_pair(cfg, precision=prec)
@@ -33,7 +33,8 @@ def test_apply_H_matches_oracle(name, cfg, prec):
     x = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) * 0.05
     got = to_np(sysm.apply_H(x.reshape(3, -1))).reshape(shape)
     want = m.apply_H(x, _veff(m, st), m.spheres(st.pos))
-    tol = 1e-11 if prec == "f64" else 3e-6
+    # FP32 rounding ~6e-8 per operation; split-bf16 products keep ~16 mantissa bits
+    tol = {"f64": 1e-11, "f32": 3e-6, "f32_bf16x3": 2e-5}[prec]
     err = np.abs(got - want).max() / np.abs(want).max()
     note(f"  rel err {err:.3e}")
     assert err < tol
