@@ -124,6 +124,8 @@ int choose_ty(int nx, int ny, int px, size_t bc) {
 }
 
 int choose_zchunk(int nz, int64_t base_blocks) {
+    const int forced = env_int("MODEHR_ZCHUNK", 0);
+    if (forced > 0 && nz % forced == 0) return forced;
     // the largest divisor of nz (>= 8 planes, or nz) giving >= 1024 workgroups
     int best = nz;
     for (int zc = nz; zc >= 1; --zc) {
@@ -140,7 +142,7 @@ me_status validate(const me_params* p, std::string& err) {
     for (int a = 0; a < 3; ++a)
         if (p->n[a] < 8 || p->n[a] > 1024) { err = "grid size must be in [8, 1024] along every axis"; return ME_EINVAL; }
     if (!(p->h > 0) || !std::isfinite(p->h)) { err = "h must be positive"; return ME_EINVAL; }
-    if (p->n_ions < 0 || p->n_ions > 32 * MAX_WORDS) { err = "n_ions out of range"; return ME_EINVAL; }
+    if (p->n_ions < 0 || p->n_ions > 2048) { err = "n_ions out of range [0, 2048]"; return ME_EINVAL; }
     if (p->n_ions > 0 && (!p->pos || !p->mass || !p->zval)) { err = "pos/mass/zval must not be NULL"; return ME_EINVAL; }
     for (int J = 0; J < p->n_ions; ++J) {
         if (!(p->mass[J] > 0)) { err = "masses must be positive"; return ME_EINVAL; }
@@ -199,7 +201,7 @@ Geometry make_geometry(const me_params* p) {
 struct Layout {
     void *psi, *bufA, *bufB, *veff0, *veff1, *cnl;
     double *vloc_cur, *vloc_next, *vstatic, *hist[3], *rho, *vh;
-    double2 *rhok, *spec, *phase, *ewald_sg;
+    double2 *rhok, *spec, *phase, *phaseT, *ewald_sg;
     void* fft_work;
     double *pos, *pos_next, *vel, *frc, *mass, *zval;
     int32_t* tidx[2];
@@ -207,9 +209,9 @@ struct Layout {
     int32_t *tmap[2], *tpts[2], *tcnt[2], *tion[2], *tnslots[2], *tflag[2], *tblk[2];
     void* tpl[2];
     int32_t* tcount[2];
-    double *fnl, *enl_part, *floc_part, *fion, *eion_part, *erec_part;
+    double *fnl, *enl_part, *kbf_part, *floc_part, *floc, *fion, *eion_part, *erec_part;
     double *ewald_gv, *ewald_wv;
-    double *norm_part, *fix_part, *kin_part, *hxc_part, *loc_part, *rep, *scal0;
+    double *norm_part, *fix_part, *norms, *kin_part, *hxc_part, *loc_part, *rep, *scal0;
     // adjoint (frozen ions): forward intermediates of both exponentials, the
     // half-step and next orbitals, adjoint orbitals, and FP64 grid buffers
     void* inter[2][MAX_TAYLOR];
@@ -238,6 +240,7 @@ static Layout carve(const Geometry& g, char* base) {
     L.rhok = c.take<double2>(g.nhalf * 16);
     L.spec = c.take<double2>(g.nhalf * 16);
     L.phase = c.take<double2>((size_t)std::max(1, g.n_ions) * (g.nx + g.ny + g.nz) * 16);
+    L.phaseT = c.take<double2>((size_t)std::max(1, g.n_ions) * (g.nx + g.ny + g.nz) * 16);
     L.fft_work = c.take<void>(g.fft_work);
     const size_t ion3 = (size_t)std::max(1, g.n_ions) * 3 * 8;
     L.pos = c.take<double>(ion3);
@@ -261,16 +264,19 @@ static Layout carve(const Geometry& g, char* base) {
     }
     L.fnl = c.take<double>(ion3);
     L.enl_part = c.take<double>(ion3 / 3);
+    L.kbf_part = c.take<double>((size_t)std::max(1, g.n_ions) * ((g.n_orb + 15) / 16) * 4 * 8);
     L.floc_part = c.take<double>((size_t)std::max(1, g.n_ions) * g.floc_chunks * 3 * 8);
     L.fion = c.take<double>(ion3);
+    L.floc = c.take<double>(ion3);
     L.eion_part = c.take<double>(ion3 / 3);
     L.ewald_sg = c.take<double2>((size_t)std::max(1, g.ewald_ng) * 16);
     L.erec_part = c.take<double>((size_t)((std::max(1, g.ewald_ng) + 255) / 256) * 8);
     L.ewald_gv = c.take<double>((size_t)std::max(1, g.ewald_ng) * 3 * 8);
     L.ewald_wv = c.take<double>((size_t)std::max(1, g.ewald_ng) * 8);
     L.norm_part = c.take<double>((size_t)g.n_orb * g.nyt * g.nzc * 8);
-    L.fix_part = c.take<double>((size_t)g.n_orb * FIX_XB * 8);
+    L.fix_part = c.take<double>((size_t)g.n_orb * fixup_blocks(g.ucap) * 8);
     L.kin_part = c.take<double>((size_t)g.n_orb * g.nyt * g.nzc * 8);
+    L.norms = c.take<double>((size_t)g.n_orb * 8);
     L.hxc_part = c.take<double>((size_t)g.nblk256 * 3 * 8);
     L.loc_part = c.take<double>((size_t)g.nblk256 * 8);
     L.rep = c.take<double>(SLOT_COUNT * 8);
@@ -392,7 +398,7 @@ me_status fft_c2r(me_system* sys, double2* in, double* out) {
 me_status ion_fields(me_system* sys, const double* pos, double* out) {
     const Geometry& g = sys->g;
     const double L[3] = {g.nx * sys->prm.h, g.ny * sys->prm.h, g.nz * sys->prm.h};
-    HIPCHK(launch_phases(pos, g.n_ions, g.nx, g.ny, g.nz, L, sys->w.phase, sys->stream));
+    HIPCHK(launch_phases(pos, g.n_ions, g.nx, g.ny, g.nz, L, sys->w.phase, sys->w.phaseT, sys->stream));
     HIPCHK(launch_vloc_spectrum(sys->w.phase, sys->w.zval, g.n_ions, g.nx, g.ny, g.nz, L,
                                 sys->prm.loc_a, sys->w.spec, sys->stream));
     CHK(fft_c2r(sys, sys->w.spec, out));
@@ -439,16 +445,16 @@ me_status density_vhxc(me_system* sys, bool energy, bool push = true) {
 me_status forces_parts(me_system* sys, const double* pos, int t) {
     const Geometry& g = sys->g;
     const double L[3] = {g.nx * sys->prm.h, g.ny * sys->prm.h, g.nz * sys->prm.h};
-    HIPCHK(launch_local_forces(sys->w.rhok, sys->w.phase, sys->w.zval, g.n_ions, g.nx, g.ny, g.nz, L,
-                               sys->prm.h, sys->prm.loc_a, sys->w.floc_part, sys->stream));
+    HIPCHK(launch_local_forces(sys->w.rhok, sys->w.phaseT, sys->w.zval, g.n_ions, g.nx, g.ny, g.nz, L,
+                               sys->prm.h, sys->prm.loc_a, sys->w.floc_part, sys->w.floc, sys->stream));
     if (g.f64)
         HIPCHK(launch_kb_forces<double>((const double2*)sys->w.psi, g.stride, g.n_orb, g.n_ions, tables(sys, t), pos,
                                         sys->geo, g.nx, g.ny, sys->prm.occ, sys->prm.kb_energy, sys->w.fnl,
-                                        sys->w.enl_part, sys->stream));
+                                        sys->w.enl_part, sys->w.kbf_part, sys->stream));
     else
         HIPCHK(launch_kb_forces<float>((const float2*)sys->w.psi, g.stride, g.n_orb, g.n_ions, tables(sys, t), pos,
                                        sys->geo, g.nx, g.ny, sys->prm.occ, sys->prm.kb_energy, sys->w.fnl,
-                                       sys->w.enl_part, sys->stream));
+                                       sys->w.enl_part, sys->w.kbf_part, sys->stream));
     HIPCHK(launch_ewald(sys->ewp, pos, sys->w.zval, g.n_ions, sys->w.ewald_sg, sys->w.erec_part, sys->w.fion,
                         sys->w.eion_part, sys->stream));
     return ME_OK;
@@ -592,7 +598,8 @@ me_status finalize(me_system* sys, bool with_norm, bool energy) {
     f.rep = sys->w.rep;
     f.norm_part = with_norm ? sys->w.norm_part : nullptr;
     f.fix_part = (with_norm && g.n_ions > 0) ? sys->w.fix_part : nullptr;
-    f.fix_tiles = FIX_XB;
+    f.fix_tiles = fixup_blocks(g.ucap);
+    f.norms = sys->w.norms;
     f.nl_flag = g.n_ions > 0 ? sys->w.tflag[sys->tab_cur] : nullptr;
     f.n_orb = g.n_orb;
     f.norm_tiles = g.nyt * g.nzc;
@@ -794,8 +801,7 @@ me_status initial_fields(me_system* sys) {
     CHK(forces_parts(sys, sys->w.pos, sys->tab_cur));
     HIPCHK(hipMemcpyAsync(sys->w.pos_next, sys->w.pos, 3 * 8 * std::max(1, sys->g.n_ions),
                           hipMemcpyDeviceToDevice, sys->stream));
-    HIPCHK(launch_ions_finish(sys->w.pos, sys->w.vel, sys->w.frc, sys->w.pos_next, sys->w.floc_part,
-                              sys->g.floc_chunks, sys->w.fnl, sys->w.fion, sys->w.mass, sys->g.n_ions,
+    HIPCHK(launch_ions_finish(sys->w.pos, sys->w.vel, sys->w.frc, sys->w.pos_next, sys->w.floc, sys->w.fnl, sys->w.fion, sys->w.mass, sys->g.n_ions,
                               sys->prm.dt, 1, sys->stream));
     HIPCHK(hipMemsetAsync(sys->w.rep, 0, SLOT_COUNT * 8, sys->stream));
     return ME_OK;
@@ -817,8 +823,7 @@ me_status step_impl(me_system* sys, double eps, bool energy) {
     // 5. density, Hartree + exchange, forces at the new positions
     CHK(density_vhxc(sys, energy));
     CHK(forces_parts(sys, sys->w.pos_next, next));
-    HIPCHK(launch_ions_finish(sys->w.pos, sys->w.vel, sys->w.frc, sys->w.pos_next, sys->w.floc_part,
-                              g.floc_chunks, sys->w.fnl, sys->w.fion, sys->w.mass, g.n_ions, sys->prm.dt,
+    HIPCHK(launch_ions_finish(sys->w.pos, sys->w.vel, sys->w.frc, sys->w.pos_next, sys->w.floc, sys->w.fnl, sys->w.fion, sys->w.mass, g.n_ions, sys->prm.dt,
                               sys->prm.freeze_ions, sys->stream));
     std::swap(sys->w.vloc_cur, sys->w.vloc_next);
     sys->tab_cur = next;
@@ -1107,7 +1112,7 @@ me_status me_report(me_system* sys, me_step_report* rep) {
     const Geometry& g = sys->g;
     const double L[3] = {g.nx * sys->prm.h, g.ny * sys->prm.h, g.nz * sys->prm.h};
     CHK(density_vhxc(sys, true, false));
-    HIPCHK(launch_phases(sys->w.pos, g.n_ions, g.nx, g.ny, g.nz, L, sys->w.phase, sys->stream));
+    HIPCHK(launch_phases(sys->w.pos, g.n_ions, g.nx, g.ny, g.nz, L, sys->w.phase, sys->w.phaseT, sys->stream));
     CHK(forces_parts(sys, sys->w.pos, sys->tab_cur));
     CHK(finalize(sys, false, true));
     return read_report(sys, rep);

@@ -35,7 +35,9 @@ struct KbGeom {
 };
 
 constexpr int NL_KMAX = 8;       // projectors that may overlap at one grid point
-constexpr int FIX_XB = 32;       // fix-up workgroups per orbital
+constexpr int FIX_OB = 8;        // orbitals per fix-up thread
+// fix-up workgroups per orbital group: one thread per possible slot
+inline int fixup_blocks(int64_t ucap) { return (int)((ucap + 255) / 256); }
 
 // Per-ion projector tables (one set per ion configuration), and the same
 // information by grid point: the union of all projector spheres as a list of
@@ -110,11 +112,12 @@ hipError_t launch_kb_gather_bf16x3(const float2* u, int64_t stride, int n_orb, i
 
 // nonlocal forces and energy, FP64 accumulation:
 // fnl[J][3] = -2 f E_KB sum_A Re(conj(c_JA) d_JA); enl_part[J] = f E_KB sum_A |c_JA|^2
+// scratch: [n_ions][ceil(n_orb/16)][4] doubles
 template <typename T>
 hipError_t launch_kb_forces(const cx_t<T>* psi, int64_t stride, int n_orb, int n_ions,
                             KbTables t, const double* pos, const KbGeom& g,
                             int nx, int ny, double occ, double ekb,
-                            double* fnl, double* enl_part, hipStream_t s);
+                            double* fnl, double* enl_part, double* scratch, hipStream_t s);
 
 // rho[i] = occ * sum_A |psi_A[i]|^2 (FP64)
 template <typename T>

@@ -55,7 +55,8 @@ template hipError_t launch_density<float>(const cx_t<float>*, int64_t, int, int6
 // ------------------------------------------------------------ phases
 // ph[J][a][i] = exp(-i G_a(i) R_Ja), G_a(i) = 2 pi m(i)/L_a, for i in [0, n_a)
 __global__ void phase_kernel(const double* __restrict__ pos, int n_ions, int nx, int ny, int nz,
-                             double Lx, double Ly, double Lz, double2* __restrict__ ph) {
+                             double Lx, double Ly, double Lz, double2* __restrict__ ph,
+                             double2* __restrict__ phT) {
     const int nt = nx + ny + nz;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)n_ions * nt) return;
@@ -68,6 +69,7 @@ __global__ void phase_kernel(const double* __restrict__ pos, int n_ions, int nx,
     double sn, cs;
     sincos(-g * pos[3 * J + a], &sn, &cs);
     ph[t] = make_double2(cs, sn);
+    phT[(int64_t)(t % nt) * n_ions + J] = make_double2(cs, sn);   // [axis offset + i][J]
 }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -207,62 +209,117 @@ __global__ void veff_kernel(const double* __restrict__ vloc0, const double* __re
 
 // ------------------------------------------------------------ local forces
 // F_J = (1/Omega) Re sum_{G in box} conj(rho(G)) (i G) v(G) Z_J exp(-i G.R_J),
-// rho(G) = h^3 fft(rho).  Thread per full-box G; 8 ions per block column.
-// part[((J*nchunk) + chunk)*3 + c]
+// rho(G) = h^3 fft(rho).  With Phi(G) = conj(rho(G)) v(G) h^3/Omega and the
+// separable phase exp(-i G.R) = ex(ix) ey(iy) ez(iz), one x-row of the box
+// contributes per ion S0 = sum_ix Phi ex, Sx = sum_ix Gx Phi ex, and
+//   F_x -= Z Im(Sx ey ez),  F_y -= Z Gy Im(S0 ey ez),  F_z -= Z Gz Im(S0 ey ez).
+// A workgroup takes rows in turn (Phi of the row staged in LDS), a thread
+// takes ions (the transposed phase table makes the ion loads coalesced).
+// part[(J * gridDim.x + block) * 3 + c]
+constexpr int LF_PASSES = 8;   // up to 8 * 256 ions
+constexpr int LF_ROWS = 8;     // x-rows per workgroup pass (reuse of each ex load)
+
 __global__ void __launch_bounds__(256) local_force_kernel(const double2* __restrict__ rhok,
-                                                          const double2* __restrict__ ph,
+                                                          const double2* __restrict__ phT,
                                                           const double* __restrict__ zval,
                                                           int n_ions, int nx, int ny, int nz,
                                                           double Lx, double Ly, double Lz,
-                                                          double a, double scale, int per_thread,
+                                                          double a, double scale,
                                                           double* __restrict__ part) {
-    __shared__ double sh[4];
+    extern __shared__ double2 phi[];      // [LF_ROWS][nx]
     const int nh = nx / 2 + 1;
-    const int nt = nx + ny + nz;
-    const int64_t N = (int64_t)nx * ny * nz;
-    const int J0 = blockIdx.y * 8;
-    const int nj = min(8, n_ions - J0);
-    double acc[8][3];
+    double acc[LF_PASSES][3];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
-    const int64_t base = ((int64_t)blockIdx.x * blockDim.x) * per_thread + threadIdx.x;
-    for (int r = 0; r < per_thread; ++r) {
-        const int64_t t = base + (int64_t)r * blockDim.x;
-        if (t >= N) break;
-        const int ix = (int)(t % nx);
-        const int iy = (int)((t / nx) % ny);
-        const int iz = (int)(t / ((int64_t)nx * ny));
-        const double gx = 2.0 * M_PI * wavenum(ix, nx) / Lx;
-        const double gy = 2.0 * M_PI * wavenum(iy, ny) / Ly;
-        const double gz = 2.0 * M_PI * wavenum(iz, nz) / Lz;
-        const double g2 = gx * gx + gy * gy + gz * gz;
-        if (g2 == 0.0) continue;
-        double2 rk;
-        if (ix < nh) {
-            rk = rhok[((int64_t)iz * ny + iy) * nh + ix];
-        } else {
-            const int mx = nx - ix, my = (ny - iy) % ny, mz = (nz - iz) % nz;
-            const double2 q = rhok[((int64_t)mz * ny + my) * nh + mx];
-            rk = make_double2(q.x, -q.y);
+    for (int p = 0; p < LF_PASSES; ++p) acc[p][0] = acc[p][1] = acc[p][2] = 0.0;
+    const int rows = ny * nz;
+    const int groups = (rows + LF_ROWS - 1) / LF_ROWS;
+    for (int grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+        const int r0 = grp * LF_ROWS;
+        __syncthreads();
+        for (int e = threadIdx.x; e < LF_ROWS * nx; e += blockDim.x) {
+            const int rr = e / nx, ix = e - rr * nx;
+            const int row = r0 + rr;
+            double2 w = make_double2(0.0, 0.0);
+            if (row < rows) {
+                const int iy = row % ny, iz = row / ny;
+                const double gx = 2.0 * M_PI * wavenum(ix, nx) / Lx;
+                const double gy = 2.0 * M_PI * wavenum(iy, ny) / Ly;
+                const double gz = 2.0 * M_PI * wavenum(iz, nz) / Lz;
+                const double g2 = gx * gx + gy * gy + gz * gz;
+                if (g2 > 0.0) {
+                    double2 rk;
+                    if (ix < nh) {
+                        rk = rhok[((int64_t)iz * ny + iy) * nh + ix];
+                    } else {
+                        const int mx = nx - ix, my = (ny - iy) % ny, mz = (nz - iz) % nz;
+                        const double2 q = rhok[((int64_t)mz * ny + my) * nh + mx];
+                        rk = make_double2(q.x, -q.y);
+                    }
+                    const double f = vloc_ff(g2, a) * scale;
+                    w = make_double2(f * rk.x, -f * rk.y);     // conj(rho) v
+                }
+            }
+            phi[e] = w;
         }
-        const double f = vloc_ff(g2, a) * scale;          // scale = h^3 / Omega
-        const double2 w = make_double2(f * rk.x, -f * rk.y);   // conj(rho) v
-        for (int j = 0; j < nj; ++j) {
-            const double2* pj = ph + (int64_t)(J0 + j) * nt;
-            const double2 e = cmul(cmul(pj[ix], pj[nx + iy]), pj[nx + ny + iz]);
-            const double2 tt = cmul(w, e);
-            const double im = zval[J0 + j] * tt.y;         // Re(i G t) = -G Im(t)
-            acc[j][0] -= gx * im;
-            acc[j][1] -= gy * im;
-            acc[j][2] -= gz * im;
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < LF_PASSES; ++p) {
+            const int J = p * 256 + threadIdx.x;
+            if (J < n_ions) {
+                double s0r[LF_ROWS], s0i[LF_ROWS], sxr[LF_ROWS], sxi[LF_ROWS];
+#pragma unroll
+                for (int rr = 0; rr < LF_ROWS; ++rr) s0r[rr] = s0i[rr] = sxr[rr] = sxi[rr] = 0.0;
+                for (int ix = 0; ix < nx; ++ix) {
+                    const double2 e = phT[(int64_t)ix * n_ions + J];
+                    const double gx = 2.0 * M_PI * wavenum(ix, nx) / Lx;
+#pragma unroll
+                    for (int rr = 0; rr < LF_ROWS; ++rr) {
+                        const double2 w = phi[rr * nx + ix];
+                        const double tr = w.x * e.x - w.y * e.y, ti = w.x * e.y + w.y * e.x;
+                        s0r[rr] += tr; s0i[rr] += ti;
+                        sxr[rr] += gx * tr; sxi[rr] += gx * ti;
+                    }
+                }
+                const double zj = zval[J];
+#pragma unroll
+                for (int rr = 0; rr < LF_ROWS; ++rr) {
+                    const int row = r0 + rr;
+                    if (row < rows) {
+                        const int iy = row % ny, iz = row / ny;
+                        const double gy = 2.0 * M_PI * wavenum(iy, ny) / Ly;
+                        const double gz = 2.0 * M_PI * wavenum(iz, nz) / Lz;
+                        const double2 ey = phT[(int64_t)(nx + iy) * n_ions + J];
+                        const double2 ez = phT[(int64_t)(nx + ny + iz) * n_ions + J];
+                        const double2 e = cmul(ey, ez);
+                        const double im0 = s0r[rr] * e.y + s0i[rr] * e.x;     // Im(S0 e)
+                        const double imx = sxr[rr] * e.y + sxi[rr] * e.x;     // Im(Sx e)
+                        acc[p][0] -= zj * imx;
+                        acc[p][1] -= zj * gy * im0;
+                        acc[p][2] -= zj * gz * im0;
+                    }
+                }
+            }
         }
     }
-    for (int j = 0; j < 8; ++j)
-        for (int c = 0; c < 3; ++c) {
-            const double s = block_sum256(acc[j][c], sh);
-            if (threadIdx.x == 0 && j < nj)
-                part[((int64_t)(J0 + j) * gridDim.x + blockIdx.x) * 3 + c] = s;
-        }
+#pragma unroll
+    for (int p = 0; p < LF_PASSES; ++p) {
+        const int J = p * 256 + threadIdx.x;
+        if (J < n_ions)
+            for (int c = 0; c < 3; ++c) part[((int64_t)J * gridDim.x + blockIdx.x) * 3 + c] = acc[p][c];
+    }
+}
+
+// per ion: F_loc = sum of the local-force partials (fixed order)
+__global__ void __launch_bounds__(256) local_force_sum_kernel(const double* __restrict__ part, int nchunk,
+                                                              double* __restrict__ floc) {
+    __shared__ double sh[4];
+    const int J = blockIdx.x;
+    for (int c = 0; c < 3; ++c) {
+        double v = 0.0;
+        for (int k = threadIdx.x; k < nchunk; k += 256) v += part[((int64_t)J * nchunk + k) * 3 + c];
+        const double r = block_sum256(v, sh);
+        if (threadIdx.x == 0) floc[3 * J + c] = r;
+    }
 }
 
 // ------------------------------------------------------------ Ewald
@@ -362,16 +419,14 @@ __global__ void ions_predict_kernel(const double* __restrict__ pos, const double
 // total force F = F_loc + F_NL + F_ion; velocities; the new state becomes current
 __global__ void ions_finish_kernel(double* __restrict__ pos, double* __restrict__ vel,
                                    double* __restrict__ frc, const double* __restrict__ pos1,
-                                   const double* __restrict__ floc_part, int nchunk,
+                                   const double* __restrict__ floc,
                                    const double* __restrict__ fnl, const double* __restrict__ fion,
                                    const double* __restrict__ mass, int n_ions, double dt,
                                    int frozen) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 3 * n_ions) return;
-    const int J = t / 3, c = t % 3;
-    double fl = 0.0;
-    for (int k = 0; k < nchunk; ++k) fl += floc_part[((int64_t)J * nchunk + k) * 3 + c];
-    const double f1 = (fl + fnl[t]) + fion[t];
+    const int J = t / 3;
+    const double f1 = (floc[t] + fnl[t]) + fion[t];
     if (!frozen) vel[t] = vel[t] + (frc[t] + f1) * dt / (2.0 * mass[J]);
     pos[t] = pos1[t];
     frc[t] = f1;
@@ -399,28 +454,36 @@ __global__ void __launch_bounds__(256) dot_partial_kernel(const double* __restri
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// norms[A] = h^3 (sum of the stencil partials + sum of the fix-up partials)
+__global__ void __launch_bounds__(256) norm_reduce_kernel(FinalizeArgs a) {
+    __shared__ double sh[4];
+    const int A = blockIdx.x;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < a.norm_tiles; k += 256) s += a.norm_part[(int64_t)A * a.norm_tiles + k];
+    if (a.fix_part != nullptr)
+        for (int k = threadIdx.x; k < a.fix_tiles; k += 256) s += a.fix_part[(int64_t)A * a.fix_tiles + k];
+    s = block_sum256(s, sh);
+    if (threadIdx.x == 0) a.norms[A] = s * a.dv;
+}
+
 // Collect the step's diagnostics into rep[] (one block of 256 threads).
 // Layout of rep: see ReportSlot.
 __global__ void __launch_bounds__(256) report_kernel(FinalizeArgs a) {
     __shared__ double sh[4];
     const int tid = threadIdx.x;
-    // norms: per orbital h^3 * sum of tile partials, max |n-1| and finiteness
+    // norms (already reduced per orbital by norm_reduce_kernel): max |n-1|
+    // and finiteness
     double worst = 0.0;
     int bad = 0;
     if (a.norm_part != nullptr) {
         for (int A = tid; A < a.n_orb; A += 256) {
-            double s = 0.0;
-            for (int k = 0; k < a.norm_tiles; ++k) s += a.norm_part[(int64_t)A * a.norm_tiles + k];
-            if (a.fix_part != nullptr)
-                for (int k = 0; k < a.fix_tiles; ++k) s += a.fix_part[(int64_t)A * a.fix_tiles + k];
-            s *= a.dv;
+            const double s = a.norms[A];
             if (!isfinite(s)) bad = 1;
-            const double dev = fabs(s - 1.0);
-            worst = fmax(worst, dev);
+            worst = fmax(worst, fabs(s - 1.0));
             if (s > 1.0 + a.norm_tol) bad = 1;
         }
     }
-    // wave/block max via shared memory
+    // block max via shared memory
     __shared__ double mx[256];
     __shared__ int bd[256];
     mx[tid] = worst;
@@ -482,10 +545,10 @@ __global__ void __launch_bounds__(256) report_kernel(FinalizeArgs a) {
 static inline unsigned nb(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
 hipError_t launch_phases(const double* pos, int n_ions, int nx, int ny, int nz, const double L[3],
-                         double2* ph, hipStream_t s) {
+                         double2* ph, double2* phT, hipStream_t s) {
     if (n_ions == 0) return hipSuccess;
     const int64_t n = (int64_t)n_ions * (nx + ny + nz);
-    phase_kernel<<<nb(n), 256, 0, s>>>(pos, n_ions, nx, ny, nz, L[0], L[1], L[2], ph);
+    phase_kernel<<<nb(n), 256, 0, s>>>(pos, n_ions, nx, ny, nz, L[0], L[1], L[2], ph, phT);
     return hipGetLastError();
 }
 
@@ -523,19 +586,19 @@ template hipError_t launch_veff<double>(const double*, const double*, const doub
 template hipError_t launch_veff<float>(const double*, const double*, const double*, const double*, const double*, int, int, int64_t, double, double, double, float*, float*, hipStream_t);
 
 int local_force_chunks(int64_t N) {
-    const int64_t per_block = 256 * 16;
-    return (int)((N + per_block - 1) / per_block);
+    (void)N;
+    return 512;
 }
 
-hipError_t launch_local_forces(const double2* rhok, const double2* ph, const double* zval,
+hipError_t launch_local_forces(const double2* rhok, const double2* phT, const double* zval,
                                int n_ions, int nx, int ny, int nz, const double L[3], double h,
-                               double a, double* part, hipStream_t s) {
+                               double a, double* part, double* floc, hipStream_t s) {
     if (n_ions == 0) return hipSuccess;
-    const int64_t N = (int64_t)nx * ny * nz;
-    dim3 grid(local_force_chunks(N), (n_ions + 7) / 8);
+    if (n_ions > LF_PASSES * 256) return hipErrorInvalidValue;
     const double scale = h * h * h / (L[0] * L[1] * L[2]);
-    local_force_kernel<<<grid, 256, 0, s>>>(rhok, ph, zval, n_ions, nx, ny, nz, L[0], L[1], L[2], a,
-                                            scale, 16, part);
+    local_force_kernel<<<local_force_chunks(0), 256, LF_ROWS * nx * sizeof(double2), s>>>(
+        rhok, phT, zval, n_ions, nx, ny, nz, L[0], L[1], L[2], a, scale, part);
+    local_force_sum_kernel<<<n_ions, 256, 0, s>>>(part, local_force_chunks(0), floc);
     return hipGetLastError();
 }
 
@@ -557,11 +620,11 @@ hipError_t launch_ions_predict(const double* pos, const double* vel, const doubl
 }
 
 hipError_t launch_ions_finish(double* pos, double* vel, double* frc, const double* pos1,
-                              const double* floc_part, int nchunk, const double* fnl,
+                              const double* floc, const double* fnl,
                               const double* fion, const double* mass, int n_ions, double dt,
                               int frozen, hipStream_t s) {
     if (n_ions == 0) return hipSuccess;
-    ions_finish_kernel<<<nb(3 * n_ions), 256, 0, s>>>(pos, vel, frc, pos1, floc_part, nchunk, fnl,
+    ions_finish_kernel<<<nb(3 * n_ions), 256, 0, s>>>(pos, vel, frc, pos1, floc, fnl,
                                                       fion, mass, n_ions, dt, frozen);
     return hipGetLastError();
 }
@@ -583,6 +646,7 @@ hipError_t launch_dot_partial(const double* a, const double* b, int64_t n, doubl
 }
 
 hipError_t launch_report(const FinalizeArgs& a, hipStream_t s) {
+    if (a.norm_part != nullptr) norm_reduce_kernel<<<a.n_orb, 256, 0, s>>>(a);
     report_kernel<<<1, 256, 0, s>>>(a);
     return hipGetLastError();
 }

@@ -15,6 +15,7 @@ struct FinalizeArgs {
     const double* norm_part;     // [n_orb][norm_tiles] or nullptr
     const double* fix_part;      // [n_orb][fix_tiles] nonlocal change of the norm, or nullptr
     const int32_t* nl_flag;      // nonzero: a grid point lies in too many projector spheres
+    double* norms;               // [n_orb] scratch: per-orbital norms
     int n_orb;
     int norm_tiles;
     int fix_tiles;
@@ -44,8 +45,9 @@ struct EwaldPlan {
     double* wv;   // [ng] device: exp(-G^2/(4 eta^2))/G^2
 };
 
+// ph: [n_ions][nx+ny+nz] exp(-i G_a(i) R_Ja); phT: the same as [nx+ny+nz][n_ions]
 hipError_t launch_phases(const double* pos, int n_ions, int nx, int ny, int nz, const double L[3],
-                         double2* ph, hipStream_t s);
+                         double2* ph, double2* phT, hipStream_t s);
 hipError_t launch_vloc_spectrum(const double2* ph, const double* zval, int n_ions, int nx, int ny,
                                 int nz, const double L[3], double a, double2* out, hipStream_t s);
 hipError_t launch_hartree_spectrum(const double2* rhok, int nx, int ny, int nz, const double L[3],
@@ -57,16 +59,17 @@ hipError_t launch_veff(const double* vloc0, const double* vloc1, const double* h
                        const double* hn2, int nhist, int nx, int64_t N, double h, double Lx,
                        double eps, T* veff0, T* veff1, hipStream_t s);
 int local_force_chunks(int64_t N);
-hipError_t launch_local_forces(const double2* rhok, const double2* ph, const double* zval,
+// part: [n_ions][local_force_chunks][3] scratch; floc: [n_ions][3]
+hipError_t launch_local_forces(const double2* rhok, const double2* phT, const double* zval,
                                int n_ions, int nx, int ny, int nz, const double L[3], double h,
-                               double a, double* part, hipStream_t s);
+                               double a, double* part, double* floc, hipStream_t s);
 hipError_t launch_ewald(const EwaldPlan& e, const double* pos, const double* zval, int n_ions,
                         double2* sg, double* erec_part, double* f, double* epart, hipStream_t s);
 hipError_t launch_ions_predict(const double* pos, const double* vel, const double* frc,
                                const double* mass, int n_ions, double dt, int frozen, double* pos1,
                                hipStream_t s);
 hipError_t launch_ions_finish(double* pos, double* vel, double* frc, const double* pos1,
-                              const double* floc_part, int nchunk, const double* fnl,
+                              const double* floc, const double* fnl,
                               const double* fion, const double* mass, int n_ions, double dt,
                               int frozen, hipStream_t s);
 hipError_t launch_add(double* a, const double* b, int64_t n, hipStream_t s);

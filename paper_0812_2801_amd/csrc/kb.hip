@@ -229,8 +229,9 @@ hipError_t launch_kb_tables(const double* pos, int n_ions, int nx, int ny, int n
 }
 
 // out_A(r) += g * sum_k pl * cnl[ion*n_orb + A] over the slots of the
-// projector spheres.  Grid (FIX_XB, n_orb): neighbouring lanes take
-// neighbouring slots of one orbital.  With dnorm, the change of the
+// projector spheres.  Grid (ceil(ucap/256), ceil(n_orb/FIX_OB)): a thread
+// takes one slot (its pairs read once) and updates FIX_OB orbitals there;
+// neighbouring lanes take neighbouring slots.  With dnorm, the change of each
 // orbital's squared norm, sum |out + d|^2 - |out|^2, is returned per block.
 template <typename T>
 __global__ void __launch_bounds__(256) kb_fixup_kernel(cx_t<T>* __restrict__ out, int64_t stride,
@@ -241,43 +242,64 @@ __global__ void __launch_bounds__(256) kb_fixup_kernel(cx_t<T>* __restrict__ out
                                                        const T* __restrict__ pl,
                                                        const cx_t<T>* __restrict__ cnl, T gr, T gi,
                                                        double* __restrict__ dnorm) {
-    __shared__ double red[4];
-    const int A = blockIdx.y;
+    __shared__ double red[4][FIX_OB];
+    const int A0 = blockIdx.y * FIX_OB;
+    const int na = min(FIX_OB, n_orb - A0);
     const int ns = *nslots;
-    cx_t<T>* oa = out + (int64_t)A * stride;
-    double dn = 0.0;
-    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < ns; s += gridDim.x * blockDim.x) {
+    double dn[FIX_OB];
+#pragma unroll
+    for (int j = 0; j < FIX_OB; ++j) dn[j] = 0.0;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < ns) {
         const int n = cnt[s];
-        T sr = 0, si = 0;
+        const int64_t r = pts[s];
+        int jj[NL_KMAX];
+        T ww[NL_KMAX];
         for (int k = 0; k < n; ++k) {
-            const T w = pl[(int64_t)s * NL_KMAX + k];
-            const cx_t<T> c = cnl[(int64_t)ion[(int64_t)s * NL_KMAX + k] * n_orb + A];
-            sr += w * c.x;
-            si += w * c.y;
+            jj[k] = ion[(int64_t)s * NL_KMAX + k];
+            ww[k] = pl[(int64_t)s * NL_KMAX + k];
         }
-        cx_t<T>* o = oa + pts[s];
-        const cx_t<T> old = *o;
-        cx_t<T> val = old;
-        val.x += gr * sr - gi * si;
-        val.y += gr * si + gi * sr;
-        *o = val;
-        if (dnorm != nullptr)
-            dn += ((double)val.x * val.x + (double)val.y * val.y) -
-                  ((double)old.x * old.x + (double)old.y * old.y);
+#pragma unroll
+        for (int j = 0; j < FIX_OB; ++j) {
+            if (j < na) {
+                const int A = A0 + j;
+                T sr = 0, si = 0;
+                for (int k = 0; k < n; ++k) {
+                    const cx_t<T> c = cnl[(int64_t)jj[k] * n_orb + A];
+                    sr += ww[k] * c.x;
+                    si += ww[k] * c.y;
+                }
+                cx_t<T>* o = out + (int64_t)A * stride + r;
+                const cx_t<T> old = *o;
+                cx_t<T> val = old;
+                val.x += gr * sr - gi * si;
+                val.y += gr * si + gi * sr;
+                *o = val;
+                if (dnorm != nullptr)
+                    dn[j] += ((double)val.x * val.x + (double)val.y * val.y) -
+                             ((double)old.x * old.x + (double)old.y * old.y);
+            }
+        }
     }
     if (dnorm != nullptr) {
-        for (int o = 32; o > 0; o >>= 1) dn += __shfl_xor(dn, o, 64);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dn;
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+        for (int j = 0; j < FIX_OB; ++j) {
+            double v = dn[j];
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) red[wv][j] = v;
+        }
         __syncthreads();
-        if (threadIdx.x == 0)
-            dnorm[(int64_t)A * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+        if (threadIdx.x < na)
+            dnorm[(int64_t)(A0 + threadIdx.x) * gridDim.x + blockIdx.x] =
+                ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
     }
 }
 
 template <typename T>
 hipError_t launch_kb_fixup(cx_t<T>* out, int64_t stride, int n_orb, KbTables t,
                            const cx_t<T>* cnl, double gr, double gi, double* dnorm, hipStream_t s) {
-    dim3 grid(FIX_XB, n_orb);
+    dim3 grid(fixup_blocks(t.ucap), (n_orb + FIX_OB - 1) / FIX_OB);
     kb_fixup_kernel<T><<<grid, 256, 0, s>>>(out, stride, n_orb, t.nslots, t.pts, t.cnt, t.ion,
                                             reinterpret_cast<const T*>(t.pl), cnl, (T)gr, (T)gi, dnorm);
     return hipGetLastError();
@@ -407,17 +429,19 @@ hipError_t launch_kb_gather_bf16x3(const float2* u, int64_t stride, int n_orb, i
 }
 
 // ------------------------------------------------------------ forces
-// One workgroup per ion; each wave takes every fourth orbital.  Everything
-// is accumulated in FP64: c = sum p psi, d = sum (r-R)/s^2 p psi (per axis),
-// F_J = -2 f E_KB h^6 sum_A Re(conj(c) d), E_J = f E_KB h^6 sum_A |c|^2.
+// Grid (n_ions, ceil(n_orb/16)); each wave takes 4 orbitals of the group.
+// Everything is accumulated in FP64: c = sum p psi, d = sum (r-R) p psi per
+// axis; per block the partial sums of Re(conj(c) d) (3 axes) and |c|^2 are
+// written, and a second kernel adds the blocks of each ion in order:
+// F_J = -2 f E_KB h^6 / s^2 sum_A Re(conj(c) d), E_J = f E_KB h^6 sum_A |c|^2.
+constexpr int KBF_OB = 16;
+
 template <typename T>
 __global__ void __launch_bounds__(256) kb_forces_kernel(const cx_t<T>* __restrict__ psi, int64_t stride,
                                                         int n_orb, const int32_t* __restrict__ idx,
                                                         const int32_t* __restrict__ count, int kcap,
                                                         const double* __restrict__ pos, KbGeom g,
-                                                        int nx, int ny, double occ, double ekb,
-                                                        double* __restrict__ fnl,
-                                                        double* __restrict__ enl_part) {
+                                                        int nx, int ny, double* __restrict__ part) {
     __shared__ double red[4][4];
     const int J = blockIdx.x;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -425,7 +449,8 @@ __global__ void __launch_bounds__(256) kb_forces_kernel(const cx_t<T>* __restric
     const int32_t* ix = idx + (int64_t)J * kcap;
     const double rx = pos[3 * J], ry = pos[3 * J + 1], rz = pos[3 * J + 2];
     double fx = 0, fy = 0, fz = 0, en = 0;
-    for (int A = wv; A < n_orb; A += 4) {
+    const int A_end = min(n_orb, (int)(blockIdx.y + 1) * KBF_OB);
+    for (int A = blockIdx.y * KBF_OB + wv; A < A_end; A += 4) {
         const cx_t<T>* pa = psi + (int64_t)A * stride;
         double cr = 0, ci = 0, xr = 0, xi = 0, yr = 0, yi = 0, zr = 0, zi = 0;
         for (int k = lane; k < K; k += 64) {
@@ -456,26 +481,37 @@ __global__ void __launch_bounds__(256) kb_forces_kernel(const cx_t<T>* __restric
         red[wv][0] = fx; red[wv][1] = fy; red[wv][2] = fz; red[wv][3] = en;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const double h6 = g.h * g.h * g.h * g.h * g.h * g.h;
-        double s[4];
-        for (int c = 0; c < 4; ++c) s[c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
-        const double kf = -2.0 * occ * ekb * h6 * g.inv_s2;
-        fnl[3 * J] = kf * s[0];
-        fnl[3 * J + 1] = kf * s[1];
-        fnl[3 * J + 2] = kf * s[2];
-        enl_part[J] = occ * ekb * h6 * s[3];
+    if (threadIdx.x < 4) {
+        const int c = threadIdx.x;
+        part[((int64_t)J * gridDim.y + blockIdx.y) * 4 + c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
     }
+}
+
+__global__ void kb_forces_reduce_kernel(const double* __restrict__ part, int nblk, int n_ions, double kf,
+                                        double ke, double* __restrict__ fnl, double* __restrict__ enl) {
+    const int J = blockIdx.x * blockDim.x + threadIdx.x;
+    if (J >= n_ions) return;
+    double s[4] = {0, 0, 0, 0};
+    for (int b = 0; b < nblk; ++b)
+        for (int c = 0; c < 4; ++c) s[c] += part[((int64_t)J * nblk + b) * 4 + c];
+    fnl[3 * J] = kf * s[0];
+    fnl[3 * J + 1] = kf * s[1];
+    fnl[3 * J + 2] = kf * s[2];
+    enl[J] = ke * s[3];
 }
 
 template <typename T>
 hipError_t launch_kb_forces(const cx_t<T>* psi, int64_t stride, int n_orb, int n_ions,
                             KbTables t, const double* pos, const KbGeom& g,
                             int nx, int ny, double occ, double ekb,
-                            double* fnl, double* enl_part, hipStream_t s) {
+                            double* fnl, double* enl_part, double* scratch, hipStream_t s) {
     if (n_ions == 0) return hipSuccess;
-    kb_forces_kernel<T><<<n_ions, 256, 0, s>>>(psi, stride, n_orb, t.idx, t.count, t.kcap, pos, g,
-                                               nx, ny, occ, ekb, fnl, enl_part);
+    const int nblk = (n_orb + KBF_OB - 1) / KBF_OB;
+    dim3 grid(n_ions, nblk);
+    kb_forces_kernel<T><<<grid, 256, 0, s>>>(psi, stride, n_orb, t.idx, t.count, t.kcap, pos, g, nx, ny, scratch);
+    const double h6 = g.h * g.h * g.h * g.h * g.h * g.h;
+    kb_forces_reduce_kernel<<<(n_ions + 63) / 64, 64, 0, s>>>(scratch, nblk, n_ions, -2.0 * occ * ekb * h6 * g.inv_s2,
+                                                             occ * ekb * h6, fnl, enl_part);
     return hipGetLastError();
 }
 
@@ -485,7 +521,7 @@ template hipError_t launch_kb_fixup<double>(cx_t<double>*, int64_t, int, KbTable
 template hipError_t launch_kb_fixup<float>(cx_t<float>*, int64_t, int, KbTables, const cx_t<float>*, double, double, double*, hipStream_t);
 template hipError_t launch_kb_gather<double>(const cx_t<double>*, int64_t, int, int, KbTables, double, cx_t<double>*, hipStream_t);
 template hipError_t launch_kb_gather<float>(const cx_t<float>*, int64_t, int, int, KbTables, double, cx_t<float>*, hipStream_t);
-template hipError_t launch_kb_forces<double>(const cx_t<double>*, int64_t, int, int, KbTables, const double*, const KbGeom&, int, int, double, double, double*, double*, hipStream_t);
-template hipError_t launch_kb_forces<float>(const cx_t<float>*, int64_t, int, int, KbTables, const double*, const KbGeom&, int, int, double, double, double*, double*, hipStream_t);
+template hipError_t launch_kb_forces<double>(const cx_t<double>*, int64_t, int, int, KbTables, const double*, const KbGeom&, int, int, double, double, double*, double*, double*, hipStream_t);
+template hipError_t launch_kb_forces<float>(const cx_t<float>*, int64_t, int, int, KbTables, const double*, const KbGeom&, int, int, double, double, double*, double*, double*, hipStream_t);
 
 }  // namespace me

@@ -33,6 +33,42 @@ __device__ __forceinline__ void load_run(const cx_t<T>* __restrict__ p, cx_t<T>*
     }
 }
 
+#ifndef STENCIL_NT
+#define STENCIL_NT 1
+#endif
+
+#ifndef STENCIL_NTLOAD
+#define STENCIL_NTLOAD 1
+#endif
+
+// streaming load of a run read once (psi0): non-temporal when STENCIL_NTLOAD
+template <typename T, int PX>
+__device__ __forceinline__ void load_once(const cx_t<T>* __restrict__ p, cx_t<T>* r) {
+    if constexpr (STENCIL_NTLOAD) {
+#pragma unroll
+        for (int i = 0; i < PX; ++i) {
+            r[i].x = __builtin_nontemporal_load(&p[i].x);
+            r[i].y = __builtin_nontemporal_load(&p[i].y);
+        }
+    } else {
+        load_run<T, PX>(p, r);
+    }
+}
+
+// streaming store of one output run (non-temporal when STENCIL_NT)
+template <typename T, int PX>
+__device__ __forceinline__ void store_out(cx_t<T>* __restrict__ p, const cx_t<T>* r) {
+#pragma unroll
+    for (int i = 0; i < PX; ++i) {
+        if constexpr (STENCIL_NT) {
+            __builtin_nontemporal_store(r[i].x, &p[i].x);
+            __builtin_nontemporal_store(r[i].y, &p[i].y);
+        } else {
+            p[i] = r[i];
+        }
+    }
+}
+
 template <typename T, int PX>
 __device__ __forceinline__ void store_run(cx_t<T>* __restrict__ p, const cx_t<T>* r) {
     if constexpr (sizeof(cx_t<T>) == 8 && (PX % 2) == 0) {
@@ -67,9 +103,24 @@ __device__ __forceinline__ void load_real(const T* __restrict__ p, T* r) {
     }
 }
 
-#ifndef STENCIL_PD
-#define STENCIL_PD 1
+#ifndef STENCIL_PD32
+#define STENCIL_PD32 1
 #endif
+#ifndef STENCIL_PD64
+#define STENCIL_PD64 1
+#endif
+#ifndef STENCIL_WPE
+#define STENCIL_WPE 0
+#endif
+#if STENCIL_WPE > 0
+#define STENCIL_ATTR __attribute__((amdgpu_waves_per_eu(STENCIL_WPE)))
+#else
+#define STENCIL_ATTR
+#endif
+
+// Global loads run D planes ahead of the compute.
+template <typename T> struct Pipe { static constexpr int D = sizeof(T) == 4 ? STENCIL_PD32 : STENCIL_PD64; };
+
 
 // Software pipeline with one barrier per plane.  Global loads run PD planes
 // ahead of the compute: at plane z the thread issues the loads of plane z+PD
@@ -79,12 +130,12 @@ __device__ __forceinline__ void load_real(const T* __restrict__ p, T* r) {
 // whose address depends on another load, so the only waits are for the
 // queued planes.  Offsets inside one orbital are 32-bit.
 template <typename T, int PX, int TY, int MODE, bool NORM>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(1024) STENCIL_ATTR
 stencil_kernel(const cx_t<T>* __restrict__ u_all, const cx_t<T>* __restrict__ p0_all,
                cx_t<T>* __restrict__ out_all, const T* __restrict__ v,
                double* __restrict__ partial, StencilArgs<T> a) {
     using C = cx_t<T>;
-    constexpr int D = STENCIL_PD;
+    constexpr int D = Pipe<T>::D;
     constexpr int HJ = (8 + TY - 1) / TY;          // halo runs per thread
     constexpr bool HORNER = MODE == MODE_HORNER;
     constexpr bool NEEDV = MODE != MODE_EXPECT_T;
@@ -155,7 +206,7 @@ stencil_kernel(const cx_t<T>* __restrict__ u_all, const cx_t<T>* __restrict__ p0
 #pragma unroll
             for (int i = 0; i < HJ; ++i)
                 if (h_ok[i]) load_run<T, PX>(u + zo + h_off[i], hq[d][i]);
-            if constexpr (HORNER) load_run<T, PX>(p0 + zo + rowoff, pq[d]);
+            if constexpr (HORNER) load_once<T, PX>(p0 + zo + rowoff, pq[d]);
             if constexpr (NEEDV) load_real<T, PX>(v + zo + rowoff, vq[d]);
         }
     }
@@ -174,7 +225,7 @@ stencil_kernel(const cx_t<T>* __restrict__ u_all, const cx_t<T>* __restrict__ p0
 #pragma unroll
             for (int i = 0; i < HJ; ++i)
                 if (h_ok[i]) load_run<T, PX>(u + zo + h_off[i], hq[D][i]);
-            if constexpr (HORNER) load_run<T, PX>(p0 + zo + rowoff, pq[D]);
+            if constexpr (HORNER) load_once<T, PX>(p0 + zo + rowoff, pq[D]);
             if constexpr (NEEDV) load_real<T, PX>(v + zo + rowoff, vq[D]);
         }
         const C* tile = tiles + buf * tile_elems;
@@ -214,7 +265,7 @@ stencil_kernel(const cx_t<T>* __restrict__ u_all, const cx_t<T>* __restrict__ p0
                     acc += (double)res[p].x * (double)res[p].x + (double)res[p].y * (double)res[p].y;
             }
         }
-        if constexpr (MODE != MODE_EXPECT_T) store_run<T, PX>(out + z * plane + rowoff, res);
+        if constexpr (MODE != MODE_EXPECT_T) store_out<T, PX>(out + z * plane + rowoff, res);
 
         if (z + 1 < z1) {
             C* nt = tiles + (buf ^ 1) * tile_elems;
@@ -253,6 +304,7 @@ stencil_kernel(const cx_t<T>* __restrict__ u_all, const cx_t<T>* __restrict__ p0
         }
     }
 }
+
 
 template <typename T, int PX, int TY>
 static hipError_t launch_ty(const StencilArgs<T>& a, int mode, bool norm, hipStream_t s) {
