@@ -1,0 +1,92 @@
+"""Summarise rocprofv3 CSV output into the short text files kept under profiles/.
+
+  python -m paper_0812_2801_amd.profsum stats <kernel_stats.csv> <out.md> "<command>"
+  python -m paper_0812_2801_amd.profsum traffic <fetch_dir> <write_dir> <copy_fetch_dir> \
+        <copy_write_dir> <copy_bytes> <out.json> "<command>"
+
+`traffic` scales FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the Horner
+stage stencil launches by what the same counters read for a plain device copy
+of known size, and records the hash of the stencil source they belong to.
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+import statistics
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+STENCIL_SRC = os.path.join(HERE, "csrc", "stencil.hip")
+
+HORNER_TAGS = (", 1, false>", ", 1, true>", ", 2, false>", ", 2, true>")
+
+
+def stencil_hash() -> str:
+    with open(STENCIL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _counter_rows(d):
+    path = glob.glob(os.path.join(d, "*counter_collection.csv"))[0]
+    return list(csv.DictReader(open(path)))
+
+
+def stats(csv_path, out, command):
+    rows = list(csv.DictReader(open(csv_path)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# rocprofv3 kernel statistics", "", f"Command: `{command}`", "",
+             "| kernel | calls | avg µs | total % |", "|---|---:|---:|---:|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:25]:
+        name = r["Name"].split("(")[0].replace("|", "/")
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{100 * float(r['TotalDurationNs']) / tot:.1f} |")
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
+def traffic(fetch_dir, write_dir, cf_dir, cw_dir, copy_bytes, out, command):
+    def per_kernel(d, pred):
+        agg = collections.defaultdict(list)
+        for r in _counter_rows(d):
+            if pred(r["Kernel_Name"]):
+                agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return agg
+
+    is_stage = lambda k: "stencil_kernel" in k and any(t in k for t in HORNER_TAGS)
+    is_copy = lambda k: "copyBuffer" in k
+    f = per_kernel(fetch_dir, is_stage)
+    w = per_kernel(write_dir, is_stage)
+    cf = [v for vs in per_kernel(cf_dir, is_copy).values() for v in vs if v > 1e5]
+    cw = [v for vs in per_kernel(cw_dir, is_copy).values() for v in vs if v > 1e5]
+    half = copy_bytes / 2.0                  # a copy reads and writes half of it each
+    kf = half / (statistics.mean(cf) * 1024.0)
+    kw = half / (statistics.mean(cw) * 1024.0)
+    fetch = [v for vs in f.values() for v in vs]
+    write = [v for vs in w.values() for v in vs]
+    per_launch = (statistics.mean(fetch) * kf + statistics.mean(write) * kw) * 1024.0
+    res = {"kernel": "stencil_kernel (Horner stages, all launches of the run)",
+           "command": command,
+           "launches": len(fetch),
+           "fetch_scale": kf, "write_scale": kw,
+           "fetch_bytes_per_launch": statistics.mean(fetch) * kf * 1024.0,
+           "write_bytes_per_launch": statistics.mean(write) * kw * 1024.0,
+           "bytes_per_launch": per_launch,
+           "by_kernel": {k.split("(")[0]: {"fetch_KiB": statistics.mean(v),
+                                            "write_KiB": statistics.mean(w.get(k, [0.0]))}
+                         for k, v in f.items()},
+           "stencil_sha256_16": stencil_hash()}
+    json.dump(res, open(out, "w"), indent=1)
+    print(json.dumps(res, indent=1))
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "traffic":
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], float(sys.argv[6]), sys.argv[7],
+                sys.argv[8])
+    else:
+        raise SystemExit(__doc__)
