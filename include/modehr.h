@@ -235,6 +235,75 @@ me_status me_timing_read(me_system* sys, int64_t* launches, double* total_ms,
 const char* me_last_error(const me_system* sys);
 const char* me_strerror(me_status s);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent systems (uneven grids and orbital counts) advanced
+ * together.  Each step is the step of me_propagate_step (sec. 5.1, no
+ * control field) for every system; every orbital of every system is
+ * independent inside the two Taylor exponentials of eq. (aetrs), so each of
+ * their Horner stages runs as ONE persistent stencil launch over all
+ * systems, whose workgroups pull (system, orbital, y-tile, z-slab) work items
+ * from per-XCD device queues.  All systems share one stream and must share
+ * the precision and the Taylor order; grids are limited to 192 points per
+ * row; at most 32 systems.  The adjoint is not available on batched systems.
+ */
+typedef struct me_batch me_batch;
+
+/* Launch shape of the persistent stencil. */
+typedef struct {
+    int32_t block;        /* threads per workgroup: multiple of 64 in [64, 1024];
+                             each system's tile is floor(block / n_x) rows */
+    int32_t wg_per_cu;    /* resident workgroups per compute unit (grid = this x CUs) */
+    int32_t zdiv;         /* z-slabs per orbital column: 1, 2 or 4 */
+    double stage_ms;      /* autotuner: measured time of one Horner stage over the
+                             whole batch (ms); ignored by me_batch_set_tuning */
+} me_batch_tuning;
+
+/* Workspace of a batch: the systems' workspaces (me_workspace_size of each,
+ * 256-byte aligned, in order) plus a small block of work-queue counters. */
+me_status me_batch_workspace_size(const me_params* ps, int32_t n_sys, size_t* bytes);
+
+/* Creates n_sys systems from ps[0..n_sys-1] (host array; each as in
+ * me_init_system) on slices of one caller-owned device workspace, all on
+ * `stream`, and picks an untuned launch shape.  Released by
+ * me_batch_destroy, which also destroys the systems. */
+me_status me_init_batch(const me_params* ps, int32_t n_sys, void* workspace_dev, size_t ws_bytes,
+                        void* stream, me_batch** out);
+
+/* The handle of system i (0-based, caller order) for me_set_state,
+ * me_get_state, me_report, me_density, me_forces, ...  Owned by the batch. */
+me_status me_batch_system(me_batch* b, int32_t i, me_system** out);
+
+/* Sets or reads the launch shape.  ME_EINVAL if it does not fit a system
+ * (8 n_x > 2 block, LDS over 64 KiB) or wg_per_cu exceeds what is resident. */
+me_status me_batch_set_tuning(me_batch* b, const me_batch_tuning* t);
+me_status me_batch_get_tuning(const me_batch* b, me_batch_tuning* t);
+
+/* Autotuner: times one Horner stage over the batch for every launch shape
+ * (block 256..1024, wg_per_cu 1..4, zdiv 1/2/4) that fits, keeps the
+ * fastest, and returns it in *out (nullable).  With cache_path (nullable) a
+ * JSON file keyed by precision, Taylor order and the systems' shapes is
+ * consulted first and updated after a search.  Needs the state of every
+ * system; overwrites their scratch orbitals only.  Synchronises. */
+me_status me_batch_autotune(me_batch* b, const char* cache_path, me_batch_tuning* out);
+
+/* n_steps MD steps of every system.  With use_graph != 0 runs of 6 steps
+ * are replayed from one captured hipGraph (captured on first use, and again
+ * when a system's state changed phase); the first steps after me_set_state
+ * and any remainder run eagerly.  Synchronises at the end and returns
+ * ME_EUNSTABLE / ME_EUNSUPPORTED if a system's last step flagged it. */
+me_status me_propagate_batch(me_batch* b, int32_t n_steps, int32_t use_graph);
+
+/* Event timing of the persistent stencil launches of eager steps (graph
+ * replays and the autotuner are not timed), as me_timing_enable /
+ * me_timing_read. */
+me_status me_batch_timing_enable(me_batch* b, int32_t enable);
+me_status me_batch_timing_read(me_batch* b, int64_t* launches, double* total_ms, double* total_bytes);
+
+/* Text of the last error of a batch call; NULL b gives the last error of a
+ * failed me_init_batch on this thread. */
+const char* me_batch_last_error(const me_batch* b);
+me_status me_batch_destroy(me_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,6 +28,9 @@ SYMBOLS = [
     "me_checkpoint_size", "me_save_checkpoint", "me_load_checkpoint",
     "me_set_static_potential_coarse", "me_dipole", "me_adjoint_begin", "me_adjoint_step",
     "me_adjoint_grad_v",
+    "me_batch_workspace_size", "me_init_batch", "me_batch_system", "me_batch_set_tuning",
+    "me_batch_get_tuning", "me_batch_autotune", "me_propagate_batch", "me_batch_timing_enable",
+    "me_batch_timing_read", "me_batch_last_error", "me_batch_destroy",
 ]
 
 
@@ -47,6 +50,13 @@ class StepReport(ctypes.Structure):
     _fields_ = [(k, c_double) for k in (
         "e_kinetic", "e_local", "e_hartree", "e_xc", "e_nonlocal", "e_ion", "e_ks",
         "e_ion_kinetic", "e_total", "max_norm_dev", "max_force", "charge")] + [("step", c_int64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("block", c_int32), ("wg_per_cu", c_int32), ("zdiv", c_int32), ("stage_ms", c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -99,8 +109,20 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.me_adjoint_begin.argtypes = [c_void_p, c_void_p]
     lib.me_adjoint_step.argtypes = [c_void_p, c_double, POINTER(c_double)]
     lib.me_adjoint_grad_v.argtypes = [c_void_p, c_void_p, c_void_p, c_int32]
+    lib.me_batch_workspace_size.argtypes = [POINTER(Params), c_int32, POINTER(c_size_t)]
+    lib.me_init_batch.argtypes = [POINTER(Params), c_int32, c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]
+    lib.me_batch_system.argtypes = [c_void_p, c_int32, POINTER(c_void_p)]
+    lib.me_batch_set_tuning.argtypes = [c_void_p, POINTER(BatchTuning)]
+    lib.me_batch_get_tuning.argtypes = [c_void_p, POINTER(BatchTuning)]
+    lib.me_batch_autotune.argtypes = [c_void_p, c_char_p, POINTER(BatchTuning)]
+    lib.me_propagate_batch.argtypes = [c_void_p, c_int32, c_int32]
+    lib.me_batch_timing_enable.argtypes = [c_void_p, c_int32]
+    lib.me_batch_timing_read.argtypes = [c_void_p, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]
+    lib.me_batch_last_error.restype = c_char_p
+    lib.me_batch_last_error.argtypes = [c_void_p]
+    lib.me_batch_destroy.argtypes = [c_void_p]
     for s in SYMBOLS:
-        if s not in ("me_last_error", "me_strerror"):
+        if s not in ("me_last_error", "me_strerror", "me_batch_last_error"):
             getattr(lib, s).restype = c_int32
     _lib = lib
     return lib
@@ -162,7 +184,7 @@ def workspace_size(p: Params) -> int:
 class System:
     """One system on one GPU; device memory from torch, work on torch's current stream."""
 
-    def __init__(self, params: Params, keep=None, device="cuda:0"):
+    def __init__(self, params: Params, keep=None, device="cuda:0", handle=None, stream=None):
         import torch
         self.torch = torch
         self.lib = load()
@@ -173,6 +195,11 @@ class System:
         self.N = params.n[0] * params.n[1] * params.n[2]
         self.n_orb = params.n_orb
         self.n_ions = params.n_ions
+        self._owned = handle is None
+        if handle is not None:          # a system owned by a Batch, on the batch's stream
+            self.h = handle
+            self.stream = stream
+            return
         size = workspace_size(params)
         self.workspace = torch.empty(size, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)
@@ -186,12 +213,26 @@ class System:
 
     # -------------------------------------------------------------- helpers
     def _check(self, st: int):
+        self._post()
         if st != ME_OK:
             raise ModehrError(st, self.lib.me_last_error(self.h).decode())
 
+    def _pre(self):
+        """Order the handle's stream after torch's current stream (inputs ready)."""
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+
+    def _post(self):
+        """Order torch's current stream after the handle's (outputs ready)."""
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
+
     def close(self):
         if getattr(self, "h", None):
-            self.lib.me_destroy(self.h)
+            if self._owned:
+                self.lib.me_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -214,23 +255,24 @@ class System:
         psi = self._orbitals(psi)
         if psi.shape[0] != self.n_orb:
             raise ValueError("set_state needs n_orb orbitals")
-        self._check(self.lib.me_set_state(self.h, c_void_p(psi.data_ptr()), c_int64(self.N)))
+        self._check(self._pre() or self.lib.me_set_state(self.h, c_void_p(psi.data_ptr()), c_int64(self.N)))
 
     def get_state(self):
         out = self.torch.empty((self.n_orb, self.N), dtype=self.cdtype, device=self.device)
-        self._check(self.lib.me_get_state(self.h, c_void_p(out.data_ptr()), c_int64(self.N)))
+        self._check(self._pre() or self.lib.me_get_state(self.h, c_void_p(out.data_ptr()), c_int64(self.N)))
         return out
 
     def apply_H(self, psi):
         psi = self._orbitals(psi)
         out = self.torch.empty_like(psi)
-        self._check(self.lib.me_apply_H(self.h, c_void_p(psi.data_ptr()), c_void_p(out.data_ptr()),
+        self._check(self._pre() or self.lib.me_apply_H(self.h, c_void_p(psi.data_ptr()), c_void_p(out.data_ptr()),
                                         c_int32(psi.shape[0]), c_int64(self.N)))
         return out
 
     def step(self, ctrl: Optional[float] = None, report: bool = False):
         c = c_double(ctrl) if ctrl is not None else None
         rep = StepReport() if report else None
+        self._pre()
         st = self.lib.me_propagate_step(self.h, ctypes.byref(c) if c is not None else None,
                                         ctypes.byref(rep) if rep is not None else None)
         self._check(st)
@@ -238,68 +280,68 @@ class System:
 
     def report(self) -> dict:
         rep = StepReport()
-        self._check(self.lib.me_report(self.h, ctypes.byref(rep)))
+        self._check(self._pre() or self.lib.me_report(self.h, ctypes.byref(rep)))
         return rep.as_dict()
 
     def sync(self):
-        self._check(self.lib.me_sync(self.h))
+        self._check(self._pre() or self.lib.me_sync(self.h))
 
     def density(self):
         out = self.torch.empty(self.N, dtype=self.torch.float64, device=self.device)
-        self._check(self.lib.me_density(self.h, c_void_p(out.data_ptr())))
+        self._check(self._pre() or self.lib.me_density(self.h, c_void_p(out.data_ptr())))
         return out
 
     def forces(self) -> np.ndarray:
         f = np.zeros((self.n_ions, 3))
-        self._check(self.lib.me_forces(self.h, _dptr(f)))
+        self._check(self._pre() or self.lib.me_forces(self.h, _dptr(f)))
         return f
 
     def ions(self):
         p = np.zeros((self.n_ions, 3))
         v = np.zeros((self.n_ions, 3))
-        self._check(self.lib.me_get_ions(self.h, _dptr(p), _dptr(v)))
+        self._check(self._pre() or self.lib.me_get_ions(self.h, _dptr(p), _dptr(v)))
         return p, v
 
     def potential(self, which: int):
         out = self.torch.empty(self.N, dtype=self.torch.float64, device=self.device)
-        self._check(self.lib.me_get_potential(self.h, c_int32(which), c_void_p(out.data_ptr())))
+        self._check(self._pre() or self.lib.me_get_potential(self.h, c_int32(which), c_void_p(out.data_ptr())))
         return out
 
     def set_static_potential(self, dv):
         if dv is None:
-            self._check(self.lib.me_set_static_potential(self.h, None))
+            self._check(self._pre() or self.lib.me_set_static_potential(self.h, None))
             return
         dv = self.torch.as_tensor(dv, dtype=self.torch.float64).to(self.device).reshape(-1).contiguous()
         self._dv = dv
-        self._check(self.lib.me_set_static_potential(self.h, c_void_p(dv.data_ptr())))
+        self._check(self._pre() or self.lib.me_set_static_potential(self.h, c_void_p(dv.data_ptr())))
 
     # -------------------------------------------------------------- adjoint
     def checkpoint_size(self) -> int:
         out = c_size_t(0)
-        self._check(self.lib.me_checkpoint_size(self.h, ctypes.byref(out)))
+        self._check(self._pre() or self.lib.me_checkpoint_size(self.h, ctypes.byref(out)))
         return out.value
 
     def new_checkpoint(self):
         return self.torch.empty(self.checkpoint_size(), dtype=self.torch.uint8, device=self.device)
 
     def save_checkpoint(self, buf):
-        self._check(self.lib.me_save_checkpoint(self.h, c_void_p(buf.data_ptr())))
+        self._check(self._pre() or self.lib.me_save_checkpoint(self.h, c_void_p(buf.data_ptr())))
 
     def load_checkpoint(self, buf):
-        self._check(self.lib.me_load_checkpoint(self.h, c_void_p(buf.data_ptr())))
+        self._check(self._pre() or self.lib.me_load_checkpoint(self.h, c_void_p(buf.data_ptr())))
 
     def set_static_potential_coarse(self, coarse):
         if coarse is None:
-            self._check(self.lib.me_set_static_potential_coarse(self.h, None, c_int32(1)))
+            self._check(self._pre() or self.lib.me_set_static_potential_coarse(self.h, None, c_int32(1)))
             return
         c = self.torch.as_tensor(coarse, dtype=self.torch.float64).to(self.device).contiguous()
         self._coarse = c
-        self._check(self.lib.me_set_static_potential_coarse(self.h, c_void_p(c.data_ptr()),
+        self._check(self._pre() or self.lib.me_set_static_potential_coarse(self.h, c_void_p(c.data_ptr()),
                                                             c_int32(c.shape[0])))
 
     def dipole(self) -> float:
         d = c_double(0)
-        self._check(self.lib.me_dipole(self.h, ctypes.byref(d)))
+        self._check(self._pre() or self.lib.me_dipole(self.h, ctypes.byref(d)))
         return d.value
 
     def adjoint_begin(self, rhobar=None):
@@ -308,29 +350,111 @@ class System:
             rhobar = self.torch.as_tensor(rhobar, dtype=self.torch.float64).to(self.device).contiguous()
             self._rhobar = rhobar
             ptr = c_void_p(rhobar.data_ptr())
-        self._check(self.lib.me_adjoint_begin(self.h, ptr))
+        self._check(self._pre() or self.lib.me_adjoint_begin(self.h, ptr))
 
     def adjoint_step(self, ctrl: float) -> float:
         g = c_double(0)
-        self._check(self.lib.me_adjoint_step(self.h, c_double(ctrl), ctypes.byref(g)))
+        self._check(self._pre() or self.lib.me_adjoint_step(self.h, c_double(ctrl), ctypes.byref(g)))
         return g.value
 
     def adjoint_grad_v(self, m: Optional[int] = None):
         t = self.torch
         if m is None:
             out = t.empty(self.N, dtype=t.float64, device=self.device)
-            self._check(self.lib.me_adjoint_grad_v(self.h, c_void_p(out.data_ptr()), None, c_int32(0)))
+            self._check(self._pre() or self.lib.me_adjoint_grad_v(self.h, c_void_p(out.data_ptr()), None, c_int32(0)))
         else:
             out = t.empty((m, m, m), dtype=t.float64, device=self.device)
-            self._check(self.lib.me_adjoint_grad_v(self.h, None, c_void_p(out.data_ptr()), c_int32(m)))
+            self._check(self._pre() or self.lib.me_adjoint_grad_v(self.h, None, c_void_p(out.data_ptr()), c_int32(m)))
         return out
 
     def timing_enable(self, on: bool = True):
-        self._check(self.lib.me_timing_enable(self.h, c_int32(1 if on else 0)))
+        self._check(self._pre() or self.lib.me_timing_enable(self.h, c_int32(1 if on else 0)))
 
     def timing_read(self):
         n = c_int64(0)
         ms = c_double(0)
         by = c_double(0)
-        self._check(self.lib.me_timing_read(self.h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+        self._check(self._pre() or self.lib.me_timing_read(self.h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+        return n.value, ms.value, by.value
+
+
+class Batch:
+    """Several systems advanced together (persistent stencil launches, graph
+    replay); device memory from torch, work on torch's current stream.
+    ``systems[i]`` is a System view of system i, owned by the batch."""
+
+    def __init__(self, params_list, keep=None, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.device = torch.device(device)
+        n = len(params_list)
+        self._params = (Params * n)(*params_list)
+        self._keep = keep
+        size = c_size_t(0)
+        st = self.lib.me_batch_workspace_size(self._params, c_int32(n), ctypes.byref(size))
+        if st != ME_OK:
+            raise ModehrError(st, self.lib.me_batch_last_error(None).decode())
+        self.workspace = torch.empty(size.value, dtype=torch.uint8, device=self.device)
+        # a stream of its own (default priority): graphs cannot be captured
+        # on the legacy default stream
+        self.stream = torch.cuda.Stream(self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        h = c_void_p()
+        st = self.lib.me_init_batch(self._params, c_int32(n), c_void_p(self.workspace.data_ptr()), size,
+                                    c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != ME_OK:
+            raise ModehrError(st, self.lib.me_batch_last_error(None).decode())
+        self.h = h
+        self.systems = []
+        for i in range(n):
+            sh = c_void_p()
+            self._check(self.lib.me_batch_system(self.h, c_int32(i), ctypes.byref(sh)))
+            self.systems.append(System(params_list[i], device=device, handle=sh, stream=self.stream))
+
+    def _check(self, st: int):
+        self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        if st != ME_OK:
+            raise ModehrError(st, self.lib.me_batch_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            for s in self.systems:
+                s.close()
+            self.lib.me_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def propagate(self, n_steps: int, use_graph: bool = True):
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        self._check(self.lib.me_propagate_batch(self.h, c_int32(n_steps), c_int32(1 if use_graph else 0)))
+
+    def tuning(self) -> dict:
+        t = BatchTuning()
+        self._check(self.lib.me_batch_get_tuning(self.h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, block: int, wg_per_cu: int, zdiv: int = 1):
+        t = BatchTuning(block, wg_per_cu, zdiv, 0.0)
+        self._check(self.lib.me_batch_set_tuning(self.h, ctypes.byref(t)))
+
+    def autotune(self, cache_path: Optional[str] = None) -> dict:
+        t = BatchTuning()
+        path = cache_path.encode() if cache_path else None
+        self._check(self.lib.me_batch_autotune(self.h, path, ctypes.byref(t)))
+        return t.as_dict()
+
+    def timing_enable(self, on: bool = True):
+        self._check(self.lib.me_batch_timing_enable(self.h, c_int32(1 if on else 0)))
+
+    def timing_read(self):
+        n = c_int64(0)
+        ms = c_double(0)
+        by = c_double(0)
+        self._check(self.lib.me_batch_timing_read(self.h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
         return n.value, ms.value, by.value

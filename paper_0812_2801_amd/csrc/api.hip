@@ -82,6 +82,7 @@ struct Geometry {
     size_t bc;        // bytes per complex
     size_t br;        // bytes per real of the compute precision
     int px, ty, nyt, zchunk, nzc;
+    int64_t norm_cap;  // norm partials per orbital (this kernel's tiles, or a batch's)
     int kcap;
     int64_t ucap;      // upper bound of projector-covered grid points
     int64_t nscan;     // point-numbering blocks
@@ -178,6 +179,7 @@ Geometry make_geometry(const me_params* p) {
     g.nyt = g.ny / g.ty;
     g.zchunk = choose_zchunk(g.nz, (int64_t)g.n_orb * g.nyt);
     g.nzc = g.nz / g.zchunk;
+    g.norm_cap = std::max<int64_t>((int64_t)g.nyt * g.nzc, 4 * (int64_t)g.ny);
     const int m = (int)std::ceil(p->kb_rcut / p->h);
     g.m = m;
     int kc = 1;
@@ -273,7 +275,7 @@ static Layout carve(const Geometry& g, char* base) {
     L.erec_part = c.take<double>((size_t)((std::max(1, g.ewald_ng) + 255) / 256) * 8);
     L.ewald_gv = c.take<double>((size_t)std::max(1, g.ewald_ng) * 3 * 8);
     L.ewald_wv = c.take<double>((size_t)std::max(1, g.ewald_ng) * 8);
-    L.norm_part = c.take<double>((size_t)g.n_orb * g.nyt * g.nzc * 8);
+    L.norm_part = c.take<double>((size_t)g.n_orb * g.norm_cap * 8);
     L.fix_part = c.take<double>((size_t)g.n_orb * fixup_blocks(g.ucap) * 8);
     L.kin_part = c.take<double>((size_t)g.n_orb * g.nyt * g.nzc * 8);
     L.norms = c.take<double>((size_t)g.n_orb * 8);
@@ -317,6 +319,7 @@ struct me_system {
     rocfft_execution_info info = nullptr;
     int tab_cur = 0;
     int hist_count = 0, hist_newest = 0;
+    int norm_tiles = 0;          // tiles per orbital of the last norm partials
     bool has_state = false;
     bool static_set = false;
     int64_t step = 0;
@@ -527,6 +530,7 @@ me_status exponential(me_system* sys, const T* veff, int t, bool last) {
         a.alpha = (T)(-tau / k);
         const bool norm = last && k == 1;
         a.partial = norm ? sys->w.norm_part : nullptr;
+        if (norm) sys->norm_tiles = g.nyt * g.nzc;
         const int mode = k == K ? MODE_HORNER_FIRST : MODE_HORNER;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (sys->timing) {
@@ -602,7 +606,7 @@ me_status finalize(me_system* sys, bool with_norm, bool energy) {
     f.norms = sys->w.norms;
     f.nl_flag = g.n_ions > 0 ? sys->w.tflag[sys->tab_cur] : nullptr;
     f.n_orb = g.n_orb;
-    f.norm_tiles = g.nyt * g.nzc;
+    f.norm_tiles = sys->norm_tiles;
     f.norm_tol = g.f64 ? 1e-6 : 1e-5;
     f.dv = sys->prm.h * sys->prm.h * sys->prm.h;
     f.occ = sys->prm.occ;
@@ -807,8 +811,8 @@ me_status initial_fields(me_system* sys) {
     return ME_OK;
 }
 
-template <typename T>
-me_status step_impl(me_system* sys, double eps, bool energy) {
+// steps 1-2 of a step: ions moved, H(t+dt) prepared
+me_status step_pre(me_system* sys, double eps) {
     const Geometry& g = sys->g;
     const int next = sys->tab_cur ^ 1;
     // 1. ions: R(t+dt) by velocity Verlet
@@ -818,9 +822,13 @@ me_status step_impl(me_system* sys, double eps, bool energy) {
     CHK(ion_fields(sys, sys->w.pos_next, sys->w.vloc_next));
     CHK(build_tables(sys, sys->w.pos_next, next));
     CHK(make_veff(sys, eps, true));
-    // 3-4. AETRS: exp(-i tau H(t+dt)) exp(-i tau H(t))
-    CHK(two_exponentials<T>(sys));
-    // 5. density, Hartree + exchange, forces at the new positions
+    return ME_OK;
+}
+
+// step 5: density, fields and forces of the propagated orbitals, ions finished
+me_status step_post(me_system* sys, bool energy) {
+    const Geometry& g = sys->g;
+    const int next = sys->tab_cur ^ 1;
     CHK(density_vhxc(sys, energy));
     CHK(forces_parts(sys, sys->w.pos_next, next));
     HIPCHK(launch_ions_finish(sys->w.pos, sys->w.vel, sys->w.frc, sys->w.pos_next, sys->w.floc, sys->w.fnl, sys->w.fion, sys->w.mass, g.n_ions, sys->prm.dt,
@@ -829,6 +837,492 @@ me_status step_impl(me_system* sys, double eps, bool energy) {
     sys->tab_cur = next;
     sys->step += 1;
     return finalize(sys, true, energy);
+}
+
+template <typename T>
+me_status step_impl(me_system* sys, double eps, bool energy) {
+    CHK(step_pre(sys, eps));
+    // 3-4. AETRS: exp(-i tau H(t+dt)) exp(-i tau H(t))
+    CHK(two_exponentials<T>(sys));
+    return step_post(sys, energy);
+}
+
+}  // namespace
+
+// ================================================================== batches
+// Many independent systems advanced together: per-system work (ions, fields,
+// tables, gathers, fix-ups, forces) is enqueued system by system, and every
+// Horner stage of all systems is one persistent stencil launch.  A run of
+// BATCH_GRAPH_STEPS steps can be captured once as a hipGraph and replayed.
+
+// The host-side state of a system changes with period 2 (projector tables,
+// V_loc buffers, the K = 1 orbital swap) and 3 (v_Hxc history ring), so six
+// steps bring every pointer a step uses back to where it was.
+constexpr int BATCH_GRAPH_STEPS = 6;
+
+struct BatchTile {
+    int ty, nyt, zchunk, nzc, items;
+};
+
+struct PhaseKey {
+    int tab_cur, hist_newest, hist_count;
+    bool static_set;
+    const void *psi, *bufA;
+    const double* vloc_cur;
+    bool operator==(const PhaseKey& o) const {
+        return tab_cur == o.tab_cur && hist_newest == o.hist_newest && hist_count == o.hist_count &&
+               static_set == o.static_set && psi == o.psi && bufA == o.bufA && vloc_cur == o.vloc_cur;
+    }
+};
+
+struct me_batch {
+    std::vector<me_system*> sys;   // caller order
+    std::vector<int> order;        // launch order: largest work items first
+    hipStream_t stream = nullptr;
+    bool f64 = false;
+    int K = 4;
+    int* counters = nullptr;       // device: [2 K + 1][QUEUE_SLOTS]
+    int n_cu = 256;
+    me_batch_tuning tune{};
+    bool tuned = false;            // tuning set explicitly or by the autotuner
+    std::vector<BatchTile> tile;   // caller order
+    size_t lds = 0;
+    int grid = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<PhaseKey> phase;   // host state the graph was captured at
+    bool capturing = false;
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<double> ev_bytes;
+    std::vector<hipEvent_t> ev_pool;
+    std::string err;
+};
+
+namespace {
+
+constexpr int QUEUE_SLOTS = 8;     // counters per persistent launch (one per XCD queue)
+
+#define BHIP(expr)                                                                     \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            b->err = std::string(#expr) + ": " + hipGetErrorString(e_);                 \
+            return ME_EDEVICE;                                                         \
+        }                                                                              \
+    } while (0)
+
+// a per-system call inside a batch operation: its error text moves to the batch
+#define BSYS(expr, s)                                                                  \
+    do {                                                                               \
+        me_status s_ = (expr);                                                         \
+        if (s_ != ME_OK) {                                                             \
+            b->err = (s)->err;                                                         \
+            return s_;                                                                 \
+        }                                                                              \
+    } while (0)
+
+int batch_hj(const me_batch* b, int block) {
+    int hj = 1;
+    for (const me_system* s : b->sys)
+        if (8 * s->g.nx > block) hj = 2;
+    return hj;
+}
+
+// Tiles of every system for a tuning; false if the tuning cannot run them.
+bool batch_tiles(const me_batch* b, const me_batch_tuning& t, std::vector<BatchTile>& out, size_t& lds) {
+    if (t.block < 64 || t.block > 1024 || t.block % 64) return false;
+    if (t.zdiv != 1 && t.zdiv != 2 && t.zdiv != 4) return false;
+    out.clear();
+    lds = 0;
+    for (const me_system* s : b->sys) {
+        const Geometry& g = s->g;
+        if (8 * g.nx > 2 * t.block) return false;
+        int ty = std::min(g.ny, t.block / g.nx);
+        while (ty > 1 && 2 * (size_t)(ty + 8) * g.nx * g.bc > 64 * 1024) --ty;
+        if (ty < 1 || 2 * (size_t)(ty + 8) * g.nx * g.bc > 64 * 1024) return false;
+        BatchTile bt{};
+        bt.ty = ty;
+        bt.nyt = (g.ny + ty - 1) / ty;
+        bt.zchunk = (g.nz + t.zdiv - 1) / t.zdiv;
+        bt.nzc = (g.nz + bt.zchunk - 1) / bt.zchunk;
+        if ((int64_t)bt.nyt * bt.nzc > g.norm_cap) return false;
+        const int64_t items = (int64_t)g.n_orb * bt.nyt * bt.nzc;
+        if (items > (1 << 26)) return false;
+        bt.items = (int)items;
+        lds = std::max(lds, 2 * (size_t)(ty + 8) * g.nx * g.bc);
+        out.push_back(bt);
+    }
+    return true;
+}
+
+template <typename T>
+int batch_max_wpc(const me_batch* b, int block, size_t lds) {
+    int w = 0;
+    if (batch_stencil_occupancy<T>(block, lds, batch_hj(b, block), &w) != hipSuccess) return 0;
+    return w;
+}
+
+me_status batch_apply_tuning(me_batch* b, const me_batch_tuning& t) {
+    std::vector<BatchTile> tiles;
+    size_t lds = 0;
+    if (!batch_tiles(b, t, tiles, lds)) {
+        b->err = "tuning does not fit this batch (block, zdiv or LDS)";
+        return ME_EINVAL;
+    }
+    const int wmax = b->f64 ? batch_max_wpc<double>(b, t.block, lds) : batch_max_wpc<float>(b, t.block, lds);
+    if (wmax < 1 || t.wg_per_cu < 1 || t.wg_per_cu > wmax) {
+        b->err = "wg_per_cu must be in [1, " + std::to_string(wmax) + "] for this block size";
+        return ME_EINVAL;
+    }
+    b->tune = t;
+    b->tile = tiles;
+    b->lds = lds;
+    b->grid = t.wg_per_cu * b->n_cu;
+    if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
+    return ME_OK;
+}
+
+// the untuned choice: 768 threads (1024 where a row needs it), two
+// workgroups per CU where they fit, whole z columns
+me_status batch_default_tuning(me_batch* b) {
+    me_batch_tuning t{};
+    t.zdiv = 1;
+    for (int block : {768, 1024, 512}) {
+        t.block = block;
+        std::vector<BatchTile> tiles;
+        size_t lds = 0;
+        if (!batch_tiles(b, t, tiles, lds)) continue;
+        const int wmax = b->f64 ? batch_max_wpc<double>(b, block, lds) : batch_max_wpc<float>(b, block, lds);
+        if (wmax < 1) continue;
+        t.wg_per_cu = std::min(2, wmax);
+        return batch_apply_tuning(b, t);
+    }
+    b->err = "no workgroup shape fits this batch";
+    return ME_EUNSUPPORTED;
+}
+
+hipEvent_t batch_event(me_batch* b) {
+    if (!b->ev_pool.empty()) {
+        hipEvent_t e = b->ev_pool.back();
+        b->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// One persistent launch: stage k of exponential e over all systems.
+// u[i] / out[i] / psi0 = psi of system i (caller order); counter slot `slot`.
+template <typename T>
+me_status batch_stage(me_batch* b, const std::vector<const cx_t<T>*>& u, const std::vector<cx_t<T>*>& out,
+                      int e, int k, bool norm, int slot, int mode) {
+    using C = cx_t<T>;
+    BatchStencilArgs<T> a{};
+    a.n_sys = (int)b->sys.size();
+    a.counter = b->counters + slot * QUEUE_SLOTS;
+    int item = 0;
+    double bytes = 0.0;
+    for (int j = 0; j < a.n_sys; ++j) {
+        const int i = b->order[j];
+        me_system* s = b->sys[i];
+        const Geometry& g = s->g;
+        const BatchTile& bt = b->tile[i];
+        BatchSys<T>& d = a.sys[j];
+        d.u = u[i];
+        d.psi0 = (const C*)s->w.psi;
+        d.out = out[i];
+        d.v = (const T*)(e == 0 ? s->w.veff0 : s->w.veff1);
+        d.partial = norm ? s->w.norm_part : nullptr;
+        d.stride = g.stride;
+        d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
+        d.ty = bt.ty; d.nyt = bt.nyt;
+        d.zchunk = bt.zchunk; d.nzc = bt.nzc;
+        d.item0 = item;
+        d.items = bt.items;
+        item += bt.items;
+        d.kin = (T)(-0.5 / (s->prm.h * s->prm.h));
+        d.alpha = (T)(-(s->prm.dt / (2.0 * s->prm.mu)) / k);
+        if (norm) s->norm_tiles = bt.nyt * bt.nzc;
+        const double streams = mode == MODE_HORNER_FIRST ? 2.0 : 3.0;
+        bytes += streams * g.bc * (double)g.N * g.n_orb + (double)g.br * g.N;
+    }
+    a.total = item;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool timed = b->timing && !b->capturing;
+    if (timed) {
+        e0 = batch_event(b);
+        e1 = batch_event(b);
+        if (e0 && e1) BHIP(hipEventRecord(e0, b->stream));
+    }
+    BHIP(launch_batch_stencil<T>(a, mode, norm, b->tune.block, b->grid, b->lds, b->stream));
+    if (timed && e0 && e1) {
+        BHIP(hipEventRecord(e1, b->stream));
+        b->ev.emplace_back(e0, e1);
+        b->ev_bytes.push_back(bytes);
+    }
+    return ME_OK;
+}
+
+// One Taylor exponential of every system (e = 0: H(t), e = 1: H(t+dt)),
+// stage by stage as in exponential(): per-system gathers, one persistent
+// stencil launch, per-system fix-ups.
+template <typename T>
+me_status batch_exponential(me_batch* b, int e, bool last) {
+    using C = cx_t<T>;
+    const int K = b->K;
+    const int n = (int)b->sys.size();
+    std::vector<const C*> u(n);
+    std::vector<C*> out(n);
+    for (int i = 0; i < n; ++i) u[i] = (const C*)b->sys[i]->w.psi;
+    int nb = 0;
+    for (int k = K; k >= 1; --k) {
+        const bool norm = last && k == 1;
+        for (int i = 0; i < n; ++i) {
+            me_system* s = b->sys[i];
+            const int t = e == 0 ? s->tab_cur : s->tab_cur ^ 1;
+            C* bufs[2] = {(C*)s->w.bufA, (C*)s->w.bufB};
+            out[i] = (k == 1 && K > 1) ? (C*)s->w.psi : bufs[nb];
+            const double ekb_h3 = s->prm.kb_energy * s->prm.h * s->prm.h * s->prm.h;
+            BSYS(gather<T>(s, u[i], s->g.stride, s->g.n_orb, t, ekb_h3), s);
+        }
+        CHK(batch_stage<T>(b, u, out, e, k, norm, e * K + (K - k), k == K ? MODE_HORNER_FIRST : MODE_HORNER));
+        for (int i = 0; i < n; ++i) {
+            me_system* s = b->sys[i];
+            const Geometry& g = s->g;
+            const int t = e == 0 ? s->tab_cur : s->tab_cur ^ 1;
+            const double tau = s->prm.dt / (2.0 * s->prm.mu);
+            if (g.n_ions > 0)
+                BHIP(launch_kb_fixup<T>(out[i], g.stride, g.n_orb, tables(s, t), (const C*)s->w.cnl, 0.0,
+                                        -tau / k, norm ? s->w.fix_part : nullptr, s->stream));
+            u[i] = out[i];
+        }
+        nb ^= 1;
+    }
+    if (K == 1)
+        for (me_system* s : b->sys) std::swap(s->w.psi, s->w.bufA);
+    return ME_OK;
+}
+
+template <typename T>
+me_status batch_step(me_batch* b) {
+    BHIP(launch_zero_i32(b->counters, 2 * b->K * QUEUE_SLOTS, b->stream));
+    for (me_system* s : b->sys) BSYS(step_pre(s, 0.0), s);
+    CHK(batch_exponential<T>(b, 0, false));
+    CHK(batch_exponential<T>(b, 1, true));
+    for (me_system* s : b->sys) BSYS(step_post(s, false), s);
+    return ME_OK;
+}
+
+me_status batch_step_any(me_batch* b) {
+    return b->f64 ? batch_step<double>(b) : batch_step<float>(b);
+}
+
+std::vector<PhaseKey> batch_phase(const me_batch* b) {
+    std::vector<PhaseKey> p;
+    for (const me_system* s : b->sys)
+        p.push_back(PhaseKey{s->tab_cur, s->hist_newest, s->hist_count, s->static_set, s->w.psi, s->w.bufA,
+                             s->w.vloc_cur});
+    return p;
+}
+
+void batch_drop_graph(me_batch* b) {
+    if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
+    b->phase.clear();
+}
+
+// Capture BATCH_GRAPH_STEPS steps as one graph at the current host state.
+// Capturing runs the host side of those steps (no device work), which
+// returns every per-system pointer and ring index to where it started.
+me_status batch_capture(me_batch* b) {
+    batch_drop_graph(b);
+    const std::vector<PhaseKey> start = batch_phase(b);
+    std::vector<int64_t> steps;
+    for (me_system* s : b->sys) steps.push_back(s->step);
+    BHIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
+    b->capturing = true;
+    me_status st = ME_OK;
+    for (int i = 0; i < BATCH_GRAPH_STEPS && st == ME_OK; ++i) st = batch_step_any(b);
+    b->capturing = false;
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(b->stream, &graph);
+    for (size_t i = 0; i < b->sys.size(); ++i) b->sys[i]->step = steps[i];
+    if (st != ME_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return st;
+    }
+    if (ec != hipSuccess) {
+        b->err = std::string("hipStreamEndCapture: ") + hipGetErrorString(ec);
+        return ME_EDEVICE;
+    }
+    if (!(batch_phase(b) == start)) {
+        hipGraphDestroy(graph);
+        b->err = "internal error: host state did not return after a graph period";
+        return ME_EDEVICE;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        hipGraphDestroy(graph);
+        b->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(ei);
+        return ME_EDEVICE;
+    }
+    b->graph = graph;
+    b->exec = exec;
+    b->phase = start;
+    return ME_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+// Candidates are timed on one Horner stage over the whole batch (u = psi0 =
+// psi, out = bufA, which the next step overwrites anyway).  Results are kept
+// in a small JSON file keyed by precision, Taylor order and the shapes.
+
+std::string batch_key(const me_batch* b) {
+    std::string k = b->sys[0]->prm.precision == ME_F64 ? "f64" : "f32";
+    k += "/K" + std::to_string(b->K);
+    for (int i : b->order) {
+        const me_system* s = b->sys[i];
+        k += "/" + std::to_string(s->g.nx) + "x" + std::to_string(s->g.ny) + "x" + std::to_string(s->g.nz) +
+             ":" + std::to_string(s->g.n_orb);
+    }
+    return k;
+}
+
+bool json_field(const std::string& line, const char* name, double* v) {
+    const std::string pat = std::string("\"") + name + "\":";
+    const size_t p = line.find(pat);
+    if (p == std::string::npos) return false;
+    char* end = nullptr;
+    *v = std::strtod(line.c_str() + p + pat.size(), &end);
+    return end != line.c_str() + p + pat.size();
+}
+
+// entries of the cache file: one `"key": {...}` per line
+std::vector<std::pair<std::string, std::string>> cache_read(const char* path) {
+    std::vector<std::pair<std::string, std::string>> out;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return out;
+    std::string line;
+    char buf[4096];
+    while (std::fgets(buf, sizeof buf, f)) {
+        line = buf;
+        const size_t q0 = line.find('"');
+        if (q0 == std::string::npos) continue;
+        const size_t q1 = line.find('"', q0 + 1);
+        const size_t br = line.find('{', q1 == std::string::npos ? 0 : q1);
+        const size_t be = line.rfind('}');
+        if (q1 == std::string::npos || br == std::string::npos || be == std::string::npos || be < br) continue;
+        out.emplace_back(line.substr(q0 + 1, q1 - q0 - 1), line.substr(br, be - br + 1));
+    }
+    std::fclose(f);
+    return out;
+}
+
+bool cache_lookup(const char* path, const std::string& key, me_batch_tuning* t) {
+    for (const auto& kv : cache_read(path)) {
+        if (kv.first != key) continue;
+        double blk, wpc, zd, ms;
+        if (json_field(kv.second, "block", &blk) && json_field(kv.second, "wg_per_cu", &wpc) &&
+            json_field(kv.second, "zdiv", &zd) && json_field(kv.second, "stage_ms", &ms)) {
+            t->block = (int32_t)blk;
+            t->wg_per_cu = (int32_t)wpc;
+            t->zdiv = (int32_t)zd;
+            t->stage_ms = ms;
+            return true;
+        }
+    }
+    return false;
+}
+
+void cache_store(const char* path, const std::string& key, const me_batch_tuning& t) {
+    auto entries = cache_read(path);
+    char val[256];
+    std::snprintf(val, sizeof val, "{\"block\": %d, \"wg_per_cu\": %d, \"zdiv\": %d, \"stage_ms\": %.6f}", t.block,
+                  t.wg_per_cu, t.zdiv, t.stage_ms);
+    bool found = false;
+    for (auto& kv : entries)
+        if (kv.first == key) { kv.second = val; found = true; }
+    if (!found) entries.emplace_back(key, val);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "{\n");
+    for (size_t i = 0; i < entries.size(); ++i)
+        std::fprintf(f, "\"%s\": %s%s\n", entries[i].first.c_str(), entries[i].second.c_str(),
+                     i + 1 < entries.size() ? "," : "");
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);
+}
+
+template <typename T>
+me_status batch_time_stage(me_batch* b, int reps, double* ms) {
+    using C = cx_t<T>;
+    const int n = (int)b->sys.size();
+    std::vector<const C*> u(n);
+    std::vector<C*> out(n);
+    for (int i = 0; i < n; ++i) {
+        u[i] = (const C*)b->sys[i]->w.psi;
+        out[i] = (C*)b->sys[i]->w.bufA;
+    }
+    const int slot = 2 * b->K;                 // the tuning slot, outside a step's range
+    const bool timing = b->timing;
+    b->timing = false;
+    hipEvent_t e0 = batch_event(b), e1 = batch_event(b);
+    if (!e0 || !e1) { b->timing = timing; b->err = "hipEventCreate failed"; return ME_EDEVICE; }
+    me_status st = ME_OK;
+    for (int r = 0; r <= reps && st == ME_OK; ++r) {
+        if (r == 1) BHIP(hipEventRecord(e0, b->stream));
+        BHIP(launch_zero_i32(b->counters + slot * QUEUE_SLOTS, QUEUE_SLOTS, b->stream));
+        st = batch_stage<T>(b, u, out, 0, 1, false, slot, MODE_HORNER);
+    }
+    b->timing = timing;
+    if (st != ME_OK) return st;
+    BHIP(hipEventRecord(e1, b->stream));
+    BHIP(hipEventSynchronize(e1));
+    float t = 0.f;
+    BHIP(hipEventElapsedTime(&t, e0, e1));
+    b->ev_pool.push_back(e0);
+    b->ev_pool.push_back(e1);
+    *ms = t / reps;
+    return ME_OK;
+}
+
+template <typename T>
+me_status batch_autotune(me_batch* b, me_batch_tuning* best) {
+    best->stage_ms = 0.0;
+    bool any = false;
+    for (int block : {256, 512, 768, 1024}) {
+        for (int zdiv : {1, 2, 4}) {
+            me_batch_tuning t{};
+            t.block = block;
+            t.zdiv = zdiv;
+            std::vector<BatchTile> tiles;
+            size_t lds = 0;
+            if (!batch_tiles(b, t, tiles, lds)) continue;
+            const int wmax = std::min(4, batch_max_wpc<T>(b, block, lds));
+            for (int w = 1; w <= wmax; ++w) {
+                t.wg_per_cu = w;
+                if (batch_apply_tuning(b, t) != ME_OK) continue;
+                double ms = 0.0;
+                CHK(batch_time_stage<T>(b, 3, &ms));
+                if (!any || ms < best->stage_ms) {
+                    *best = t;
+                    best->stage_ms = ms;
+                    any = true;
+                }
+            }
+        }
+    }
+    if (!any) {
+        b->err = "no workgroup shape fits this batch";
+        return ME_EUNSUPPORTED;
+    }
+    return batch_apply_tuning(b, *best);
 }
 
 }  // namespace
@@ -1329,6 +1823,211 @@ me_status me_adjoint_grad_v(me_system* sys, double* g_fine_dev, double* g_coarse
         if (m < 1 || sys->g.nx % m) return ME_EINVAL;
         HIPCHK(launch_fine_to_coarse(sys->w.gfine, m, sys->g.nx, g_coarse_dev, sys->stream));
     }
+    return ME_OK;
+}
+
+// ------------------------------------------------------------------ batches
+
+me_status me_batch_workspace_size(const me_params* ps, int32_t n_sys, size_t* bytes) {
+    if (!ps || !bytes || n_sys < 1 || n_sys > MAX_BATCH) {
+        g_init_error = "params/bytes NULL or n_sys outside [1, " + std::to_string(MAX_BATCH) + "]";
+        return ME_EINVAL;
+    }
+    size_t total = 0;
+    for (int i = 0; i < n_sys; ++i) {
+        size_t b = 0;
+        const me_status st = me_workspace_size(ps + i, &b);
+        if (st != ME_OK) { g_init_error = "system " + std::to_string(i) + ": " + g_init_error; return st; }
+        total += align_up(b);
+    }
+    *bytes = total + align_up((2 * MAX_TAYLOR + 1) * QUEUE_SLOTS * sizeof(int));
+    return ME_OK;
+}
+
+me_status me_init_batch(const me_params* ps, int32_t n_sys, void* workspace, size_t ws_bytes, void* stream,
+                        me_batch** out) {
+    size_t need = 0;
+    me_status st = me_batch_workspace_size(ps, n_sys, &need);
+    if (st != ME_OK) return st;
+    if (!out || !workspace) { g_init_error = "out/workspace is NULL"; return ME_EINVAL; }
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) { g_init_error = "workspace must be 256-byte aligned"; return ME_EINVAL; }
+    if (ws_bytes < need) { g_init_error = "workspace too small: need " + std::to_string(need) + " bytes"; return ME_ENOMEM; }
+    for (int i = 0; i < n_sys; ++i) {
+        if (ps[i].precision != ps[0].precision || ps[i].taylor_order != ps[0].taylor_order) {
+            g_init_error = "all systems of a batch need the same precision and Taylor order";
+            return ME_EINVAL;
+        }
+        if (ps[i].enable_adjoint) { g_init_error = "batches do not run the adjoint"; return ME_EUNSUPPORTED; }
+        if (ps[i].n[0] > 192) { g_init_error = "batched grids are limited to 192 points per row"; return ME_EUNSUPPORTED; }
+    }
+    me_batch* b = new (std::nothrow) me_batch();
+    if (!b) { g_init_error = "out of host memory"; return ME_EINVAL; }
+    char* base = reinterpret_cast<char*>(workspace);
+    size_t off = 0;
+    for (int i = 0; i < n_sys; ++i) {
+        size_t sz = 0;
+        me_workspace_size(ps + i, &sz);
+        me_system* s = nullptr;
+        st = me_init_system(ps + i, base + off, sz, stream, &s);
+        if (st != ME_OK) {
+            g_init_error = "system " + std::to_string(i) + ": " + g_init_error;
+            for (me_system* t : b->sys) me_destroy(t);
+            delete b;
+            return st;
+        }
+        b->sys.push_back(s);
+        off += align_up(sz);
+    }
+    b->counters = reinterpret_cast<int*>(base + off);
+    b->stream = reinterpret_cast<hipStream_t>(stream);
+    b->f64 = ps[0].precision == ME_F64;
+    b->K = ps[0].taylor_order;
+    b->order.resize(n_sys);
+    for (int i = 0; i < n_sys; ++i) b->order[i] = i;
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
+        const Geometry &gx = b->sys[x]->g, &gy = b->sys[y]->g;
+        return gx.N != gy.N ? gx.N > gy.N : gx.n_orb > gy.n_orb;
+    });
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            b->n_cu = cus;
+    }
+    if (hipMemsetAsync(b->counters, 0, (2 * MAX_TAYLOR + 1) * QUEUE_SLOTS * sizeof(int), b->stream) != hipSuccess ||
+        batch_default_tuning(b) != ME_OK) {
+        g_init_error = b->err.empty() ? "device error" : b->err;
+        for (me_system* t : b->sys) me_destroy(t);
+        delete b;
+        return ME_EDEVICE;
+    }
+    *out = b;
+    return ME_OK;
+}
+
+me_status me_batch_system(me_batch* b, int32_t i, me_system** out) {
+    if (!b || !out || i < 0 || i >= (int)b->sys.size()) return ME_EINVAL;
+    *out = b->sys[i];
+    return ME_OK;
+}
+
+me_status me_batch_set_tuning(me_batch* b, const me_batch_tuning* t) {
+    if (!b || !t) return ME_EINVAL;
+    try {
+        const me_status st = batch_apply_tuning(b, *t);
+        if (st == ME_OK) b->tuned = true;
+        return st;
+    } catch (...) {
+        b->err = "internal error";
+        return ME_EDEVICE;
+    }
+}
+
+me_status me_batch_get_tuning(const me_batch* b, me_batch_tuning* t) {
+    if (!b || !t) return ME_EINVAL;
+    *t = b->tune;
+    return ME_OK;
+}
+
+me_status me_batch_autotune(me_batch* b, const char* cache_path, me_batch_tuning* out) {
+    if (!b) return ME_EINVAL;
+    for (me_system* s : b->sys)
+        if (!s->has_state) { b->err = "no state: call me_set_state on every system first"; return ME_ESTATE; }
+    try {
+        const std::string key = batch_key(b);
+        me_batch_tuning t{};
+        if (cache_path && cache_lookup(cache_path, key, &t) && batch_apply_tuning(b, t) == ME_OK) {
+            b->tuned = true;
+            if (out) *out = b->tune;
+            return ME_OK;
+        }
+        const me_status st = b->f64 ? batch_autotune<double>(b, &t) : batch_autotune<float>(b, &t);
+        if (st != ME_OK) return st;
+        b->tuned = true;
+        b->tune.stage_ms = t.stage_ms;
+        if (cache_path) cache_store(cache_path, key, b->tune);
+        if (out) *out = b->tune;
+        return ME_OK;
+    } catch (...) {
+        b->err = "internal error";
+        return ME_EDEVICE;
+    }
+}
+
+me_status me_propagate_batch(me_batch* b, int32_t n_steps, int32_t use_graph) {
+    if (!b) return ME_EINVAL;
+    if (n_steps < 0) { b->err = "n_steps must be >= 0"; return ME_EINVAL; }
+    for (me_system* s : b->sys)
+        if (!s->has_state) { b->err = "no state: call me_set_state on every system first"; return ME_ESTATE; }
+    try {
+        int done = 0;
+        auto warm = [&]() {
+            for (const me_system* s : b->sys)
+                if (s->hist_count < 3) return false;
+            return true;
+        };
+        while (done < n_steps && !warm()) {
+            CHK(batch_step_any(b));
+            ++done;
+        }
+        if (use_graph && n_steps - done >= BATCH_GRAPH_STEPS) {
+            if (!b->exec || !(batch_phase(b) == b->phase)) CHK(batch_capture(b));
+            while (n_steps - done >= BATCH_GRAPH_STEPS) {
+                BHIP(hipGraphLaunch(b->exec, b->stream));
+                for (me_system* s : b->sys) s->step += BATCH_GRAPH_STEPS;
+                done += BATCH_GRAPH_STEPS;
+            }
+        }
+        while (done < n_steps) {
+            CHK(batch_step_any(b));
+            ++done;
+        }
+        for (me_system* s : b->sys) BSYS(read_report(s, nullptr), s);
+        return ME_OK;
+    } catch (...) {
+        b->err = "internal error";
+        return ME_EDEVICE;
+    }
+}
+
+me_status me_batch_timing_enable(me_batch* b, int32_t enable) {
+    if (!b) return ME_EINVAL;
+    BHIP(hipStreamSynchronize(b->stream));
+    for (auto& e : b->ev) { b->ev_pool.push_back(e.first); b->ev_pool.push_back(e.second); }
+    b->ev.clear();
+    b->ev_bytes.clear();
+    b->timing = enable != 0;
+    return ME_OK;
+}
+
+me_status me_batch_timing_read(me_batch* b, int64_t* launches, double* total_ms, double* total_bytes) {
+    if (!b || !launches || !total_ms || !total_bytes) return ME_EINVAL;
+    BHIP(hipStreamSynchronize(b->stream));
+    double ms = 0.0, by = 0.0;
+    for (size_t i = 0; i < b->ev.size(); ++i) {
+        float t = 0.f;
+        BHIP(hipEventElapsedTime(&t, b->ev[i].first, b->ev[i].second));
+        ms += t;
+        by += b->ev_bytes[i];
+    }
+    *launches = (int64_t)b->ev.size();
+    *total_ms = ms;
+    *total_bytes = by;
+    return ME_OK;
+}
+
+const char* me_batch_last_error(const me_batch* b) {
+    return b ? b->err.c_str() : g_init_error.c_str();
+}
+
+me_status me_batch_destroy(me_batch* b) {
+    if (!b) return ME_OK;
+    hipStreamSynchronize(b->stream);
+    batch_drop_graph(b);
+    for (auto& e : b->ev) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
+    for (auto& e : b->ev_pool) hipEventDestroy(e);
+    for (me_system* s : b->sys) me_destroy(s);
+    delete b;
     return ME_OK;
 }
 

@@ -84,11 +84,44 @@ struct StencilArgs {
     double* partial;         // [n_orb][nyt*nzc] norm or expectation partials, or nullptr
 };
 
+// One system of a batched (persistent) stencil launch.
+constexpr int MAX_BATCH = 32;
+template <typename T>
+struct BatchSys {
+    const cx_t<T>* u;
+    const cx_t<T>* psi0;
+    cx_t<T>* out;
+    const T* v;
+    double* partial;
+    int64_t stride;
+    int nx, ny, nz;
+    int ty, nyt;             // rows per tile, tiles (the last may be ragged)
+    int zchunk, nzc;         // planes per slab, slabs (the last may be short)
+    int item0, items;        // first work item of this system, item count
+    T kin, alpha;
+};
+template <typename T>
+struct BatchStencilArgs {
+    BatchSys<T> sys[MAX_BATCH];
+    int n_sys;
+    int total;               // work items over all systems
+    int* counter;            // device, 8 queue counters, zero at launch
+};
+
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `s` and return hipGetLastError().
 template <typename T>
 hipError_t launch_stencil(const StencilArgs<T>& a, int mode, bool want_norm,
                           int ty, int px, hipStream_t s);
+
+// persistent launch over all systems of a batch (HORNER / HORNER_FIRST modes)
+template <typename T>
+hipError_t launch_batch_stencil(const BatchStencilArgs<T>& a, int mode, bool norm, int block, int grid,
+                                size_t lds, hipStream_t s);
+// resident workgroups per CU of the batched kernel (hj = halo runs per thread)
+template <typename T>
+hipError_t batch_stencil_occupancy(int block, size_t lds, int hj, int* wg_per_cu);
+hipError_t launch_zero_i32(int* p, int n, hipStream_t s);
 
 template <typename T>
 hipError_t launch_kb_tables(const double* pos, int n_ions, int nx, int ny, int nz,

@@ -122,49 +122,42 @@ __device__ __forceinline__ void load_real(const T* __restrict__ p, T* r) {
 template <typename T> struct Pipe { static constexpr int D = sizeof(T) == 4 ? STENCIL_PD32 : STENCIL_PD64; };
 
 
-// Software pipeline with one barrier per plane.  Global loads run PD planes
-// ahead of the compute: at plane z the thread issues the loads of plane z+PD
-// (its y-halo run, psi0 and v_eff) and of plane z+4+PD of its z-queue, all
-// into register queues; plane z+1 is staged into the second LDS buffer after
-// plane z has been computed from the first.  The loop body issues no load
-// whose address depends on another load, so the only waits are for the
-// queued planes.  Offsets inside one orbital are 32-bit.
-template <typename T, int PX, int TY, int MODE, bool NORM>
-__global__ void __launch_bounds__(1024) STENCIL_ATTR
-stencil_kernel(const cx_t<T>* __restrict__ u_all, const cx_t<T>* __restrict__ p0_all,
-               cx_t<T>* __restrict__ out_all, const T* __restrict__ v,
-               double* __restrict__ partial, StencilArgs<T> a) {
+// One workgroup's z-march over planes [z0, z1) of one orbital, rows
+// [y0, y0 + rows) (rows <= TY), all x (2.5-D: a register queue of 9 planes per
+// thread, the current plane plus a 4-row y-halo in a double-buffered LDS
+// tile).  Software pipeline with one barrier per plane: at plane z the thread
+// issues the loads of plane z+D (its y-halo run, psi0 and v_eff) and of plane
+// z+4+D of its z-queue; plane z+1 is staged into the second LDS buffer after
+// plane z has been computed from the first.  The loop issues no load whose
+// address depends on another load, so the only waits are for queued planes.
+// Offsets inside one orbital are 32-bit.  TYC > 0 fixes TY = rows at compile
+// time; TYC == 0 takes them at run time, with HJR halo runs per thread (the
+// workgroup needs HJR * blockDim >= 8 * nx / PX).  The LDS tile is sized for
+// TY rows; a ragged last tile (rows < TY) places its lower halo right below
+// its own rows.  Threads with active == false (beyond nx/PX * rows) only take
+// part in the halo loads and the barriers.  Returns this thread's sum for the
+// NORM / EXPECT_T partials.
+template <typename T, int PX, int TYC, int HJR, int MODE, bool NORM>
+__device__ __forceinline__ double zmarch(const cx_t<T>* __restrict__ u, const cx_t<T>* __restrict__ p0,
+                                         cx_t<T>* __restrict__ out, const T* __restrict__ v, int nx,
+                                         int ny, int nz, int TY, int y0, int rows, int z0, int z1, T kin,
+                                         T alpha, cx_t<T>* tiles, bool active) {
     using C = cx_t<T>;
     constexpr int D = Pipe<T>::D;
-    constexpr int HJ = (8 + TY - 1) / TY;          // halo runs per thread
+    constexpr int HJ = TYC > 0 ? (8 + TYC - 1) / TYC : HJR;   // halo runs per thread
     constexpr bool HORNER = MODE == MODE_HORNER;
     constexpr bool NEEDV = MODE != MODE_EXPECT_T;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    C* tiles = reinterpret_cast<C*>(smem_raw);     // 2 x [(TY+8)][nx]
-    __shared__ double red[16];
+    if constexpr (TYC > 0) { TY = TYC; rows = TYC; }
 
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int nxt = nx / PX;
     const int tid = threadIdx.x;
-    const int tx = tid % nxt, ty = tid / nxt;
-
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int ytile = b % a.nyt;
-    const int rest = b / a.nyt;
-    const int zc = rest % a.nzc;
-    const int A = rest / a.nzc;
-    const int y0 = ytile * TY;
+    const int tx = active ? tid % nxt : 0;
+    const int ty = active ? tid / nxt : 0;
     const int y = y0 + ty;
     const int x0 = tx * PX;
-    const int z0 = zc * a.zchunk;
-    const int z1 = z0 + a.zchunk;
     const int plane = nx * ny;
     const int rowoff = y * nx + x0;
     const int tile_elems = (TY + 8) * nx;
-
-    const C* __restrict__ u = u_all + (int64_t)A * a.stride;
-    const C* __restrict__ p0 = p0_all + (int64_t)A * a.stride;
-    C* __restrict__ out = out_all + (int64_t)A * a.stride;
 
     const T c0 = (T)(3.0 * FD_C0);
     const T cm[4] = {(T)FD_C1, (T)FD_C2, (T)FD_C3, (T)FD_C4};
@@ -185,8 +178,8 @@ stencil_kernel(const cx_t<T>* __restrict__ u_all, const cx_t<T>* __restrict__ p0
         h_ok[i] = j < n_halo;
         const int r = h_ok[i] ? j / nxt : 0;
         const int xr = h_ok[i] ? (j - r * nxt) * PX : 0;
-        const int lr = r < 4 ? r : TY + r;
-        const int gy = wrap1(r < 4 ? y0 - 4 + r : y0 + TY + (r - 4), ny);
+        const int lr = r < 4 ? r : rows + r;
+        const int gy = wrap1(r < 4 ? y0 - 4 + r : y0 + rows + (r - 4), ny);
         h_lds[i] = lr * nx + xr;
         h_off[i] = gy * nx + xr;
     }
@@ -197,8 +190,10 @@ stencil_kernel(const cx_t<T>* __restrict__ u_all, const cx_t<T>* __restrict__ p0
     C hq[D + 1][HJ][PX];
     C pq[D + 1][PX];
     T vq[D + 1][PX];
+    if (active) {
 #pragma unroll
-    for (int k = 0; k < 8 + D; ++k) load_run<T, PX>(u + wrap1(z0 - 4 + k, nz) * plane + rowoff, q[k]);
+        for (int k = 0; k < 8 + D; ++k) load_run<T, PX>(u + wrap1(z0 - 4 + k, nz) * plane + rowoff, q[k]);
+    }
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         if (z0 + d < z1) {
@@ -206,11 +201,13 @@ stencil_kernel(const cx_t<T>* __restrict__ u_all, const cx_t<T>* __restrict__ p0
 #pragma unroll
             for (int i = 0; i < HJ; ++i)
                 if (h_ok[i]) load_run<T, PX>(u + zo + h_off[i], hq[d][i]);
-            if constexpr (HORNER) load_once<T, PX>(p0 + zo + rowoff, pq[d]);
-            if constexpr (NEEDV) load_real<T, PX>(v + zo + rowoff, vq[d]);
+            if (active) {
+                if constexpr (HORNER) load_once<T, PX>(p0 + zo + rowoff, pq[d]);
+                if constexpr (NEEDV) load_real<T, PX>(v + zo + rowoff, vq[d]);
+            }
         }
     }
-    store_run<T, PX>(tiles + yo, q[4]);
+    if (active) store_run<T, PX>(tiles + yo, q[4]);
 #pragma unroll
     for (int i = 0; i < HJ; ++i)
         if (h_ok[i]) store_run<T, PX>(tiles + h_lds[i], hq[0][i]);
@@ -221,55 +218,59 @@ stencil_kernel(const cx_t<T>* __restrict__ u_all, const cx_t<T>* __restrict__ p0
         const int buf = (z - z0) & 1;
         if (z + D < z1) {
             const int zo = (z + D) * plane;
-            load_run<T, PX>(u + wrap1(z + 4 + D, nz) * plane + rowoff, q[8 + D]);
+            if (active) load_run<T, PX>(u + wrap1(z + 4 + D, nz) * plane + rowoff, q[8 + D]);
 #pragma unroll
             for (int i = 0; i < HJ; ++i)
                 if (h_ok[i]) load_run<T, PX>(u + zo + h_off[i], hq[D][i]);
-            if constexpr (HORNER) load_once<T, PX>(p0 + zo + rowoff, pq[D]);
-            if constexpr (NEEDV) load_real<T, PX>(v + zo + rowoff, vq[D]);
+            if (active) {
+                if constexpr (HORNER) load_once<T, PX>(p0 + zo + rowoff, pq[D]);
+                if constexpr (NEEDV) load_real<T, PX>(v + zo + rowoff, vq[D]);
+            }
         }
         const C* tile = tiles + buf * tile_elems;
 
-        C res[PX];
+        if (active) {
+            C res[PX];
 #pragma unroll
-        for (int p = 0; p < PX; ++p) {
-            const C ctr = q[4][p];
-            T sre = c0 * ctr.x, sim = c0 * ctr.y;
+            for (int p = 0; p < PX; ++p) {
+                const C ctr = q[4][p];
+                T sre = c0 * ctr.x, sim = c0 * ctr.y;
 #pragma unroll
-            for (int m = 1; m <= 4; ++m) {
-                const C xp = tile[xo[4 + p + m]];
-                const C xm = tile[xo[4 + p - m]];
-                const C yp = tile[yo + p + m * nx];
-                const C ym = tile[yo + p - m * nx];
-                const C zp = q[4 + m][p];
-                const C zm = q[4 - m][p];
-                sre += cm[m - 1] * (((xp.x + xm.x) + (yp.x + ym.x)) + (zp.x + zm.x));
-                sim += cm[m - 1] * (((xp.y + xm.y) + (yp.y + ym.y)) + (zp.y + zm.y));
-            }
-            const T tre = a.kin * sre, tim = a.kin * sim;
-            if constexpr (MODE == MODE_EXPECT_T) {
-                acc += (double)ctr.x * (double)tre + (double)ctr.y * (double)tim;
-            } else {
-                const T vv = vq[0][p];
-                const T hre = tre + vv * ctr.x;
-                const T him = tim + vv * ctr.y;
-                if constexpr (MODE == MODE_APPLY) {
-                    res[p] = C{hre, him};
-                } else if constexpr (MODE == MODE_SCALED) {
-                    res[p] = C{-a.alpha * him, a.alpha * hre};
-                } else {
-                    const C base = HORNER ? pq[0][p] : ctr;
-                    res[p] = C{base.x - a.alpha * him, base.y + a.alpha * hre};
+                for (int m = 1; m <= 4; ++m) {
+                    const C xp = tile[xo[4 + p + m]];
+                    const C xm = tile[xo[4 + p - m]];
+                    const C yp = tile[yo + p + m * nx];
+                    const C ym = tile[yo + p - m * nx];
+                    const C zp = q[4 + m][p];
+                    const C zm = q[4 - m][p];
+                    sre += cm[m - 1] * (((xp.x + xm.x) + (yp.x + ym.x)) + (zp.x + zm.x));
+                    sim += cm[m - 1] * (((xp.y + xm.y) + (yp.y + ym.y)) + (zp.y + zm.y));
                 }
-                if constexpr (NORM)
-                    acc += (double)res[p].x * (double)res[p].x + (double)res[p].y * (double)res[p].y;
+                const T tre = kin * sre, tim = kin * sim;
+                if constexpr (MODE == MODE_EXPECT_T) {
+                    acc += (double)ctr.x * (double)tre + (double)ctr.y * (double)tim;
+                } else {
+                    const T vv = vq[0][p];
+                    const T hre = tre + vv * ctr.x;
+                    const T him = tim + vv * ctr.y;
+                    if constexpr (MODE == MODE_APPLY) {
+                        res[p] = C{hre, him};
+                    } else if constexpr (MODE == MODE_SCALED) {
+                        res[p] = C{-alpha * him, alpha * hre};
+                    } else {
+                        const C base = HORNER ? pq[0][p] : ctr;
+                        res[p] = C{base.x - alpha * him, base.y + alpha * hre};
+                    }
+                    if constexpr (NORM)
+                        acc += (double)res[p].x * (double)res[p].x + (double)res[p].y * (double)res[p].y;
+                }
             }
+            if constexpr (MODE != MODE_EXPECT_T) store_out<T, PX>(out + z * plane + rowoff, res);
         }
-        if constexpr (MODE != MODE_EXPECT_T) store_out<T, PX>(out + z * plane + rowoff, res);
 
         if (z + 1 < z1) {
             C* nt = tiles + (buf ^ 1) * tile_elems;
-            store_run<T, PX>(nt + yo, q[5]);
+            if (active) store_run<T, PX>(nt + yo, q[5]);
 #pragma unroll
             for (int i = 0; i < HJ; ++i)
                 if (h_ok[i]) store_run<T, PX>(nt + h_lds[i], hq[1][i]);
@@ -290,21 +291,172 @@ stencil_kernel(const cx_t<T>* __restrict__ u_all, const cx_t<T>* __restrict__ p0
             }
         }
     }
+    return acc;
+}
 
+// workgroup sum of one double per thread; result in thread 0
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) s += red[i];
+    }
+    __syncthreads();
+    return s;
+}
+
+// One system: a workgroup per (orbital, y-tile, z-chunk).
+template <typename T, int PX, int TY, int MODE, bool NORM>
+__global__ void __launch_bounds__(1024) STENCIL_ATTR
+stencil_kernel(const cx_t<T>* __restrict__ u_all, const cx_t<T>* __restrict__ p0_all,
+               cx_t<T>* __restrict__ out_all, const T* __restrict__ v,
+               double* __restrict__ partial, StencilArgs<T> a) {
+    using C = cx_t<T>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C* tiles = reinterpret_cast<C*>(smem_raw);     // 2 x [(TY+8)][nx]
+    __shared__ double red[16];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int ytile = b % a.nyt;
+    const int rest = b / a.nyt;
+    const int zc = rest % a.nzc;
+    const int A = rest / a.nzc;
+    const int z0 = zc * a.zchunk;
+    const double acc = zmarch<T, PX, TY, 1, MODE, NORM>(
+        u_all + (int64_t)A * a.stride, p0_all + (int64_t)A * a.stride, out_all + (int64_t)A * a.stride, v,
+        a.nx, a.ny, a.nz, TY, ytile * TY, TY, z0, z0 + a.zchunk, a.kin, a.alpha, tiles, true);
     if constexpr (NORM || MODE == MODE_EXPECT_T) {
-        acc = wave_sum(acc);
-        const int lane = tid & 63, wv = tid >> 6;
-        if (lane == 0) red[wv] = acc;
+        const double s = block_sum(acc, red);
+        if (threadIdx.x == 0) partial[(int64_t)A * (a.nyt * a.nzc) + zc * a.nyt + ytile] = s;
+    }
+}
+
+// Many systems in one persistent launch.  Work items are (system, orbital,
+// y-tile, z-slab), numbered system by system in launch order (the host puts
+// the largest systems first), y-tiles fastest, then z-slabs, then orbitals.
+// Every system's items are cut into QUEUES contiguous slices, and queue q
+// holds slice q of every system, in launch order.  A workgroup starts on the
+// queue of its XCD (workgroups are dealt to the 8 XCDs round-robin), so
+// neighbouring tiles, which share y-halo rows, meet in one L2; when its queue
+// is empty it moves on to the next ones.  Each queue is a device counter that
+// must be zero at launch.
+constexpr int QUEUES = 8;
+
+__device__ __forceinline__ int batch_slice_lo(int count, int q) { return (int)((int64_t)count * q / QUEUES); }
+
+template <typename T>
+__device__ int batch_pull(const BatchStencilArgs<T>& a, int* q_next) {
+    while (*q_next < QUEUES) {
+        const int q = (blockIdx.x + *q_next) % QUEUES;
+        int i = atomicAdd(a.counter + q, 1);
+        for (int s = 0; s < a.n_sys; ++s) {
+            const int cnt = a.sys[s].items;
+            const int lo = batch_slice_lo(cnt, q);
+            const int len = batch_slice_lo(cnt, q + 1) - lo;
+            if (i < len) return a.sys[s].item0 + lo + i;
+            i -= len;
+        }
+        ++*q_next;   // this queue is exhausted for good
+    }
+    return -1;
+}
+
+template <typename T, int HJ, int MODE, bool NORM>
+__global__ void __launch_bounds__(1024) STENCIL_ATTR batch_stencil_kernel(BatchStencilArgs<T> a) {
+    using C = cx_t<T>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C* tiles = reinterpret_cast<C*>(smem_raw);
+    __shared__ double red[16];
+    __shared__ int item_sh;
+    int q_next = 0;                           // used by thread 0 only
+    for (;;) {
+        if (threadIdx.x == 0) item_sh = batch_pull(a, &q_next);
         __syncthreads();
-        if (tid == 0) {
-            double s = 0.0;
-            const int nw = (blockDim.x + 63) >> 6;
-            for (int i = 0; i < nw; ++i) s += red[i];
-            partial[(int64_t)A * (a.nyt * a.nzc) + zc * a.nyt + ytile] = s;
+        const int item = item_sh;
+        __syncthreads();
+        if (item < 0) break;
+        int s = 0;
+        while (s + 1 < a.n_sys && item >= a.sys[s + 1].item0) ++s;
+        const BatchSys<T>& d = a.sys[s];
+        const int local = item - d.item0;
+        const int ytile = local % d.nyt;
+        const int rest = local / d.nyt;
+        const int zc = rest % d.nzc;
+        const int A = rest / d.nzc;
+        const int y0 = ytile * d.ty;
+        const int rows = min(d.ty, d.ny - y0);
+        const int z0 = zc * d.zchunk;
+        const int z1 = min(z0 + d.zchunk, d.nz);
+        const bool active = (int)threadIdx.x < d.nx * rows;
+        const double acc = zmarch<T, 1, 0, HJ, MODE, NORM>(
+            d.u + (int64_t)A * d.stride, d.psi0 + (int64_t)A * d.stride, d.out + (int64_t)A * d.stride, d.v,
+            d.nx, d.ny, d.nz, d.ty, y0, rows, z0, z1, d.kin, d.alpha, tiles, active);
+        if constexpr (NORM) {
+            const double sum = block_sum(acc, red);
+            if (threadIdx.x == 0) d.partial[(int64_t)A * (d.nyt * d.nzc) + zc * d.nyt + ytile] = sum;
         }
     }
 }
 
+template <typename T, int HJ>
+static void launch_batch_hj(const BatchStencilArgs<T>& a, int mode, bool norm, int block, int grid, size_t lds,
+                            hipStream_t s) {
+    if (mode == MODE_HORNER) {
+        if (norm) batch_stencil_kernel<T, HJ, MODE_HORNER, true><<<grid, block, lds, s>>>(a);
+        else batch_stencil_kernel<T, HJ, MODE_HORNER, false><<<grid, block, lds, s>>>(a);
+    } else {
+        if (norm) batch_stencil_kernel<T, HJ, MODE_HORNER_FIRST, true><<<grid, block, lds, s>>>(a);
+        else batch_stencil_kernel<T, HJ, MODE_HORNER_FIRST, false><<<grid, block, lds, s>>>(a);
+    }
+}
+
+template <typename T>
+hipError_t launch_batch_stencil(const BatchStencilArgs<T>& a, int mode, bool norm, int block, int grid,
+                                size_t lds, hipStream_t s) {
+    if (mode != MODE_HORNER && mode != MODE_HORNER_FIRST) return hipErrorInvalidValue;
+    if (block < 64 || block > 1024 || block % 64 || grid < 1 || a.n_sys < 1 || a.n_sys > MAX_BATCH)
+        return hipErrorInvalidValue;
+    int hj = 1;
+    for (int i = 0; i < a.n_sys; ++i) {
+        const BatchSys<T>& d = a.sys[i];
+        if (d.nx * d.ty > block || d.ty < 1 || d.nyt * d.ty < d.ny || d.nzc * d.zchunk < d.nz)
+            return hipErrorInvalidValue;
+        if (8 * d.nx > block) hj = 2;
+        if (8 * d.nx > 2 * block) return hipErrorInvalidValue;
+        if (2 * (size_t)(d.ty + 8) * d.nx * sizeof(cx_t<T>) > lds) return hipErrorInvalidValue;
+    }
+    if (hj == 1) launch_batch_hj<T, 1>(a, mode, norm, block, grid, lds, s);
+    else launch_batch_hj<T, 2>(a, mode, norm, block, grid, lds, s);
+    return hipGetLastError();
+}
+template hipError_t launch_batch_stencil<double>(const BatchStencilArgs<double>&, int, bool, int, int, size_t, hipStream_t);
+template hipError_t launch_batch_stencil<float>(const BatchStencilArgs<float>&, int, bool, int, int, size_t, hipStream_t);
+
+// attributes the host needs to size a persistent launch
+template <typename T>
+hipError_t batch_stencil_occupancy(int block, size_t lds, int hj, int* wg_per_cu) {
+    if (hj == 1)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, batch_stencil_kernel<T, 1, MODE_HORNER, false>,
+                                                            block, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, batch_stencil_kernel<T, 2, MODE_HORNER, false>,
+                                                        block, lds);
+}
+template hipError_t batch_stencil_occupancy<double>(int, size_t, int, int*);
+template hipError_t batch_stencil_occupancy<float>(int, size_t, int, int*);
+
+// zero n ints (graph-safe replacement for a memset)
+__global__ void zero_i32_kernel(int* __restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+hipError_t launch_zero_i32(int* p, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    zero_i32_kernel<<<(n + 255) / 256, 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
 
 template <typename T, int PX, int TY>
 static hipError_t launch_ty(const StencilArgs<T>& a, int mode, bool norm, hipStream_t s) {

@@ -85,3 +85,52 @@ def test_grid_bounds_and_null_checks(lib):
     assert lib.me_init_system(ctypes.byref(p2), None, 0, None, ctypes.byref(h)) == B.ME_EINVAL
     assert lib.me_destroy(None) == B.ME_OK
     assert lib.me_strerror(B.ME_EUNSTABLE).decode() == "propagation unstable"
+
+
+def _batch_params(B, cfgs, **over):
+    ps, keep = [], []
+    for c in cfgs:
+        p, k = B.params_from_config(c, W.ion_positions(c), **over)
+        ps.append(p)
+        keep.append(k)
+    return (B.Params * len(ps))(*ps), keep
+
+
+def test_batch_workspace_is_the_sum_of_the_systems(lib):
+    from paper_0812_2801_amd import binding as B
+    cfgs = [W.C1, W.C1.replace(n=24, n_orb=8, seed=3), W.C1.replace(n=20, n_ions=0)]
+    arr, keep = _batch_params(B, cfgs)
+    total = ctypes.c_size_t(0)
+    assert lib.me_batch_workspace_size(arr, len(cfgs), ctypes.byref(total)) == B.ME_OK
+    singles = sum(-(-B.workspace_size(arr[i]) // 256) * 256 for i in range(len(cfgs)))
+    assert singles < total.value <= singles + 4096
+
+
+def test_batch_validation_happens_on_the_host(lib):
+    from paper_0812_2801_amd import binding as B
+    total = ctypes.c_size_t(0)
+    arr, keep = _batch_params(B, [W.C1])
+    assert lib.me_batch_workspace_size(arr, 0, ctypes.byref(total)) == B.ME_EINVAL
+    assert lib.me_batch_workspace_size(arr, 33, ctypes.byref(total)) == B.ME_EINVAL
+    assert lib.me_batch_last_error(None).decode() != ""
+    # mixed precision / Taylor order and oversize rows are refused before the
+    # workspace (a fake, aligned, never dereferenced address) is touched
+    a, k1 = B.params_from_config(W.C1, W.ion_positions(W.C1), precision="f32")
+    b, k2 = B.params_from_config(W.C1, W.ion_positions(W.C1), precision="f64")
+    mixed = (B.Params * 2)(a, b)
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.me_init_batch(mixed, 2, fake, 1 << 40, None, ctypes.byref(h)) == B.ME_EINVAL
+    c, k3 = B.params_from_config(W.C1, W.ion_positions(W.C1), precision="f32", taylor_order=3)
+    mixed = (B.Params * 2)(a, c)
+    assert lib.me_init_batch(mixed, 2, fake, 1 << 40, None, ctypes.byref(h)) == B.ME_EINVAL
+    big, k4 = B.params_from_config(W.C1.replace(n=200, h=0.3), W.ion_positions(W.C1), precision="f32")
+    one = (B.Params * 1)(big)
+    assert lib.me_init_batch(one, 1, fake, 1 << 40, None, ctypes.byref(h)) == B.ME_EUNSUPPORTED
+    adj, k5 = B.params_from_config(W.C1, W.ion_positions(W.C1), precision="f32", enable_adjoint=True,
+                                   freeze_ions=True)
+    one = (B.Params * 1)(adj)
+    assert lib.me_init_batch(one, 1, fake, 1 << 40, None, ctypes.byref(h)) == B.ME_EUNSUPPORTED
+    assert lib.me_init_batch(arr, 1, fake, 16, None, ctypes.byref(h)) == B.ME_ENOMEM
+    assert lib.me_propagate_batch(None, 1, 1) == B.ME_EINVAL
+    assert lib.me_batch_destroy(None) == B.ME_OK
