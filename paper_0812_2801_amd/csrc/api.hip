@@ -101,13 +101,8 @@ int env_int(const char* name, int dflt) {
     return v && *v ? std::atoi(v) : dflt;
 }
 
-// x-points per thread of the stencil kernel (1 or 2)
-int choose_px(int nx, bool f64) {
-    int w = env_int("MODEHR_PX", 1);
-    if (w != 1 && w != 2) w = 1;
-    while (w > 1 && nx % w) w /= 2;
-    return w;
-}
+// x-points per thread of the stencil kernel
+int choose_px(int nx, bool f64) { return 1; }
 
 // y-rows per stencil workgroup: the largest candidate dividing ny that keeps
 // the workgroup within 1024 threads and its two LDS planes within 64 KiB

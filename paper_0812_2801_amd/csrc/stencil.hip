@@ -109,6 +109,12 @@ __device__ __forceinline__ void load_real(const T* __restrict__ p, T* r) {
 #ifndef STENCIL_PD64
 #define STENCIL_PD64 1
 #endif
+#ifndef STENCIL_HLX32
+#define STENCIL_HLX32 4
+#endif
+#ifndef STENCIL_HLX64
+#define STENCIL_HLX64 4
+#endif
 #ifndef STENCIL_WPE
 #define STENCIL_WPE 0
 #endif
@@ -118,8 +124,12 @@ __device__ __forceinline__ void load_real(const T* __restrict__ p, T* r) {
 #define STENCIL_ATTR
 #endif
 
-// Global loads run D planes ahead of the compute.
-template <typename T> struct Pipe { static constexpr int D = sizeof(T) == 4 ? STENCIL_PD32 : STENCIL_PD64; };
+// Global loads run D planes ahead of the compute; the y-halo rows run HL >= D
+// planes ahead.
+template <typename T> struct Pipe {
+    static constexpr int D = sizeof(T) == 4 ? STENCIL_PD32 : STENCIL_PD64;
+    static constexpr int HL = D + (sizeof(T) == 4 ? STENCIL_HLX32 : STENCIL_HLX64);
+};
 
 
 // One workgroup's z-march over planes [z0, z1) of one orbital, rows
@@ -144,6 +154,7 @@ __device__ __forceinline__ double zmarch(const cx_t<T>* __restrict__ u, const cx
                                          T alpha, cx_t<T>* tiles, bool active) {
     using C = cx_t<T>;
     constexpr int D = Pipe<T>::D;
+    constexpr int HL = Pipe<T>::HL;
     constexpr int HJ = TYC > 0 ? (8 + TYC - 1) / TYC : HJR;   // halo runs per thread
     constexpr bool HORNER = MODE == MODE_HORNER;
     constexpr bool NEEDV = MODE != MODE_EXPECT_T;
@@ -185,9 +196,9 @@ __device__ __forceinline__ double zmarch(const cx_t<T>* __restrict__ u, const cx
     }
 
     // register queues: q = planes z-4 .. z+4+D (the last one in flight),
-    // hq/pq/vq = planes z .. z+D
+    // pq/vq = planes z .. z+D, hq = planes z .. z+HL
     C q[9 + D][PX];
-    C hq[D + 1][HJ][PX];
+    C hq[HL + 1][HJ][PX];
     C pq[D + 1][PX];
     T vq[D + 1][PX];
     if (active) {
@@ -195,12 +206,18 @@ __device__ __forceinline__ double zmarch(const cx_t<T>* __restrict__ u, const cx
         for (int k = 0; k < 8 + D; ++k) load_run<T, PX>(u + wrap1(z0 - 4 + k, nz) * plane + rowoff, q[k]);
     }
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
+    for (int d = 0; d < HL; ++d) {
         if (z0 + d < z1) {
             const int zo = (z0 + d) * plane;
 #pragma unroll
             for (int i = 0; i < HJ; ++i)
                 if (h_ok[i]) load_run<T, PX>(u + zo + h_off[i], hq[d][i]);
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        if (z0 + d < z1) {
+            const int zo = (z0 + d) * plane;
             if (active) {
                 if constexpr (HORNER) load_once<T, PX>(p0 + zo + rowoff, pq[d]);
                 if constexpr (NEEDV) load_real<T, PX>(v + zo + rowoff, vq[d]);
@@ -216,12 +233,15 @@ __device__ __forceinline__ double zmarch(const cx_t<T>* __restrict__ u, const cx
     double acc = 0.0;
     for (int z = z0; z < z1; ++z) {
         const int buf = (z - z0) & 1;
+        if (z + HL < z1) {
+            const int zo = (z + HL) * plane;
+#pragma unroll
+            for (int i = 0; i < HJ; ++i)
+                if (h_ok[i]) load_run<T, PX>(u + zo + h_off[i], hq[HL][i]);
+        }
         if (z + D < z1) {
             const int zo = (z + D) * plane;
             if (active) load_run<T, PX>(u + wrap1(z + 4 + D, nz) * plane + rowoff, q[8 + D]);
-#pragma unroll
-            for (int i = 0; i < HJ; ++i)
-                if (h_ok[i]) load_run<T, PX>(u + zo + h_off[i], hq[D][i]);
             if (active) {
                 if constexpr (HORNER) load_once<T, PX>(p0 + zo + rowoff, pq[D]);
                 if constexpr (NEEDV) load_real<T, PX>(v + zo + rowoff, vq[D]);
@@ -281,11 +301,15 @@ __device__ __forceinline__ double zmarch(const cx_t<T>* __restrict__ u, const cx
 #pragma unroll
             for (int p = 0; p < PX; ++p) q[k][p] = q[k + 1][p];
 #pragma unroll
+        for (int d = 0; d < HL; ++d)
+#pragma unroll
+            for (int p = 0; p < PX; ++p)
+#pragma unroll
+                for (int i = 0; i < HJ; ++i) hq[d][i][p] = hq[d + 1][i][p];
+#pragma unroll
         for (int d = 0; d < D; ++d) {
 #pragma unroll
             for (int p = 0; p < PX; ++p) {
-#pragma unroll
-                for (int i = 0; i < HJ; ++i) hq[d][i][p] = hq[d + 1][i][p];
                 if constexpr (HORNER) pq[d][p] = pq[d + 1][p];
                 if constexpr (NEEDV) vq[d][p] = vq[d + 1][p];
             }
@@ -464,49 +488,34 @@ static hipError_t launch_ty(const StencilArgs<T>& a, int mode, bool norm, hipStr
     dim3 block(nxt * TY);
     dim3 grid((unsigned)((int64_t)a.n_orb * a.nyt * a.nzc));
     const size_t lds = 2 * (size_t)(TY + 8) * a.nx * sizeof(cx_t<T>);
+#define ME_STENCIL(M, NORM) \
+    stencil_kernel<T, PX, TY, M, NORM><<<grid, block, lds, s>>>(a.u, a.psi0, a.out, a.v, a.partial, a)
     switch (mode) {
-    case MODE_APPLY:
-        stencil_kernel<T, PX, TY, MODE_APPLY, false><<<grid, block, lds, s>>>(a.u, a.psi0, a.out, a.v, a.partial, a);
-        break;
+    case MODE_APPLY: ME_STENCIL(MODE_APPLY, false); break;
     case MODE_HORNER:
-        if (norm) stencil_kernel<T, PX, TY, MODE_HORNER, true><<<grid, block, lds, s>>>(a.u, a.psi0, a.out, a.v, a.partial, a);
-        else stencil_kernel<T, PX, TY, MODE_HORNER, false><<<grid, block, lds, s>>>(a.u, a.psi0, a.out, a.v, a.partial, a);
+        if (norm) ME_STENCIL(MODE_HORNER, true); else ME_STENCIL(MODE_HORNER, false);
         break;
     case MODE_HORNER_FIRST:
-        if (norm) stencil_kernel<T, PX, TY, MODE_HORNER_FIRST, true><<<grid, block, lds, s>>>(a.u, a.psi0, a.out, a.v, a.partial, a);
-        else stencil_kernel<T, PX, TY, MODE_HORNER_FIRST, false><<<grid, block, lds, s>>>(a.u, a.psi0, a.out, a.v, a.partial, a);
+        if (norm) ME_STENCIL(MODE_HORNER_FIRST, true); else ME_STENCIL(MODE_HORNER_FIRST, false);
         break;
-    case MODE_EXPECT_T:
-        stencil_kernel<T, PX, TY, MODE_EXPECT_T, false><<<grid, block, lds, s>>>(a.u, a.psi0, a.out, a.v, a.partial, a);
-        break;
-    case MODE_SCALED:
-        stencil_kernel<T, PX, TY, MODE_SCALED, false><<<grid, block, lds, s>>>(a.u, a.psi0, a.out, a.v, a.partial, a);
-        break;
-    default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <typename T, int PX>
-static hipError_t launch_px(const StencilArgs<T>& a, int mode, bool norm, int ty, hipStream_t s) {
-    switch (ty) {
-    case 16: return launch_ty<T, PX, 16>(a, mode, norm, s);
-    case 8: return launch_ty<T, PX, 8>(a, mode, norm, s);
-    case 4: return launch_ty<T, PX, 4>(a, mode, norm, s);
-    case 2: return launch_ty<T, PX, 2>(a, mode, norm, s);
-    case 1: return launch_ty<T, PX, 1>(a, mode, norm, s);
+    case MODE_EXPECT_T: ME_STENCIL(MODE_EXPECT_T, false); break;
+    case MODE_SCALED: ME_STENCIL(MODE_SCALED, false); break;
     default: return hipErrorInvalidValue;
     }
+#undef ME_STENCIL
+    return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_stencil(const StencilArgs<T>& a, int mode, bool want_norm, int ty, int px,
                           hipStream_t s) {
-    if (a.nx % px) return hipErrorInvalidValue;
-    switch (px) {
-    case 1: return launch_px<T, 1>(a, mode, want_norm, ty, s);
-    case 2: return launch_px<T, 2>(a, mode, want_norm, ty, s);
+    if (px != 1) return hipErrorInvalidValue;
+    switch (ty) {
+    case 16: return launch_ty<T, 1, 16>(a, mode, want_norm, s);
+    case 8: return launch_ty<T, 1, 8>(a, mode, want_norm, s);
+    case 4: return launch_ty<T, 1, 4>(a, mode, want_norm, s);
+    case 2: return launch_ty<T, 1, 2>(a, mode, want_norm, s);
+    case 1: return launch_ty<T, 1, 1>(a, mode, want_norm, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -33,3 +33,19 @@ def test_batch_configs_cover_the_stated_ranges():
         assert c.n in (32, 48, 64, 80, 96)
         assert 4 <= c.n_ions <= 64
         assert c.n_orb % 8 == 0 and 8 <= c.n_orb <= 256
+
+
+def test_device_orbital_recipe_on_cpu():
+    """The torch form of the orbital recipe (used for large benchmark batches)
+    gives an orthonormal, smooth, reproducible set."""
+    import torch
+    cfg = W.C1.replace(n=16, n_orb=6, seed=77)
+    a = W.initial_orbitals_device(cfg, "cpu")
+    b = W.initial_orbitals_device(cfg, "cpu")
+    assert a.shape == (6, 16 ** 3) and a.dtype == torch.complex128
+    assert torch.equal(a, b)
+    S = cfg.h ** 3 * (a.conj() @ a.T)
+    assert (S - torch.eye(6, dtype=S.dtype)).abs().max() < 1e-12
+    # the smoothing exp(-(|G| h)^2) leaves almost no weight at the highest |G|
+    spec = torch.fft.fftn(a.reshape(6, 16, 16, 16), dim=(1, 2, 3)).abs() ** 2
+    assert spec[:, 8, 8, 8].max() < 1e-12 * spec.sum(dim=(1, 2, 3)).max()
