@@ -104,8 +104,12 @@ int env_int(const char* name, int dflt) {
 // x-points per thread of the stencil kernel
 int choose_px(int nx, bool f64) { return 1; }
 
+// LDS of one stencil workgroup: at most 64 KiB
+constexpr size_t STENCIL_LDS_MAX = 64 * 1024;
+
 // y-rows per stencil workgroup: the largest candidate dividing ny that keeps
-// the workgroup within 1024 threads and its two LDS planes within 64 KiB
+// the workgroup within 1024 threads and its two LDS tiles within
+// STENCIL_LDS_MAX
 int choose_ty(int nx, int ny, int px, size_t bc) {
     const int nxt = nx / px;
     const int cap = env_int("MODEHR_TY", 16);
@@ -113,7 +117,7 @@ int choose_ty(int nx, int ny, int px, size_t bc) {
         if (ty > cap) continue;
         if (ny % ty) continue;
         if ((int64_t)nxt * ty > 1024) continue;
-        if (2 * (size_t)(ty + 8) * nx * bc > 64 * 1024) continue;
+        if (stencil_lds_bytes(ty, nx, bc) > STENCIL_LDS_MAX) continue;
         return ty;
     }
     return -1;
@@ -207,7 +211,7 @@ struct Layout {
     void* tpl[2];
     int32_t* tcount[2];
     double *fnl, *enl_part, *kbf_part, *floc_part, *floc, *fion, *eion_part, *erec_part;
-    double *ewald_gv, *ewald_wv;
+    double *ewald_gv, *ewald_wv, *ewald_part;
     double *norm_part, *fix_part, *norms, *kin_part, *hxc_part, *loc_part, *rep, *scal0;
     // adjoint (frozen ions): forward intermediates of both exponentials, the
     // half-step and next orbitals, adjoint orbitals, and FP64 grid buffers
@@ -267,9 +271,10 @@ static Layout carve(const Geometry& g, char* base) {
     L.floc = c.take<double>(ion3);
     L.eion_part = c.take<double>(ion3 / 3);
     L.ewald_sg = c.take<double2>((size_t)std::max(1, g.ewald_ng) * 16);
-    L.erec_part = c.take<double>((size_t)((std::max(1, g.ewald_ng) + 255) / 256) * 8);
+    L.erec_part = c.take<double>((size_t)ewald_sg_blocks(g.ewald_ng) * 8);
     L.ewald_gv = c.take<double>((size_t)std::max(1, g.ewald_ng) * 3 * 8);
     L.ewald_wv = c.take<double>((size_t)std::max(1, g.ewald_ng) * 8);
+    L.ewald_part = c.take<double>(ewald_scratch_doubles(g.n_ions) * 8);
     L.norm_part = c.take<double>((size_t)g.n_orb * g.norm_cap * 8);
     L.fix_part = c.take<double>((size_t)g.n_orb * fixup_blocks(g.ucap) * 8);
     L.kin_part = c.take<double>((size_t)g.n_orb * g.nyt * g.nzc * 8);
@@ -397,7 +402,7 @@ me_status ion_fields(me_system* sys, const double* pos, double* out) {
     const Geometry& g = sys->g;
     const double L[3] = {g.nx * sys->prm.h, g.ny * sys->prm.h, g.nz * sys->prm.h};
     HIPCHK(launch_phases(pos, g.n_ions, g.nx, g.ny, g.nz, L, sys->w.phase, sys->w.phaseT, sys->stream));
-    HIPCHK(launch_vloc_spectrum(sys->w.phase, sys->w.zval, g.n_ions, g.nx, g.ny, g.nz, L,
+    HIPCHK(launch_vloc_spectrum(sys->w.phase, sys->w.phaseT, sys->w.zval, g.n_ions, g.nx, g.ny, g.nz, L,
                                 sys->prm.loc_a, sys->w.spec, sys->stream));
     CHK(fft_c2r(sys, sys->w.spec, out));
     if (sys->static_set) HIPCHK(launch_add(out, sys->w.vstatic, g.N, sys->stream));
@@ -454,7 +459,7 @@ me_status forces_parts(me_system* sys, const double* pos, int t) {
                                        sys->geo, g.nx, g.ny, sys->prm.occ, sys->prm.kb_energy, sys->w.fnl,
                                        sys->w.enl_part, sys->w.kbf_part, sys->stream));
     HIPCHK(launch_ewald(sys->ewp, pos, sys->w.zval, g.n_ions, sys->w.ewald_sg, sys->w.erec_part, sys->w.fion,
-                        sys->w.eion_part, sys->stream));
+                        sys->w.eion_part, sys->w.ewald_part, sys->stream));
     return ME_OK;
 }
 
@@ -615,7 +620,7 @@ me_status finalize(me_system* sys, bool with_norm, bool energy) {
     f.enl_part = sys->w.enl_part;
     f.eion_part = sys->w.eion_part;
     f.erec_part = sys->w.erec_part;
-    f.erec_n = (std::max(1, sys->ewp.ng) + 255) / 256;
+    f.erec_n = (g.n_ions > 0 && sys->ewp.ng > 0) ? ewald_sg_blocks(sys->ewp.ng) : 0;   // unwritten without ions
     f.ewald_rec_scale = 2.0 * M_PI / (sys->ew.L * sys->ew.L * sys->ew.L);
     f.ewald_const = sys->ew.e_const;
     f.vel = sys->w.vel;
@@ -934,8 +939,8 @@ bool batch_tiles(const me_batch* b, const me_batch_tuning& t, std::vector<BatchT
         const Geometry& g = s->g;
         if (8 * g.nx > 2 * t.block) return false;
         int ty = std::min(g.ny, t.block / g.nx);
-        while (ty > 1 && 2 * (size_t)(ty + 8) * g.nx * g.bc > 64 * 1024) --ty;
-        if (ty < 1 || 2 * (size_t)(ty + 8) * g.nx * g.bc > 64 * 1024) return false;
+        while (ty > 1 && stencil_lds_bytes(ty, g.nx, g.bc) > STENCIL_LDS_MAX) --ty;
+        if (ty < 1 || stencil_lds_bytes(ty, g.nx, g.bc) > STENCIL_LDS_MAX) return false;
         BatchTile bt{};
         bt.ty = ty;
         bt.nyt = (g.ny + ty - 1) / ty;
@@ -945,7 +950,7 @@ bool batch_tiles(const me_batch* b, const me_batch_tuning& t, std::vector<BatchT
         const int64_t items = (int64_t)g.n_orb * bt.nyt * bt.nzc;
         if (items > (1 << 26)) return false;
         bt.items = (int)items;
-        lds = std::max(lds, 2 * (size_t)(ty + 8) * g.nx * g.bc);
+        lds = std::max(lds, stencil_lds_bytes(ty, g.nx, g.bc));
         out.push_back(bt);
     }
     return true;

@@ -108,6 +108,9 @@ struct BatchStencilArgs {
     int* counter;            // device, 8 queue counters, zero at launch
 };
 
+// dynamic LDS of a stencil workgroup: two halo tiles of (ty + 8) rows of nx
+inline size_t stencil_lds_bytes(int ty, int nx, size_t bc) { return 2 * (size_t)(ty + 8) * nx * bc; }
+
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `s` and return hipGetLastError().
 template <typename T>

@@ -132,6 +132,140 @@ __global__ void vloc_spectrum_kernel(const double2* __restrict__ ph, const doubl
     out[t] = w;
 }
 
+// The same half spectrum, computed row by row.  A workgroup takes VR_ROWS
+// x-rows (iy, iz) and the ions in chunks of VR_CH: the x phases of the chunk
+// and b_J = Z_J ey_J(iy) ez_J(iz) of its rows are staged in LDS, and lane ix
+// of wave w sums b_J ex_J(ix) for four rows.  Points with a Nyquist index
+// (whose mirror lies in another row) are left to vloc_nyquist_kernel.
+constexpr int VR_ROWS = 16;
+constexpr int VR_CH = 64;
+
+__device__ __forceinline__ bool nyq_row(int iy, int iz, int ny, int nz) {
+    return ((ny % 2 == 0) && iy == ny / 2) || ((nz % 2 == 0) && iz == nz / 2);
+}
+
+__global__ void __launch_bounds__(256) vloc_rows_kernel(const double2* __restrict__ ph,
+                                                        const double2* __restrict__ phT,
+                                                        const double* __restrict__ zval, int n_ions,
+                                                        int nx, int ny, int nz, double Lx, double Ly,
+                                                        double Lz, double a, double inv_omega,
+                                                        double2* __restrict__ out) {
+    __shared__ double2 ex[VR_CH * 64];
+    __shared__ double2 bc[VR_ROWS * VR_CH];
+    const int nh = nx / 2 + 1;
+    const int nt = nx + ny + nz;
+    const int rows = ny * nz;
+    const int r0 = blockIdx.x * VR_ROWS;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int ix0 = 0; ix0 < nh; ix0 += 64) {
+        double2 acc[VR_ROWS / 4];
+#pragma unroll
+        for (int q = 0; q < VR_ROWS / 4; ++q) acc[q] = make_double2(0.0, 0.0);
+        for (int J0 = 0; J0 < n_ions; J0 += VR_CH) {
+            const int cnt = min(VR_CH, n_ions - J0);
+            __syncthreads();
+            for (int e = threadIdx.x; e < cnt * 64; e += blockDim.x) {
+                const int j = e >> 6, xi = e & 63;
+                ex[e] = ix0 + xi < nh ? ph[(int64_t)(J0 + j) * nt + ix0 + xi] : make_double2(0.0, 0.0);
+            }
+            for (int e = threadIdx.x; e < VR_ROWS * cnt; e += blockDim.x) {
+                const int rr = e / cnt, j = e - rr * cnt;
+                const int row = r0 + rr;
+                double2 b = make_double2(0.0, 0.0);
+                if (row < rows) {
+                    const int iy = row % ny, iz = row / ny, J = J0 + j;
+                    const double2 t = cmul(phT[(int64_t)(nx + iy) * n_ions + J], phT[(int64_t)(nx + ny + iz) * n_ions + J]);
+                    b = make_double2(zval[J] * t.x, zval[J] * t.y);
+                }
+                bc[rr * VR_CH + j] = b;
+            }
+            __syncthreads();
+            for (int j = 0; j < cnt; ++j) {
+                const double2 e = ex[j * 64 + lane];
+#pragma unroll
+                for (int q = 0; q < VR_ROWS / 4; ++q) {
+                    const double2 b = bc[(wv * (VR_ROWS / 4) + q) * VR_CH + j];
+                    acc[q].x += b.x * e.x - b.y * e.y;
+                    acc[q].y += b.x * e.y + b.y * e.x;
+                }
+            }
+        }
+        const int ix = ix0 + lane;
+#pragma unroll
+        for (int q = 0; q < VR_ROWS / 4; ++q) {
+            const int row = r0 + wv * (VR_ROWS / 4) + q;
+            if (row >= rows || ix >= nh) continue;
+            const int iy = row % ny, iz = row / ny;
+            if (nyq_row(iy, iz, ny, nz) || ((nx % 2 == 0) && ix == nx / 2)) continue;
+            const double gx = 2.0 * M_PI * wavenum(ix, nx) / Lx;
+            const double gy = 2.0 * M_PI * wavenum(iy, ny) / Ly;
+            const double gz = 2.0 * M_PI * wavenum(iz, nz) / Lz;
+            const double g2 = gx * gx + gy * gy + gz * gz;
+            double2 w = make_double2(0.0, 0.0);
+            if (g2 > 0.0) {
+                const double f = vloc_ff(g2, a) * inv_omega;
+                w = make_double2(f * acc[q].x, f * acc[q].y);
+            }
+            out[(int64_t)row * nh + ix] = w;
+        }
+    }
+}
+
+// The points vloc_rows_kernel leaves: the ix = nx/2 column of every row, and
+// the other points of the rows with iy = ny/2 or iz = nz/2; each by the
+// direct per-point sum with its mirror.
+__global__ void vloc_nyquist_kernel(const double2* __restrict__ ph, const double* __restrict__ zval,
+                                    int n_ions, int nx, int ny, int nz, double Lx, double Ly, double Lz,
+                                    double a, double inv_omega, double2* __restrict__ out) {
+    const int nh = nx / 2 + 1;
+    const int rows = ny * nz;
+    const int ncol = (nx % 2 == 0) ? rows : 0;                  // column ix = nx/2
+    const int nxr = (nx % 2 == 0) ? nh - 1 : nh;                // other points of a row
+    const int nry = (ny % 2 == 0) ? nz : 0;                     // rows iy = ny/2
+    const int nrz = (nz % 2 == 0) ? ny - (ny % 2 == 0 ? 1 : 0) : 0;   // rows iz = nz/2, iy != ny/2
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int ix, iy, iz;
+    if (t < ncol) {
+        ix = nx / 2; iy = (int)(t % ny); iz = (int)(t / ny);
+    } else {
+        int64_t u = t - ncol;
+        if (u >= (int64_t)(nry + nrz) * nxr) return;
+        const int r = (int)(u / nxr);
+        ix = (int)(u % nxr);                                    // ix < nx/2 when nx is even
+        if (r < nry) { iy = ny / 2; iz = r; }
+        else { iz = nz / 2; iy = r - nry; if ((ny % 2 == 0) && iy >= ny / 2) ++iy; }
+    }
+    const int nt = nx + ny + nz;
+    const double gx = 2.0 * M_PI * wavenum(ix, nx) / Lx;
+    const double gy = 2.0 * M_PI * wavenum(iy, ny) / Ly;
+    const double gz = 2.0 * M_PI * wavenum(iz, nz) / Lz;
+    const double g2 = gx * gx + gy * gy + gz * gz;
+    double2 w = make_double2(0.0, 0.0);
+    if (g2 > 0.0) {
+        const double2 s = sfac(ph, zval, n_ions, nt, nx, ny, ix, iy, iz);
+        const double f = vloc_ff(g2, a) * inv_omega;
+        w = make_double2(f * s.x, f * s.y);
+        const int mx = (nx - ix) % nx, my = (ny - iy) % ny, mz = (nz - iz) % nz;
+        const double hx = 2.0 * M_PI * wavenum(mx, nx) / Lx;
+        const double hy = 2.0 * M_PI * wavenum(my, ny) / Ly;
+        const double hz = 2.0 * M_PI * wavenum(mz, nz) / Lz;
+        const double h2 = hx * hx + hy * hy + hz * hz;
+        const double2 sm = sfac(ph, zval, n_ions, nt, nx, ny, mx, my, mz);
+        const double fm = vloc_ff(h2, a) * inv_omega;
+        w = make_double2(0.5 * (w.x + fm * sm.x), 0.5 * (w.y - fm * sm.y));
+    }
+    out[((int64_t)iz * ny + iy) * nh + ix] = w;
+}
+
+int64_t vloc_nyquist_points(int nx, int ny, int nz) {
+    const int nh = nx / 2 + 1;
+    const int64_t ncol = (nx % 2 == 0) ? (int64_t)ny * nz : 0;
+    const int nxr = (nx % 2 == 0) ? nh - 1 : nh;
+    const int nry = (ny % 2 == 0) ? nz : 0;
+    const int nrz = (nz % 2 == 0) ? ny - (ny % 2 == 0 ? 1 : 0) : 0;
+    return ncol + (int64_t)(nry + nrz) * nxr;
+}
+
 // ------------------------------------------------------------ Hartree
 // tmp(k) = rho(k) 4 pi / G^2 / N (G != 0), for the complex-to-real transform
 __global__ void hartree_spectrum_kernel(const double2* __restrict__ rhok, int nx, int ny, int nz,
@@ -213,8 +347,11 @@ __global__ void veff_kernel(const double* __restrict__ vloc0, const double* __re
 // separable phase exp(-i G.R) = ex(ix) ey(iy) ez(iz), one x-row of the box
 // contributes per ion S0 = sum_ix Phi ex, Sx = sum_ix Gx Phi ex, and
 //   F_x -= Z Im(Sx ey ez),  F_y -= Z Gy Im(S0 ey ez),  F_z -= Z Gz Im(S0 ey ez).
-// A workgroup takes rows in turn (Phi of the row staged in LDS), a thread
-// takes ions (the transposed phase table makes the ion loads coalesced).
+// A workgroup takes groups of LF_ROWS rows in turn (Phi of the rows staged in
+// LDS).  A thread takes one ion (the transposed phase table makes the ion
+// loads coalesced) and one of XS interleaved slices of ix, XS = 256 / JW with
+// JW = 64, 128 or 256 ion lanes; the force is linear in S0 and Sx, so each
+// slice adds its own share and the slices are summed once at the end.
 // part[(J * gridDim.x + block) * 3 + c]
 constexpr int LF_PASSES = 8;   // up to 8 * 256 ions
 constexpr int LF_ROWS = 8;     // x-rows per workgroup pass (reuse of each ex load)
@@ -227,7 +364,12 @@ __global__ void __launch_bounds__(256) local_force_kernel(const double2* __restr
                                                           double a, double scale,
                                                           double* __restrict__ part) {
     extern __shared__ double2 phi[];      // [LF_ROWS][nx]
+    __shared__ double red[256 * 3];
     const int nh = nx / 2 + 1;
+    const int JW = n_ions <= 64 ? 64 : (n_ions <= 128 ? 128 : 256);
+    const int XS = 256 / JW;
+    const int jl = threadIdx.x % JW, xs = threadIdx.x / JW;
+    const int passes = (n_ions + JW - 1) / JW;
     double acc[LF_PASSES][3];
 #pragma unroll
     for (int p = 0; p < LF_PASSES; ++p) acc[p][0] = acc[p][1] = acc[p][2] = 0.0;
@@ -264,12 +406,12 @@ __global__ void __launch_bounds__(256) local_force_kernel(const double2* __restr
         __syncthreads();
 #pragma unroll
         for (int p = 0; p < LF_PASSES; ++p) {
-            const int J = p * 256 + threadIdx.x;
-            if (J < n_ions) {
+            const int J = p * JW + jl;
+            if (p < passes && J < n_ions) {
                 double s0r[LF_ROWS], s0i[LF_ROWS], sxr[LF_ROWS], sxi[LF_ROWS];
 #pragma unroll
                 for (int rr = 0; rr < LF_ROWS; ++rr) s0r[rr] = s0i[rr] = sxr[rr] = sxi[rr] = 0.0;
-                for (int ix = 0; ix < nx; ++ix) {
+                for (int ix = xs; ix < nx; ix += XS) {
                     const double2 e = phT[(int64_t)ix * n_ions + J];
                     const double gx = 2.0 * M_PI * wavenum(ix, nx) / Lx;
 #pragma unroll
@@ -301,11 +443,21 @@ __global__ void __launch_bounds__(256) local_force_kernel(const double2* __restr
             }
         }
     }
+    // sum the XS slices of each ion (fixed order)
 #pragma unroll
     for (int p = 0; p < LF_PASSES; ++p) {
-        const int J = p * 256 + threadIdx.x;
-        if (J < n_ions)
-            for (int c = 0; c < 3; ++c) part[((int64_t)J * gridDim.x + blockIdx.x) * 3 + c] = acc[p][c];
+        if (p >= passes) break;
+        __syncthreads();
+        for (int c = 0; c < 3; ++c) red[threadIdx.x * 3 + c] = acc[p][c];
+        __syncthreads();
+        const int J = p * JW + threadIdx.x;
+        if (threadIdx.x < JW && J < n_ions) {
+            for (int c = 0; c < 3; ++c) {
+                double v = 0.0;
+                for (int k = 0; k < XS; ++k) v += red[(k * JW + threadIdx.x) * 3 + c];
+                part[((int64_t)J * gridDim.x + blockIdx.x) * 3 + c] = v;
+            }
+        }
     }
 }
 
@@ -347,7 +499,13 @@ __global__ void ewald_sg_kernel(const double* __restrict__ gv, const double* __r
     if (threadIdx.x == 0) epart[blockIdx.x] = s;
 }
 
-// one block per ion: real-space pair/image sum and reciprocal force
+int ewald_sg_blocks(int ng) { return ng > 0 ? (ng + 255) / 256 : 1; }
+
+// grid (ion, EW_SPLIT): block (J, sl) takes every EW_SPLIT-th chunk of 256 of
+// J's pair/image terms and of the reciprocal vectors; partials
+// part[(J * EW_SPLIT + sl) * 4 + {e, fx, fy, fz}], summed by ewald_sum_kernel
+constexpr int EW_SPLIT = 8;
+
 __global__ void __launch_bounds__(256) ewald_ion_kernel(const double* __restrict__ pos,
                                                         const double* __restrict__ zval, int n_ions,
                                                         double L, int nmax, double eta, double rc,
@@ -355,16 +513,17 @@ __global__ void __launch_bounds__(256) ewald_ion_kernel(const double* __restrict
                                                         const double* __restrict__ wv,
                                                         const double2* __restrict__ sg, int ng,
                                                         double four_pi_over_omega,
-                                                        double* __restrict__ f,
-                                                        double* __restrict__ epart) {
+                                                        double* __restrict__ part) {
     __shared__ double sh[4];
     const int J = blockIdx.x;
+    const int sl = blockIdx.y;
+    const int step = blockDim.x * EW_SPLIT;
     const int side = 2 * nmax + 1;
     const int nimg = side * side * side;
     const double rj[3] = {pos[3 * J], pos[3 * J + 1], pos[3 * J + 2]};
     double e = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
     const double two_eta_pi = 2.0 * eta / sqrt(M_PI);
-    for (int64_t t = threadIdx.x; t < (int64_t)n_ions * nimg; t += blockDim.x) {
+    for (int64_t t = (int64_t)sl * blockDim.x + threadIdx.x; t < (int64_t)n_ions * nimg; t += step) {
         const int K = (int)(t / nimg);
         const int im = (int)(t % nimg);
         const int ii = im % side - nmax, jj = (im / side) % side - nmax, kk = im / (side * side) - nmax;
@@ -383,7 +542,7 @@ __global__ void __launch_bounds__(256) ewald_ion_kernel(const double* __restrict
         }
     }
     // reciprocal: F_J = (4 pi Z_J / Omega) sum_G w(G) G Im(exp(i G.R_J) conj(S(G)))
-    for (int t = threadIdx.x; t < ng; t += blockDim.x) {
+    for (int t = sl * blockDim.x + threadIdx.x; t < ng; t += step) {
         const double ph = gv[3 * t] * rj[0] + gv[3 * t + 1] * rj[1] + gv[3 * t + 2] * rj[2];
         double sn, cs;
         sincos(ph, &sn, &cs);
@@ -399,12 +558,28 @@ __global__ void __launch_bounds__(256) ewald_ion_kernel(const double* __restrict
     const double sy = block_sum256(fy, sh);
     const double sz = block_sum256(fz, sh);
     if (threadIdx.x == 0) {
-        f[3 * J] = sx;
-        f[3 * J + 1] = sy;
-        f[3 * J + 2] = sz;
-        epart[J] = se;
+        double* q = part + ((int64_t)J * EW_SPLIT + sl) * 4;
+        q[0] = se;
+        q[1] = sx;
+        q[2] = sy;
+        q[3] = sz;
     }
 }
+
+__global__ void ewald_sum_kernel(const double* __restrict__ part, int n_ions, double* __restrict__ f,
+                                 double* __restrict__ epart) {
+    const int J = blockIdx.x * blockDim.x + threadIdx.x;
+    if (J >= n_ions) return;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int sl = 0; sl < EW_SPLIT; ++sl)
+        for (int c = 0; c < 4; ++c) v[c] += part[((int64_t)J * EW_SPLIT + sl) * 4 + c];
+    epart[J] = v[0];
+    f[3 * J] = v[1];
+    f[3 * J + 1] = v[2];
+    f[3 * J + 2] = v[3];
+}
+
+size_t ewald_scratch_doubles(int n_ions) { return (size_t)(n_ions > 0 ? n_ions : 1) * EW_SPLIT * 4; }
 
 // ------------------------------------------------------------ ions
 __global__ void ions_predict_kernel(const double* __restrict__ pos, const double* __restrict__ vel,
@@ -552,11 +727,22 @@ hipError_t launch_phases(const double* pos, int n_ions, int nx, int ny, int nz, 
     return hipGetLastError();
 }
 
-hipError_t launch_vloc_spectrum(const double2* ph, const double* zval, int n_ions, int nx, int ny,
-                                int nz, const double L[3], double a, double2* out, hipStream_t s) {
-    const int64_t n = (int64_t)(nx / 2 + 1) * ny * nz;
-    vloc_spectrum_kernel<<<nb(n), 256, 0, s>>>(ph, zval, n_ions, nx, ny, nz, L[0], L[1], L[2], a,
-                                               1.0 / (L[0] * L[1] * L[2]), out);
+hipError_t launch_vloc_spectrum(const double2* ph, const double2* phT, const double* zval, int n_ions,
+                                int nx, int ny, int nz, const double L[3], double a, double2* out,
+                                hipStream_t s) {
+    const double inv_omega = 1.0 / (L[0] * L[1] * L[2]);
+    if (n_ions == 0) {
+        const int64_t n = (int64_t)(nx / 2 + 1) * ny * nz;
+        vloc_spectrum_kernel<<<nb(n), 256, 0, s>>>(ph, zval, 0, nx, ny, nz, L[0], L[1], L[2], a, inv_omega, out);
+        return hipGetLastError();
+    }
+    const int rows = ny * nz;
+    vloc_rows_kernel<<<(rows + VR_ROWS - 1) / VR_ROWS, 256, 0, s>>>(ph, phT, zval, n_ions, nx, ny, nz, L[0], L[1],
+                                                                    L[2], a, inv_omega, out);
+    const int64_t nq = vloc_nyquist_points(nx, ny, nz);
+    if (nq > 0)
+        vloc_nyquist_kernel<<<nb(nq), 256, 0, s>>>(ph, zval, n_ions, nx, ny, nz, L[0], L[1], L[2], a, inv_omega,
+                                                   out);
     return hipGetLastError();
 }
 
@@ -603,11 +789,14 @@ hipError_t launch_local_forces(const double2* rhok, const double2* phT, const do
 }
 
 hipError_t launch_ewald(const EwaldPlan& e, const double* pos, const double* zval, int n_ions,
-                        double2* sg, double* erec_part, double* f, double* epart, hipStream_t s) {
+                        double2* sg, double* erec_part, double* f, double* epart, double* scratch,
+                        hipStream_t s) {
     if (n_ions == 0) return hipSuccess;
-    ewald_sg_kernel<<<nb(e.ng), 256, 0, s>>>(e.gv, e.wv, e.ng, pos, zval, n_ions, sg, erec_part);
-    ewald_ion_kernel<<<n_ions, 256, 0, s>>>(pos, zval, n_ions, e.L, e.nmax, e.eta, e.rc, e.gv, e.wv,
-                                            sg, e.ng, 4.0 * M_PI / (e.L * e.L * e.L), f, epart);
+    ewald_sg_kernel<<<ewald_sg_blocks(e.ng), 256, 0, s>>>(e.gv, e.wv, e.ng, pos, zval, n_ions, sg, erec_part);
+    ewald_ion_kernel<<<dim3(n_ions, EW_SPLIT), 256, 0, s>>>(pos, zval, n_ions, e.L, e.nmax, e.eta, e.rc, e.gv,
+                                                            e.wv, sg, e.ng, 4.0 * M_PI / (e.L * e.L * e.L),
+                                                            scratch);
+    ewald_sum_kernel<<<nb(n_ions), 256, 0, s>>>(scratch, n_ions, f, epart);
     return hipGetLastError();
 }
 

@@ -48,8 +48,9 @@ struct EwaldPlan {
 // ph: [n_ions][nx+ny+nz] exp(-i G_a(i) R_Ja); phT: the same as [nx+ny+nz][n_ions]
 hipError_t launch_phases(const double* pos, int n_ions, int nx, int ny, int nz, const double L[3],
                          double2* ph, double2* phT, hipStream_t s);
-hipError_t launch_vloc_spectrum(const double2* ph, const double* zval, int n_ions, int nx, int ny,
-                                int nz, const double L[3], double a, double2* out, hipStream_t s);
+hipError_t launch_vloc_spectrum(const double2* ph, const double2* phT, const double* zval, int n_ions,
+                                int nx, int ny, int nz, const double L[3], double a, double2* out,
+                                hipStream_t s);
 hipError_t launch_hartree_spectrum(const double2* rhok, int nx, int ny, int nz, const double L[3],
                                    double2* out, hipStream_t s);
 hipError_t launch_vhxc(const double* rho, const double* vh, int64_t N, double* vhxc, double* part,
@@ -63,8 +64,12 @@ int local_force_chunks(int64_t N);
 hipError_t launch_local_forces(const double2* rhok, const double2* phT, const double* zval,
                                int n_ions, int nx, int ny, int nz, const double L[3], double h,
                                double a, double* part, double* floc, hipStream_t s);
+// scratch: ewald_scratch_doubles(n_ions) doubles; erec_part: ewald_sg_blocks(ng) doubles
+size_t ewald_scratch_doubles(int n_ions);
+int ewald_sg_blocks(int ng);
 hipError_t launch_ewald(const EwaldPlan& e, const double* pos, const double* zval, int n_ions,
-                        double2* sg, double* erec_part, double* f, double* epart, hipStream_t s);
+                        double2* sg, double* erec_part, double* f, double* epart, double* scratch,
+                        hipStream_t s);
 hipError_t launch_ions_predict(const double* pos, const double* vel, const double* frc,
                                const double* mass, int n_ions, double dt, int frozen, double* pos1,
                                hipStream_t s);

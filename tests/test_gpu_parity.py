@@ -129,10 +129,14 @@ def test_no_ions_and_frozen_field_step():
     cfg = W.C1.replace(n_ions=0, placement="lattice", n_orb=2, seed=77)
     sysm, m, st, inp, cfg = make_pair(cfg)
     for eps in (0.01, -0.02):
-        sysm.step(ctrl=eps)
+        rep = sysm.step(ctrl=eps, report=True)
         st = dynamics.aetrs_step(m, st, eps)
     psi = to_np(sysm.get_state()).reshape(st.psi.shape)
     assert np.abs(psi - st.psi).max() < 1e-10
+    e = dynamics.total_energy(m, st)
+    note(f"  E {rep['e_total']:.12f} oracle {e['total']:.12f}, E_ion {rep['e_ion']}")
+    assert rep["e_ion"] == 0.0
+    assert abs(rep["e_total"] - e["total"]) < 1e-9 * max(1.0, abs(e["total"]))
     sysm.close()
 
 
