@@ -201,6 +201,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 16-system run")
     ap.add_argument("--batch-steps", type=int, default=48)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--batch-only", action="store_true", help="run only the batched workload (profiling)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -209,6 +210,9 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.batch_only:           # profiling aid: the batched workload alone
+        print(json.dumps({"batched": run_batch(args.batch_steps, 8, 6, not args.no_autotune)}))
         return
 
     import numpy as np
