@@ -859,6 +859,7 @@ me_status step_impl(me_system* sys, double eps, bool energy) {
 // V_loc buffers, the K = 1 orbital swap) and 3 (v_Hxc history ring), so six
 // steps bring every pointer a step uses back to where it was.
 constexpr int BATCH_GRAPH_STEPS = 6;
+constexpr int BATCH_WORKERS = 4;
 
 struct BatchTile {
     int ty, nyt, zchunk, nzc, items;
@@ -892,6 +893,13 @@ struct me_batch {
     hipGraphExec_t exec = nullptr;
     std::vector<PhaseKey> phase;   // host state the graph was captured at
     bool capturing = false;
+    // Per-system work of a step runs on BATCH_WORKERS streams (system i on
+    // worker i mod BATCH_WORKERS, default priority), forked from and joined
+    // back to `stream` around every persistent stencil launch, so the small
+    // kernels of different systems overlap (also inside a captured graph).
+    std::vector<hipStream_t> workers;
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     std::vector<double> ev_bytes;
@@ -1014,6 +1022,39 @@ hipEvent_t batch_event(me_batch* b) {
     return e;
 }
 
+// Move every system's work onto its worker stream, after all work queued so
+// far on the batch stream.
+me_status batch_fork(me_batch* b) {
+    BHIP(hipEventRecord(b->ev_fork, b->stream));
+    for (hipStream_t w : b->workers) BHIP(hipStreamWaitEvent(w, b->ev_fork, 0));
+    for (size_t i = 0; i < b->sys.size(); ++i) {
+        me_system* s = b->sys[i];
+        s->stream = b->workers[i % b->workers.size()];
+        if (rocfft_execution_info_set_stream(s->info, s->stream) != rocfft_status_success) {
+            b->err = "rocfft_execution_info_set_stream failed";
+            return ME_EDEVICE;
+        }
+    }
+    return ME_OK;
+}
+
+// The batch stream waits for everything queued on the workers; the systems
+// return to the batch stream.
+me_status batch_join(me_batch* b) {
+    for (size_t w = 0; w < b->workers.size(); ++w) {
+        BHIP(hipEventRecord(b->ev_join[w], b->workers[w]));
+        BHIP(hipStreamWaitEvent(b->stream, b->ev_join[w], 0));
+    }
+    for (me_system* s : b->sys) {
+        s->stream = b->stream;
+        if (rocfft_execution_info_set_stream(s->info, s->stream) != rocfft_status_success) {
+            b->err = "rocfft_execution_info_set_stream failed";
+            return ME_EDEVICE;
+        }
+    }
+    return ME_OK;
+}
+
 // One persistent launch: stage k of exponential e over all systems.
 // u[i] / out[i] / psi0 = psi of system i (caller order); counter slot `slot`.
 template <typename T>
@@ -1088,7 +1129,9 @@ me_status batch_exponential(me_batch* b, int e, bool last) {
             const double ekb_h3 = s->prm.kb_energy * s->prm.h * s->prm.h * s->prm.h;
             BSYS(gather<T>(s, u[i], s->g.stride, s->g.n_orb, t, ekb_h3), s);
         }
+        CHK(batch_join(b));
         CHK(batch_stage<T>(b, u, out, e, k, norm, e * K + (K - k), k == K ? MODE_HORNER_FIRST : MODE_HORNER));
+        CHK(batch_fork(b));
         for (int i = 0; i < n; ++i) {
             me_system* s = b->sys[i];
             const Geometry& g = s->g;
@@ -1109,11 +1152,22 @@ me_status batch_exponential(me_batch* b, int e, bool last) {
 template <typename T>
 me_status batch_step(me_batch* b) {
     BHIP(launch_zero_i32(b->counters, 2 * b->K * QUEUE_SLOTS, b->stream));
-    for (me_system* s : b->sys) BSYS(step_pre(s, 0.0), s);
-    CHK(batch_exponential<T>(b, 0, false));
-    CHK(batch_exponential<T>(b, 1, true));
-    for (me_system* s : b->sys) BSYS(step_post(s, false), s);
-    return ME_OK;
+    CHK(batch_fork(b));
+    me_status st = ME_OK;
+    for (me_system* s : b->sys) {
+        if (st != ME_OK) break;
+        st = step_pre(s, 0.0);
+        if (st != ME_OK) b->err = s->err;
+    }
+    if (st == ME_OK) st = batch_exponential<T>(b, 0, false);
+    if (st == ME_OK) st = batch_exponential<T>(b, 1, true);
+    for (me_system* s : b->sys) {
+        if (st != ME_OK) break;
+        st = step_post(s, false);
+        if (st != ME_OK) b->err = s->err;
+    }
+    const me_status sj = batch_join(b);
+    return st != ME_OK ? st : sj;
 }
 
 me_status batch_step_any(me_batch* b) {
@@ -1132,6 +1186,18 @@ void batch_drop_graph(me_batch* b) {
     if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
     if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
     b->phase.clear();
+}
+
+// everything the batch owns (after its streams are idle)
+void batch_release(me_batch* b) {
+    batch_drop_graph(b);
+    for (auto& e : b->ev) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
+    for (auto& e : b->ev_pool) hipEventDestroy(e);
+    for (hipEvent_t e : b->ev_join) hipEventDestroy(e);
+    if (b->ev_fork) hipEventDestroy(b->ev_fork);
+    for (hipStream_t w : b->workers) hipStreamDestroy(w);
+    for (me_system* s : b->sys) me_destroy(s);
+    delete b;
 }
 
 // Capture BATCH_GRAPH_STEPS steps as one graph at the current host state.
@@ -1888,17 +1954,27 @@ me_status me_init_batch(const me_params* ps, int32_t n_sys, void* workspace, siz
         const Geometry &gx = b->sys[x]->g, &gy = b->sys[y]->g;
         return gx.N != gy.N ? gx.N > gy.N : gx.n_orb > gy.n_orb;
     });
+    bool streams_ok = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) == hipSuccess;
+    const int n_workers = std::min(n_sys, BATCH_WORKERS);
+    for (int w = 0; w < n_workers && streams_ok; ++w) {
+        hipStream_t ws = nullptr;
+        hipEvent_t ev = nullptr;
+        streams_ok = hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) == hipSuccess;
+        if (streams_ok) b->workers.push_back(ws);
+        streams_ok = streams_ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+        if (streams_ok) b->ev_join.push_back(ev);
+    }
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) {
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
             b->n_cu = cus;
     }
-    if (hipMemsetAsync(b->counters, 0, (2 * MAX_TAYLOR + 1) * QUEUE_SLOTS * sizeof(int), b->stream) != hipSuccess ||
+    if (!streams_ok ||
+        hipMemsetAsync(b->counters, 0, (2 * MAX_TAYLOR + 1) * QUEUE_SLOTS * sizeof(int), b->stream) != hipSuccess ||
         batch_default_tuning(b) != ME_OK) {
-        g_init_error = b->err.empty() ? "device error" : b->err;
-        for (me_system* t : b->sys) me_destroy(t);
-        delete b;
+        g_init_error = !streams_ok ? "could not create the worker streams" : (b->err.empty() ? "device error" : b->err);
+        batch_release(b);
         return ME_EDEVICE;
     }
     *out = b;
@@ -2023,11 +2099,8 @@ const char* me_batch_last_error(const me_batch* b) {
 me_status me_batch_destroy(me_batch* b) {
     if (!b) return ME_OK;
     hipStreamSynchronize(b->stream);
-    batch_drop_graph(b);
-    for (auto& e : b->ev) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
-    for (auto& e : b->ev_pool) hipEventDestroy(e);
-    for (me_system* s : b->sys) me_destroy(s);
-    delete b;
+    for (hipStream_t w : b->workers) hipStreamSynchronize(w);
+    batch_release(b);
     return ME_OK;
 }
 
