@@ -77,7 +77,7 @@ def run_precision(cfg, inp, prec, steps, warmup, sample):
     torch.cuda.empty_cache()
     ms = (t1 - t0) * 1e3 / steps
     return {"ms_per_step": ms, "launches": launches, "kernel_ms": kms, "kernel_bytes": kbytes,
-            "psi_sample": got, "report": rep, "energy_drift": rep["e_total"] - e_start,
+            "psi_sample": got, "report": rep, "energy_drift": rep["e_total"] - e_start, "e_start": e_start,
             "steps_total": 1 + warmup + steps}
 
 
@@ -174,6 +174,33 @@ def traffic_entry():
     return d.get("bytes_per_launch")
 
 
+def device_streams(n_bytes: int, reps: int = 20) -> dict:
+    """HBM rate of plain torch streams over buffers of n_bytes each: a copy
+    (1 read, 1 write) and a + b (2 reads, 1 write, the stencil's mix)."""
+    import torch
+    n = n_bytes // 4
+    a = torch.ones(n, device="cuda:0")
+    b = torch.ones(n, device="cuda:0")
+    c = torch.empty(n, device="cuda:0")
+
+    def rate(fn, moved):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return moved / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+
+    out = {"copy": rate(lambda: c.copy_(a), 2 * n * 4), "add": rate(lambda: torch.add(a, b, out=c), 3 * n * 4)}
+    del a, b, c
+    torch.cuda.empty_cache()
+    return out
+
+
 def calibrate_copy(gib: float = 2.0, reps: int = 5):
     """A plain device copy of known size, for scaling HBM counters."""
     import torch
@@ -258,6 +285,7 @@ def main():
     avg_bytes = main_run["kernel_bytes"] / max(1, main_run["launches"])
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
     traffic = traffic_entry()
+    streams = device_streams(cfg.n_orb * cfg.n_points * 8)
     out = {
         "metric": METRIC,
         "value": value,
@@ -278,10 +306,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "stencil_kernel (Horner stage)",
-                     "kernel_avg_ms": avg_ms, "algorithmic_bytes_per_launch": avg_bytes},
+                     "kernel_avg_ms": avg_ms, "algorithmic_bytes_per_launch": avg_bytes,
+                     "device_streams_GBps": streams},
         "cpu_baseline": cpu,
         "errors_vs_fp64_oracle_one_step": errors,
-        "energy_drift": {"total": main_run["energy_drift"], "steps": main_run["steps_total"],
+        "energy_drift": {"total": main_run["energy_drift"], "e_start": main_run["e_start"],
+                         "steps": main_run["steps_total"],
                          "max_norm_dev": main_run["report"]["max_norm_dev"]},
     }
     if f64_run is not None:

@@ -1,0 +1,90 @@
+"""Precision study at the full 128^3 shape (216 ions on a jittered lattice,
+432 orbitals, mu = 4, dt = 0.08).
+
+1. One AETRS step in FP32 and in FP32 with the split-bf16 projector
+   contraction, against the FP64 CPU oracle on sampled orbitals.  The oracle
+   builds H(t) and H(t+dt) from the density of all 432 orbitals and
+   propagates the sampled ones; the ions are frozen so that the step needs no
+   forces of the full set.
+2. Twenty steps with moving ions in FP32, FP32 + bf16x3 and FP64 on the GPU
+   side by side: the per-step distance of the sampled orbitals from the FP64
+   run (a report of how the reduced-precision error grows, bounded loosely).
+
+The oracle part alone takes about two minutes of one CPU core, so the test
+runs only with MODEHR_FULL_SHAPE=1."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_common import note, to_np
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(os.environ.get("MODEHR_FULL_SHAPE") != "1",
+                                 reason="full 128^3 x 432 shape: set MODEHR_FULL_SHAPE=1 (about 4 minutes)")]
+
+SAMPLE = [0, 431]
+
+
+def _system(cfg, pos, prec, psi_dev):
+    from paper_0812_2801_amd import binding as B
+    p, keep = B.params_from_config(cfg, pos, precision=prec)
+    s = B.System(p, keep)
+    s.set_state(psi_dev)
+    return s
+
+
+def _sample(s):
+    return to_np(s.get_state()[SAMPLE])
+
+
+def test_c4_shape_precision():
+    import torch
+    from oracle import Model, dynamics
+    cfg = W.C4
+    note("c4 shape: orbitals on the device")
+    psi_dev = W.initial_orbitals_device(cfg, "cuda:0")
+    pos = W.ion_positions(cfg)
+
+    # 2. twenty steps, moving ions, three precisions side by side
+    runs = {prec: _system(cfg, pos, prec, psi_dev) for prec in ("f64", "f32", "f32_bf16x3")}
+    worst = {"f32": 0.0, "f32_bf16x3": 0.0}
+    for n in range(cfg.steps):
+        for s in runs.values():
+            s.step()
+        ref = _sample(runs["f64"])
+        line = []
+        for prec in worst:
+            d = float(np.abs(_sample(runs[prec]) - ref).max())
+            worst[prec] = max(worst[prec], d)
+            line.append(f"{prec} {d:.2e}")
+        note(f"  step {n + 1}: max|psi - psi_f64| " + ", ".join(line))
+    for s in runs.values():
+        s.close()
+    del runs
+    torch.cuda.empty_cache()
+    assert max(worst.values()) < 1e-3
+
+    # 1. one step against the oracle, frozen ions
+    frozen = cfg.replace(freeze_ions=True)
+    got = {}
+    for prec in ("f32", "f32_bf16x3"):
+        s = _system(frozen, pos, prec, psi_dev)
+        s.step()
+        got[prec] = _sample(s)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    note("  oracle: H(t), H(t+dt) from all 432 orbitals")
+    psi = to_np(psi_dev).reshape(cfg.n_orb, cfg.n, cfg.n, cfg.n)
+    del psi_dev
+    torch.cuda.empty_cache()
+    m = Model.from_config(frozen)
+    st = dynamics.init_state(m, psi, pos)
+    _, h0, h1 = dynamics.step_hamiltonians(m, st)
+    ref = dynamics.propagate_orbitals(m, psi[SAMPLE], h0, h1).reshape(len(SAMPLE), -1)
+    for prec, g in got.items():
+        err = float(np.abs(g - ref).max())
+        note(f"  one step vs oracle, {prec}: max|dpsi| {err:.3e} (max|psi| {np.abs(ref).max():.3e})")
+        assert err < 1e-4
