@@ -259,6 +259,10 @@ def main():
     if not args.no_fp64 and args.precision != "f64":
         f64_run = run_precision(cfg, inp, "f64", max(10, args.steps // 4), args.warmup, sample)
         print(f"# f64: {f64_run['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    bf_run = None
+    if not args.no_fp64 and args.precision == "f32":
+        bf_run = run_precision(cfg, inp, "f32_bf16x3", max(10, args.steps // 4), args.warmup, sample)
+        print(f"# f32_bf16x3: {bf_run['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
 
     batch = None
     if not args.no_batch:
@@ -273,6 +277,8 @@ def main():
         errors[args.precision] = float(np.abs(main_run["psi_sample"] - ref).max())
         if f64_run is not None:
             errors["f64"] = float(np.abs(f64_run["psi_sample"] - ref).max())
+        if bf_run is not None:
+            errors["f32_bf16x3"] = float(np.abs(bf_run["psi_sample"] - ref).max())
         cpu_work = len(sample) * cfg.n_points * 8
         cpu = {"value": cpu_work / t_cpu, "unit": "orbital·gridpt·Hψ/s", "cores": 1,
                "kind": "oracle",
@@ -319,6 +325,10 @@ def main():
                        "value": work / (f64_run["ms_per_step"] * 1e-3),
                        "stencil_avg_ms": f64_run["kernel_ms"] / max(1, f64_run["launches"])}
         out["speedup_vs_fp64"] = f64_run["ms_per_step"] / ms
+    if bf_run is not None:
+        out["f32_bf16x3"] = {"ms_per_step": bf_run["ms_per_step"],
+                             "value": work / (bf_run["ms_per_step"] * 1e-3),
+                             "stencil_avg_ms": bf_run["kernel_ms"] / max(1, bf_run["launches"])}
     if batch is not None:
         out["batched"] = batch
         out["batched_vs_single_system"] = batch["value"] / value

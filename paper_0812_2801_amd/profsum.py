@@ -3,6 +3,12 @@
   python -m paper_0812_2801_amd.profsum stats <kernel_stats.csv> <out.md> "<command>"
   python -m paper_0812_2801_amd.profsum traffic <fetch_dir> <write_dir> <copy_fetch_dir> \
         <copy_write_dir> <copy_bytes> <out.json> "<command>"
+  python -m paper_0812_2801_amd.profsum mfma <pmc_dir> <kernel substring> <n_simd> <out.md> "<command>"
+
+`mfma` reports, for the kernels whose name contains the substring, the MFMA
+busy fraction SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x SIMDs) and the
+bf16 MFMA rate (SQ_INSTS_VALU_MFMA_MOPS_BF16 x 512 flop over the dispatch
+time) against the 2.5 PFLOP/s dense bf16 peak.
 
 `traffic` scales FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the Horner
 stage stencil launches by what the same counters read for a plain device copy
@@ -82,11 +88,40 @@ def traffic(fetch_dir, write_dir, cf_dir, cw_dir, copy_bytes, out, command):
     print(json.dumps(res, indent=1))
 
 
+def mfma(pmc_dir, pattern, n_simd, out, command):
+    per = collections.defaultdict(dict)
+    names = {}
+    for r in _counter_rows(pmc_dir):
+        if pattern not in r["Kernel_Name"]:
+            continue
+        d = r["Dispatch_Id"]
+        per[d][r["Counter_Name"]] = per[d].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        per[d]["ns"] = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+        names[d] = r["Kernel_Name"].split("(")[0]
+    util, rate, dur = [], [], []
+    for d, c in per.items():
+        util.append(100.0 * c["SQ_VALU_MFMA_BUSY_CYCLES"] / (c["GRBM_GUI_ACTIVE"] * n_simd))
+        rate.append(c["SQ_INSTS_VALU_MFMA_MOPS_BF16"] * 512.0 / (c["ns"] * 1e-9) / 1e12)
+        dur.append(c["ns"] / 1e3)
+    kname = sorted(set(names.values()))
+    lines = ["# MFMA use of the split-bf16 projector contraction", "", f"Command: `{command}`", "",
+             f"Kernels: {', '.join('`' + k + '`' for k in kname)}; {len(util)} dispatches.", "",
+             "| quantity | mean | min | max |", "|---|---:|---:|---:|",
+             f"| duration (µs) | {statistics.mean(dur):.2f} | {min(dur):.2f} | {max(dur):.2f} |",
+             f"| MFMA busy (% of SIMD cycles) | {statistics.mean(util):.3f} | {min(util):.3f} | {max(util):.3f} |",
+             f"| bf16 MFMA rate (TFLOP/s) | {statistics.mean(rate):.3f} | {min(rate):.3f} | {max(rate):.3f} |",
+             f"| fraction of the 2.5 PFLOP/s dense bf16 peak (%) | {100 * statistics.mean(rate) / 2500:.4f} | | |"]
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], float(sys.argv[6]), sys.argv[7],
                 sys.argv[8])
+    elif sys.argv[1] == "mfma":
+        mfma(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5], sys.argv[6])
     else:
         raise SystemExit(__doc__)
