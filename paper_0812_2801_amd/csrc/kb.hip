@@ -368,15 +368,19 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
     lo = (__bf16)(x - (float)hi);
 }
 
+// A workgroup takes 8 orbitals of one ion; its four waves take every fourth
+// 32-point chunk of the ion's points, and their partial tiles are summed in a
+// fixed order at the end.
 __global__ void __launch_bounds__(256) kb_gather_bf16x3_kernel(const float2* __restrict__ u, int64_t stride,
                                                                int n_orb, const int32_t* __restrict__ idx,
                                                                const float* __restrict__ pv,
                                                                const int32_t* __restrict__ count, int kcap,
                                                                float scale, float2* __restrict__ cnl) {
+    __shared__ float part[4][4][4];                               // [wave][kq][row in the quad]
     const int J = blockIdx.y;
     const int lane = threadIdx.x & 63;
-    const int A0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 8;     // first orbital of this wave
-    if (A0 >= n_orb) return;
+    const int wv = threadIdx.x >> 6;
+    const int A0 = blockIdx.x * 8;                                // first orbital of this workgroup
     const int K = count[J];
     const int32_t* ix = idx + (int64_t)J * kcap;
     const float* pp = pv + (int64_t)J * kcap;
@@ -384,9 +388,9 @@ __global__ void __launch_bounds__(256) kb_gather_bf16x3_kernel(const float2* __r
     const int kq = lane >> 4;
     const int a = A0 + (m >> 1);
     const bool a_ok = a < n_orb;
-    const float2* ua = u + (int64_t)(a_ok ? a : A0) * stride;
+    const float2* ua = u + (int64_t)(a_ok ? a : 0) * stride;
     f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 32) {
+    for (int k0 = 32 * wv; k0 < K; k0 += 128) {
         bf16x8_t ah, al, bh, bl;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
@@ -411,18 +415,24 @@ __global__ void __launch_bounds__(256) kb_gather_bf16x3_kernel(const float2* __r
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
     }
-    if (m == 0) {
-        // rows 4kq .. 4kq+3 of column 0: orbitals A0 + 2kq and A0 + 2kq + 1, (re, im) each
-        const int a1 = A0 + 2 * kq;
-        if (a1 < n_orb) cnl[(int64_t)J * n_orb + a1] = make_float2(scale * acc[0], scale * acc[1]);
-        if (a1 + 1 < n_orb) cnl[(int64_t)J * n_orb + a1 + 1] = make_float2(scale * acc[2], scale * acc[3]);
+    // column 0 holds the result: rows 4kq .. 4kq+3 (orbitals A0 + 2kq, +1; re, im)
+    if (m == 0)
+        for (int r = 0; r < 4; ++r) part[wv][kq][r] = acc[r];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int q = threadIdx.x;
+        float v[4];
+        for (int r = 0; r < 4; ++r) v[r] = ((part[0][q][r] + part[1][q][r]) + part[2][q][r]) + part[3][q][r];
+        const int a1 = A0 + 2 * q;
+        if (a1 < n_orb) cnl[(int64_t)J * n_orb + a1] = make_float2(scale * v[0], scale * v[1]);
+        if (a1 + 1 < n_orb) cnl[(int64_t)J * n_orb + a1 + 1] = make_float2(scale * v[2], scale * v[3]);
     }
 }
 
 hipError_t launch_kb_gather_bf16x3(const float2* u, int64_t stride, int n_orb, int n_ions, KbTables t,
                                    double ekb_h3, float2* cnl, hipStream_t s) {
     if (n_ions == 0) return hipSuccess;
-    dim3 grid((n_orb + 31) / 32, n_ions);
+    dim3 grid((n_orb + 7) / 8, n_ions);
     kb_gather_bf16x3_kernel<<<grid, 256, 0, s>>>(u, stride, n_orb, t.idx, reinterpret_cast<const float*>(t.p),
                                                  t.count, t.kcap, (float)ekb_h3, cnl);
     return hipGetLastError();
