@@ -141,6 +141,46 @@ def run_batch(steps, warmup, eager_steps, autotune):
     }
 
 
+def run_adjoint(every: int = 10):
+    """The adjoint workload: 64^3, 32 frozen ions, 64 FP32 orbitals, 50 steps
+    with per-step field amplitudes and a 16^3 static perturbation; the final
+    dipole and its gradient with respect to both through the checkpointed
+    adjoint (checkpoints every `every` steps)."""
+    import torch
+    import workloads as W
+    from paper_0812_2801_amd import binding as B
+    from paper_0812_2801_amd.autograd import DipoleObjective
+    cfg = W.C5
+    pos = W.ion_positions(cfg)
+    rngs = W.rngs(cfg)
+    ctrl = W.controls(cfg, rngs[2])
+    psi0 = W.initial_orbitals_device(cfg, "cuda:0")
+    p, keep = B.params_from_config(cfg, pos, precision="f32", enable_adjoint=True)
+    s = B.System(p, keep)
+    c = torch.tensor(ctrl, dtype=torch.float64, requires_grad=True)
+    dv = torch.zeros((cfg.coarse_n,) * 3, dtype=torch.float64, requires_grad=True)
+    J = DipoleObjective.apply(c, dv, s, psi0, every)          # warm-up (plans, code objects)
+    J.backward()
+    c.grad = None
+    dv.grad = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = DipoleObjective.apply(c, dv, s, psi0, every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    s.close()
+    del s, psi0
+    torch.cuda.empty_cache()
+    return {"workload": "64^3 h=0.25, 32 frozen ions, 64 FP32 orbitals, mu=1, dt=0.02, 50 steps with "
+                        "field amplitudes; dJ/d(eps_n) and dJ/d(dV 16^3) of the final dipole",
+            "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
+            "backward_over_forward": (t2 - t1) / (t1 - t0), "checkpoint_every": every,
+            "J": float(J), "grad_eps_norm": float(c.grad.norm())}
+
+
 def oracle_sample(cfg, inp, sample):
     """FP64 oracle: one AETRS propagation of the sampled orbitals (both
     exponentials) from the initial state, single-threaded; timed."""
@@ -228,6 +268,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 16-system run")
     ap.add_argument("--batch-steps", type=int, default=48)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
     ap.add_argument("--batch-only", action="store_true", help="run only the batched workload (profiling)")
     args = ap.parse_args()
 
@@ -268,6 +309,12 @@ def main():
     if not args.no_batch:
         batch = run_batch(args.batch_steps, 8, 6, not args.no_autotune)
         print(f"# batch: {batch['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+
+    adj = None
+    if not args.no_adjoint:
+        adj = run_adjoint()
+        print(f"# adjoint: forward {adj['forward_ms']:.1f} ms, backward {adj['backward_ms']:.1f} ms",
+              file=sys.stderr, flush=True)
 
     cpu = None
     errors = {}
@@ -329,6 +376,8 @@ def main():
         out["f32_bf16x3"] = {"ms_per_step": bf_run["ms_per_step"],
                              "value": work / (bf_run["ms_per_step"] * 1e-3),
                              "stencil_avg_ms": bf_run["kernel_ms"] / max(1, bf_run["launches"])}
+    if adj is not None:
+        out["adjoint"] = adj
     if batch is not None:
         out["batched"] = batch
         out["batched_vs_single_system"] = batch["value"] / value
