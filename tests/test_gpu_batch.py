@@ -62,14 +62,14 @@ def _state(s):
     return to_np(s.get_state()), s.ions()[0], s.forces()
 
 
-TOL = {"f64": 1e-12, "f32": 2e-6}
+TOL = {"f64": 1e-12, "f32": 2e-6, "f32_bf16x3": 2e-6}
 
 
 def _maxabs(a):
     return float(np.abs(a).max()) if np.size(a) else 0.0
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32_bf16x3"])
 def test_batch_graph_matches_systems_alone(prec):
     steps = 14                       # 2 eager warm-up steps + 2 graph replays of 6
     note(f"batch vs alone {prec}, {steps} steps")
