@@ -107,19 +107,27 @@ int choose_px(int nx, bool f64) { return 1; }
 // LDS of one stencil workgroup: at most 64 KiB
 constexpr size_t STENCIL_LDS_MAX = 64 * 1024;
 
-// y-rows per stencil workgroup: the largest candidate dividing ny that keeps
+// y-rows per stencil workgroup, among the candidates that divide ny and keep
 // the workgroup within 1024 threads and its two LDS tiles within
-// STENCIL_LDS_MAX
+// STENCIL_LDS_MAX.  Workgroups of at most 768 threads leave room for two per
+// CU at the kernel's register use, so the largest such tile of at least 8
+// rows (one y-halo row per thread) comes first; FP32 then accepts shorter
+// tiles of at most 768 threads (two halo rows per thread fit its registers),
+// and otherwise the largest tile is taken.  Measured on 64^3, 96^3 and 128^3.
 int choose_ty(int nx, int ny, int px, size_t bc) {
     const int nxt = nx / px;
     const int cap = env_int("MODEHR_TY", 16);
-    for (int ty : {16, 8, 4, 2, 1}) {
-        if (ty > cap) continue;
-        if (ny % ty) continue;
-        if ((int64_t)nxt * ty > 1024) continue;
-        if (stencil_lds_bytes(ty, nx, bc) > STENCIL_LDS_MAX) continue;
-        return ty;
-    }
+    auto ok = [&](int ty) {
+        return ty <= cap && ny % ty == 0 && (int64_t)nxt * ty <= 1024 &&
+               stencil_lds_bytes(ty, nx, bc) <= STENCIL_LDS_MAX;
+    };
+    for (int ty : {16, 8})
+        if (ok(ty) && nxt * ty <= 768) return ty;
+    if (bc == 8)
+        for (int ty : {4, 2, 1})
+            if (ok(ty) && nxt * ty <= 768) return ty;
+    for (int ty : {16, 8, 4, 2, 1})
+        if (ok(ty)) return ty;
     return -1;
 }
 
