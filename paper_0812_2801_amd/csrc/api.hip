@@ -596,11 +596,15 @@ me_status finalize(me_system* sys, bool with_norm, bool energy) {
         if (g.f64) {
             StencilArgs<double> a = base_args<double>(sys, nullptr, g.n_orb);
             a.u = (const double2*)sys->w.psi;
+            a.psi0 = a.u;                      // not read in this mode
+            a.out = (double2*)sys->w.bufA;     // not written in this mode
             a.partial = sys->w.kin_part;
             HIPCHK(launch_stencil<double>(a, MODE_EXPECT_T, false, g.ty, g.px, sys->stream));
         } else {
             StencilArgs<float> a = base_args<float>(sys, nullptr, g.n_orb);
             a.u = (const float2*)sys->w.psi;
+            a.psi0 = a.u;                      // not read in this mode
+            a.out = (float2*)sys->w.bufA;      // not written in this mode
             a.partial = sys->w.kin_part;
             HIPCHK(launch_stencil<float>(a, MODE_EXPECT_T, false, g.ty, g.px, sys->stream));
         }

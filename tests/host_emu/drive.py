@@ -1,0 +1,201 @@
+"""Runs the library built for CPU emulation (tests/host_emu) through its C ABI
+and compares with the FP64 oracle: drive.py LIB SCENARIO [PRECISION] [TMPDIR].
+"Device" buffers are numpy arrays.  Prints OK on success; any misuse the
+emulator or AddressSanitizer detects aborts the process."""
+import ctypes
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+import workloads as W                                      # noqa: E402
+from oracle import Model, adjoint, dynamics                # noqa: E402
+from paper_0812_2801_amd import binding as B               # noqa: E402
+
+lib = B.load(sys.argv[1])
+lib.mock_new_stream.restype = ctypes.c_void_p
+lib.mock_live_handles.restype = ctypes.c_long
+lib.mock_memsets_in_capture.restype = ctypes.c_long
+scenario = sys.argv[2]
+prec = sys.argv[3] if len(sys.argv) > 3 else "f64"
+tmp = sys.argv[4] if len(sys.argv) > 4 else "."
+stream = lib.mock_new_stream()
+held = []
+base_handles = lib.mock_live_handles()
+CDT = np.complex128 if prec == "f64" else np.complex64
+# one-step-scale tolerances: FP64 agrees with the oracle to rounding; FP32
+# (and the split-bf16 contraction) to single precision over a few steps
+TOL_PSI = {"f64": 1e-12, "f32": 2e-6, "f32_bf16x3": 2e-6}[prec]
+TOL_F = {"f64": 1e-10, "f32": 1e-4, "f32_bf16x3": 1e-4}[prec]
+
+
+def buf(nbytes):
+    a = np.zeros(nbytes + 256, np.uint8)
+    held.append(a)
+    return (a.ctypes.data + 255) // 256 * 256
+
+
+def ok(st, h=None, batch=False):
+    if st != B.ME_OK:
+        err = (lib.me_batch_last_error if batch else lib.me_last_error)(h)
+        raise SystemExit(f"status {st}: {err.decode()}")
+
+
+def orbitals(c, inp):
+    return np.ascontiguousarray(inp["psi"].reshape(c.n_orb, -1).astype(CDT))
+
+
+def state(h, c):
+    out = np.zeros((c.n_orb, c.n_points), CDT)
+    ok(lib.me_get_state(h, out.ctypes.data, c.n_points), h)
+    f = np.zeros(3 * c.n_ions)
+    ok(lib.me_forces(h, f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), h)
+    return out, f
+
+
+def oracle_run(c, inp, steps, ctrl=None):
+    m = Model.from_config(c)
+    st = dynamics.init_state(m, inp["psi"], inp["pos"])
+    for n in range(steps):
+        st = dynamics.aetrs_step(m, st, 0.0 if ctrl is None else float(ctrl[n]))
+    return st
+
+
+def compare(name, c, psi, f, st):
+    dpsi = np.abs(psi.reshape(st.psi.shape) - st.psi).max()
+    df = np.abs(f - st.force.ravel()).max() if c.n_ions else 0.0
+    print(f"{name}: max|dpsi| {dpsi:.2e} max|dF| {df:.2e}", flush=True)
+    assert dpsi <= TOL_PSI, (name, dpsi)
+    assert df <= TOL_F, (name, df)
+
+
+def new_system(c, inp, **over):
+    p, keep = B.params_from_config(c, inp["pos"], precision=prec, **over)
+    held.append(keep)
+    size = ctypes.c_size_t(0)
+    ok(lib.me_workspace_size(ctypes.byref(p), ctypes.byref(size)))
+    h = ctypes.c_void_p()
+    ok(lib.me_init_system(ctypes.byref(p), buf(size.value), size.value, stream, ctypes.byref(h)))
+    return h
+
+
+UNEVEN = [
+    W.C1.replace(name="b0", seed=1001),
+    W.C1.replace(name="b1", n=24, n_orb=6, n_ions=5, placement="lattice", jitter=0.2, seed=1002),
+    W.C1.replace(name="b2", n=20, n_orb=3, n_ions=0, seed=1003),
+    W.C1.replace(name="b3", n=40, h=0.25, n_orb=2, n_ions=3, placement="lattice", jitter=0.2, seed=1004),
+]
+
+if scenario == "system":
+    # 20^3 with 5 orbitals and 5 ions: a tile height of 4 rows, an odd
+    # orbital count for the 8-orbital contraction blocks
+    for c in (W.C1, W.C1.replace(name="odd", n=20, n_orb=5, n_ions=5, placement="lattice", jitter=0.2, seed=77)):
+        inp = W.make_inputs(c)
+        h = new_system(c, inp)
+        psi = orbitals(c, inp)
+        ok(lib.me_set_state(h, psi.ctypes.data, c.n_points), h)
+        rep = B.StepReport()
+        ok(lib.me_timing_enable(h, 1), h)
+        for _ in range(3):
+            ok(lib.me_propagate_step(h, None, ctypes.byref(rep)), h)
+        n_, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        ok(lib.me_timing_read(h, ctypes.byref(n_), ctypes.byref(ms), ctypes.byref(by)), h)
+        assert n_.value == 3 * 2 * 4, n_.value
+        st = oracle_run(c, inp, 3)
+        psi_out, f = state(h, c)
+        compare(f"{c.name} 3 steps", c, psi_out, f, st)
+        e = dynamics.total_energy(Model.from_config(c), st)
+        de = abs(rep.e_total - e["total"])
+        print(f"{c.name}: |dE_total| {de:.2e}", flush=True)
+        assert de < (1e-9 if prec == "f64" else 1e-3) * max(1.0, abs(e["total"]))
+        # H applied to the state, against the oracle's H at the same state
+        hpsi = np.zeros_like(psi_out)
+        ok(lib.me_apply_H(h, psi_out.ctypes.data, hpsi.ctypes.data, c.n_orb, c.n_points), h)
+        m = Model.from_config(c)
+        veff = m.vloc(st.pos) + m.v_hxc(st.rho)
+        ref = m.apply_H(psi_out.reshape(st.psi.shape).astype(np.complex128), veff, m.spheres(st.pos))
+        dh = np.abs(hpsi.reshape(ref.shape) - ref).max()
+        print(f"{c.name}: max|d(H psi)| {dh:.2e}", flush=True)
+        assert dh <= (1e-10 if prec == "f64" else 1e-3) * max(1.0, np.abs(ref).max())
+        ok(lib.me_destroy(h))
+elif scenario == "batch":
+    arr = (B.Params * len(UNEVEN))()
+    keep, inps = [], []
+    for i, c in enumerate(UNEVEN):
+        inp = W.make_inputs(c)
+        p, k = B.params_from_config(c, inp["pos"], precision=prec)
+        arr[i] = p
+        keep.append(k)
+        inps.append(inp)
+    size = ctypes.c_size_t(0)
+    ok(lib.me_batch_workspace_size(arr, len(UNEVEN), ctypes.byref(size)))
+    h = ctypes.c_void_p()
+    ok(lib.me_init_batch(arr, len(UNEVEN), buf(size.value), size.value, stream, ctypes.byref(h)))
+    sys_h = []
+    for i, c in enumerate(UNEVEN):
+        s = ctypes.c_void_p()
+        ok(lib.me_batch_system(h, i, ctypes.byref(s)), h, True)
+        psi = orbitals(c, inps[i])
+        ok(lib.me_set_state(s, psi.ctypes.data, c.n_points), s)
+        sys_h.append(s)
+    # warm-up, capture, one replay; then shapes with two halo runs per
+    # thread (block 256 < 8 n_x) and ragged z-slabs, eagerly
+    ok(lib.me_propagate_batch(h, 8, 1), h, True)
+    t = B.BatchTuning(block=256, wg_per_cu=1, zdiv=4, stage_ms=0.0)
+    ok(lib.me_batch_set_tuning(h, ctypes.byref(t)), h, True)
+    ok(lib.me_propagate_batch(h, 2, 0), h, True)
+    t = B.BatchTuning(block=1024, wg_per_cu=1, zdiv=2, stage_ms=0.0)
+    ok(lib.me_batch_set_tuning(h, ctypes.byref(t)), h, True)
+    ok(lib.me_propagate_batch(h, 7, 1), h, True)        # a new phase: recapture, one replay, one eager
+    total = 17
+    for i, c in enumerate(UNEVEN):
+        psi_out, f = state(sys_h[i], c)
+        compare(f"batch {c.name} {total} steps", c, psi_out, f, oracle_run(c, inps[i], total))
+    if prec == "f32":
+        tt = B.BatchTuning()
+        ok(lib.me_batch_autotune(h, os.path.join(tmp, "tune.json").encode(), ctypes.byref(tt)), h, True)
+    ok(lib.me_batch_destroy(h))
+elif scenario == "adjoint":
+    c = W.C1.replace(freeze_ions=True, coarse_n=4, control_sigma=0.01, steps=4, seed=901)
+    inp = W.make_inputs(c)
+    dv = 0.01 * np.random.default_rng(0).standard_normal((4, 4, 4))
+    J0, ge0, gv0 = adjoint.gradient(Model.from_config(c), inp["psi"], inp["pos"], inp["ctrl"], dv)
+    h = new_system(c, inp, enable_adjoint=True)
+    dvb = np.ascontiguousarray(dv)
+    ok(lib.me_set_static_potential_coarse(h, dvb.ctypes.data, 4), h)
+    psi = orbitals(c, inp)
+    ok(lib.me_set_state(h, psi.ctypes.data, c.n_points), h)
+    cp = ctypes.c_size_t(0)
+    ok(lib.me_checkpoint_size(h, ctypes.byref(cp)), h)
+    ck = [buf(cp.value) for _ in range(c.steps)]
+    for n in range(c.steps):
+        ok(lib.me_save_checkpoint(h, ck[n]), h)
+        e = ctypes.c_double(float(inp["ctrl"][n]))
+        ok(lib.me_propagate_step(h, ctypes.byref(e), None), h)
+    J = ctypes.c_double()
+    ok(lib.me_dipole(h, ctypes.byref(J)), h)
+    ok(lib.me_adjoint_begin(h, None), h)
+    ge = np.zeros(c.steps)
+    for n in reversed(range(c.steps)):
+        ok(lib.me_load_checkpoint(h, ck[n]), h)
+        g = ctypes.c_double()
+        ok(lib.me_adjoint_step(h, float(inp["ctrl"][n]), ctypes.byref(g)), h)
+        ge[n] = g.value
+    gv = np.zeros((4, 4, 4))
+    ok(lib.me_adjoint_grad_v(h, None, gv.ctypes.data, 4), h)
+    dj = abs(J.value - J0)
+    dge = np.abs(ge - ge0).max() / max(1e-3, np.abs(ge0).max())
+    dgv = np.abs(gv - gv0).max() / max(1e-3, np.abs(gv0).max())
+    print(f"adjoint: |dJ| {dj:.2e} rel|dge| {dge:.2e} rel|dgv| {dgv:.2e}", flush=True)
+    tol = 1e-9 if prec == "f64" else 2e-3
+    assert dj < tol * max(1.0, abs(J0)) and dge < tol and dgv < tol
+    ok(lib.me_destroy(h))
+else:
+    raise SystemExit(f"unknown scenario {scenario}")
+
+leaked = lib.mock_live_handles() - base_handles
+assert leaked == 0, f"{leaked} runtime handles not released"
+assert lib.mock_memsets_in_capture() == 0, "hipMemsetAsync recorded in a captured graph"
+print("OK", scenario, prec, flush=True)
