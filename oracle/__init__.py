@@ -22,6 +22,8 @@ ab initio molecular dynamics", arXiv:0812.2801):
                    (sec. 5.1, eq. aetrs), velocity Verlet for the ions, the
                    density eq. density.
 * ``adjoint``   -- reverse-mode derivative of an AETRS trajectory.
+* ``cp``        -- the Car-Parrinello comparison scheme (eq. L_CP, eq. EoM_CP)
+                   with RATTLE / velocity Verlet for the orbitals.
 
 Conventions: arrays of grid functions have axes (z, y, x) with x fastest;
 grid point (ix, iy, iz) sits at r = h*(ix, iy, iz); the inner product is the
@@ -29,4 +31,4 @@ grid quadrature h^3 sum conj(a) b.
 """
 from .grid import Grid  # noqa: F401
 from .model import Model  # noqa: F401
-from . import dynamics, potentials, kb, adjoint  # noqa: F401
+from . import dynamics, potentials, kb, adjoint, cp  # noqa: F401
