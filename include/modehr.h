@@ -113,6 +113,10 @@ typedef struct {
     double max_force;      /* max_J |F_J| */
     double charge;         /* h^3 sum rho */
     int64_t step;          /* steps taken since me_set_state */
+    double e_fictitious;   /* me_cp_step only: f mu_cp sum_A <psi_A'|psi_A'> (included in
+                              e_total); 0 for the other steps */
+    double cp_constraint_residual;  /* me_cp_step only: max |A + B^H X + X B + X^2 - I| left
+                                       by the orthonormality constraint solve */
 } me_step_report;
 
 /* Bytes of device workspace me_init_system needs for these parameters.
@@ -219,6 +223,29 @@ me_status me_adjoint_step(me_system* sys, double ctrl_n, double* g_ctrl_n);
 /* dJ/d(dV) accumulated so far: on the grid (g_fine_dev [N]) and/or by the
  * transpose of the trilinear interpolation on an m^3 grid (g_coarse_dev). */
 me_status me_adjoint_grad_v(me_system* sys, double* g_fine_dev, double* g_coarse_dev, int32_t m);
+
+/* ------------------------------------------------------- Car-Parrinello
+ * The comparison scheme of sec. 3 (eq. L_CP, eq. EoM_CP): orbitals with a
+ * fictitious mass mu_cp and orthonormality kept by Lagrange multipliers,
+ * integrated by RATTLE / velocity Verlet (sec. 5, the CP implementation):
+ *   mu_cp psi_A'' = -H psi_A + sum_B psi_B Lambda_BA,  M R'' = -grad E_KS,
+ * conserving f mu_cp sum_A <psi_A'|psi_A'> + E_KS + sum M V^2 / 2.  Each step
+ * costs one H psi and five O(N_W^2 N_C) complex GEMMs (overlaps, constraint
+ * rotations) on rocBLAS, against eight H psi for me_propagate_step.  The
+ * rocBLAS handle is created by me_cp_begin and allocates its own device
+ * workspace; everything else lives in the system's workspace.
+ *
+ * me_cp_begin: start from the current state (me_set_state or a step) with
+ * zero orbital velocities; mu_cp > 0; dt is the CP time step (ions and
+ * orbitals; the params' dt is not used).  Computes H psi (asynchronous).
+ * me_cp_step: one step (ions, orbitals, velocities).  ME_ESTATE unless
+ * me_cp_begin ran after the last state change (me_set_state,
+ * me_load_checkpoint, me_propagate_step, batch steps, adjoint steps and a
+ * new static potential all end the CP run).  rep (nullable) as for
+ * me_propagate_step, plus e_fictitious and cp_constraint_residual; the norm
+ * deviation is not computed (the constraint holds it to the residual). */
+me_status me_cp_begin(me_system* sys, double mu_cp, double dt);
+me_status me_cp_step(me_system* sys, me_step_report* rep);
 
 /* Per-kernel timing.  me_timing_enable(sys, 1) brackets every launch of the
  * Horner-stage stencil kernel with HIP events on the handle's stream;

@@ -27,7 +27,7 @@ SYMBOLS = [
     "me_timing_enable", "me_timing_read", "me_last_error", "me_strerror",
     "me_checkpoint_size", "me_save_checkpoint", "me_load_checkpoint",
     "me_set_static_potential_coarse", "me_dipole", "me_adjoint_begin", "me_adjoint_step",
-    "me_adjoint_grad_v",
+    "me_adjoint_grad_v", "me_cp_begin", "me_cp_step",
     "me_batch_workspace_size", "me_init_batch", "me_batch_system", "me_batch_set_tuning",
     "me_batch_get_tuning", "me_batch_autotune", "me_propagate_batch", "me_batch_timing_enable",
     "me_batch_timing_read", "me_batch_last_error", "me_batch_destroy",
@@ -49,7 +49,8 @@ class Params(ctypes.Structure):
 class StepReport(ctypes.Structure):
     _fields_ = [(k, c_double) for k in (
         "e_kinetic", "e_local", "e_hartree", "e_xc", "e_nonlocal", "e_ion", "e_ks",
-        "e_ion_kinetic", "e_total", "max_norm_dev", "max_force", "charge")] + [("step", c_int64)]
+        "e_ion_kinetic", "e_total", "max_norm_dev", "max_force", "charge")] + [("step", c_int64)] + [
+        ("e_fictitious", c_double), ("cp_constraint_residual", c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -109,6 +110,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.me_adjoint_begin.argtypes = [c_void_p, c_void_p]
     lib.me_adjoint_step.argtypes = [c_void_p, c_double, POINTER(c_double)]
     lib.me_adjoint_grad_v.argtypes = [c_void_p, c_void_p, c_void_p, c_int32]
+    lib.me_cp_begin.argtypes = [c_void_p, c_double, c_double]
+    lib.me_cp_step.argtypes = [c_void_p, POINTER(StepReport)]
     lib.me_batch_workspace_size.argtypes = [POINTER(Params), c_int32, POINTER(c_size_t)]
     lib.me_init_batch.argtypes = [POINTER(Params), c_int32, c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]
     lib.me_batch_system.argtypes = [c_void_p, c_int32, POINTER(c_void_p)]
@@ -276,6 +279,16 @@ class System:
         st = self.lib.me_propagate_step(self.h, ctypes.byref(c) if c is not None else None,
                                         ctypes.byref(rep) if rep is not None else None)
         self._check(st)
+        return rep.as_dict() if rep is not None else None
+
+    def cp_begin(self, mu_cp: float, dt: float):
+        """Start Car-Parrinello steps from the current state (zero orbital velocities)."""
+        self._check(self._pre() or self.lib.me_cp_begin(self.h, c_double(mu_cp), c_double(dt)))
+
+    def cp_step(self, report: bool = False):
+        rep = StepReport() if report else None
+        self._pre()
+        self._check(self.lib.me_cp_step(self.h, ctypes.byref(rep) if rep is not None else None))
         return rep.as_dict() if rep is not None else None
 
     def report(self) -> dict:

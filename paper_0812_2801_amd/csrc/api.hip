@@ -4,6 +4,7 @@
 // Taylor exponentials evaluated in Horner form, then the density, Hartree /
 // exchange, and the forces at the new positions.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 #include <rocfft/rocfft.h>
 
 #include <algorithm>
@@ -19,6 +20,7 @@
 #include "common.hpp"
 #include "fields.hpp"
 #include "adjoint.hpp"
+#include "cp.hpp"
 
 using namespace me;
 
@@ -226,6 +228,11 @@ struct Layout {
     void* inter[2][MAX_TAYLOR];
     void *psi_half, *psi_next, *lamA, *lamB, *ubA, *ubB;
     double *vbar[4], *wbar1, *wbar2, *gfine, *rhobar_T, *rhobar, *hv, *dpart, *scal;
+    // Car-Parrinello comparison step: N_W x N_W matrices (orbital precision),
+    // FP64 constraint-solve scratch, fictitious kinetic energy partials
+    void *cpA, *cpB, *cpX, *cpQ, *cpY;
+    double2 *cpX64, *cpR64;
+    double *cp_part, *cp_info, *fict_part;
     size_t total;
 };
 
@@ -291,6 +298,17 @@ static Layout carve(const Geometry& g, char* base) {
     L.loc_part = c.take<double>((size_t)g.nblk256 * 8);
     L.rep = c.take<double>(SLOT_COUNT * 8);
     L.scal0 = c.take<double>(64);
+    const size_t mat = (size_t)g.n_orb * g.n_orb;
+    L.cpA = c.take<void>(mat * g.bc);
+    L.cpB = c.take<void>(mat * g.bc);
+    L.cpX = c.take<void>(mat * g.bc);
+    L.cpQ = c.take<void>(mat * g.bc);
+    L.cpY = c.take<void>(mat * g.bc);
+    L.cpX64 = c.take<double2>(mat * 16);
+    L.cpR64 = c.take<double2>(mat * 16);
+    L.cp_part = c.take<double>((size_t)cp_solve_blocks(g.n_orb) * 8);
+    L.cp_info = c.take<double>(2 * 8);
+    L.fict_part = c.take<double>((size_t)g.nblk256 * 8);
     if (g.adjoint) {
         for (int e = 0; e < 2; ++e)
             for (int k = 0; k < g.taylor - 1; ++k) L.inter[e][k] = c.take<void>(orb);
@@ -341,6 +359,12 @@ struct me_system {
     // adjoint bookkeeping
     bool adj_ready = false;
     bool adj_pending_final = false;
+    // Car-Parrinello comparison step: rocBLAS handle (created by me_cp_begin),
+    // fictitious mass, time step; cp_ready while bufA holds the orbital
+    // velocities and bufB H psi of the current state
+    rocblas_handle blas = nullptr;
+    double mu_cp = 0.0, dt_cp = 0.0;
+    bool cp_ready = false;
 };
 
 namespace {
@@ -589,7 +613,8 @@ me_status make_veff(me_system* sys, double eps, bool both) {
 }
 
 // fill the report buffer (norm check always; energies when `energy`)
-me_status finalize(me_system* sys, bool with_norm, bool energy) {
+me_status finalize(me_system* sys, bool with_norm, bool energy, const double* fict_part = nullptr,
+                   double fict_scale = 0.0, const double* cp_info = nullptr) {
     const Geometry& g = sys->g;
     if (energy) {
         // kinetic expectation per orbital, E_loc = h^3 sum rho V_loc
@@ -639,6 +664,10 @@ me_status finalize(me_system* sys, bool with_norm, bool energy) {
     f.frc = sys->w.frc;
     f.mass = sys->w.mass;
     f.n_ions = g.n_ions;
+    f.fict_part = fict_part;
+    f.fict_n = fict_part ? g.nblk256 : 0;
+    f.fict_scale = fict_scale;
+    f.cp_info = cp_info;
     HIPCHK(launch_report(f, sys->stream));
     return ME_OK;
 }
@@ -661,6 +690,8 @@ me_status read_report(me_system* sys, me_step_report* rep) {
         rep->max_force = r[SLOT_FMAX];
         rep->charge = r[SLOT_CHARGE];
         rep->step = sys->step;
+        rep->e_fictitious = r[SLOT_EFICT];
+        rep->cp_constraint_residual = r[SLOT_CP_RES];
     }
     if (r[SLOT_UNSTABLE] == 2.0) {
         sys->err = "a grid point lies inside more than 8 projector spheres";
@@ -749,6 +780,7 @@ me_status vhxc_adjoint(me_system* sys, const double* vbar, const double* rho, co
 // Reverse of one frozen-ion step n (state at the start of the step loaded).
 template <typename T>
 me_status adjoint_step_impl(me_system* sys, double eps, double* g_eps) {
+    sys->cp_ready = false;
     using C = cx_t<T>;
     const Geometry& g = sys->g;
     const int64_t n = sys->step;
@@ -826,6 +858,7 @@ me_status initial_fields(me_system* sys) {
 // steps 1-2 of a step: ions moved, H(t+dt) prepared
 me_status step_pre(me_system* sys, double eps) {
     const Geometry& g = sys->g;
+    sys->cp_ready = false;          // bufA / bufB become Taylor-stage scratch
     const int next = sys->tab_cur ^ 1;
     // 1. ions: R(t+dt) by velocity Verlet
     HIPCHK(launch_ions_predict(sys->w.pos, sys->w.vel, sys->w.frc, sys->w.mass, g.n_ions, sys->prm.dt,
@@ -1403,6 +1436,119 @@ me_status batch_autotune(me_batch* b, me_batch_tuning* best) {
     return batch_apply_tuning(b, *best);
 }
 
+// ------------------------------------------------------------ Car-Parrinello
+// The comparison scheme of sec. 3 (eq. L_CP, eq. EoM_CP) with the electronic
+// RATTLE / velocity Verlet integrator the paper uses for it (sec. 5): per
+// step one H psi and five O(N_W^2 N_C) complex GEMMs (the matrices A, B, Q
+// and the rotations Psi X, Psi Y) on rocBLAS (MFMA), against eight H psi and
+// no N_W^2 work for the modified Ehrenfest step.
+
+#define BLASCHK(expr)                                                                  \
+    do {                                                                               \
+        rocblas_status b_ = (expr);                                                    \
+        if (b_ != rocblas_status_success) {                                            \
+            sys->err = std::string(#expr) + ": rocblas status " + std::to_string((int)b_); \
+            return ME_EDEVICE;                                                         \
+        }                                                                              \
+    } while (0)
+
+// C = alpha op(A) op(B) + beta C, column-major complex, alpha and beta real
+rocblas_status cgemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k, double alpha,
+                     const float2* A, int lda, const float2* B, int ldb, double beta, float2* C, int ldc) {
+    const rocblas_float_complex al((float)alpha, 0.0f), be((float)beta, 0.0f);
+    return rocblas_cgemm(h, ta, tb, m, n, k, &al, reinterpret_cast<const rocblas_float_complex*>(A), lda,
+                         reinterpret_cast<const rocblas_float_complex*>(B), ldb, &be,
+                         reinterpret_cast<rocblas_float_complex*>(C), ldc);
+}
+rocblas_status cgemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k, double alpha,
+                     const double2* A, int lda, const double2* B, int ldb, double beta, double2* C, int ldc) {
+    const rocblas_double_complex al(alpha, 0.0), be(beta, 0.0);
+    return rocblas_zgemm(h, ta, tb, m, n, k, &al, reinterpret_cast<const rocblas_double_complex*>(A), lda,
+                         reinterpret_cast<const rocblas_double_complex*>(B), ldb, &be,
+                         reinterpret_cast<rocblas_double_complex*>(C), ldc);
+}
+
+// out = H in for the system's n_orb orbitals (stride g.stride), with the
+// current v_eff (veff0) and projector tables
+template <typename T>
+me_status apply_h_self(me_system* sys, const cx_t<T>* in, cx_t<T>* out) {
+    const Geometry& g = sys->g;
+    const double ekb_h3 = sys->prm.kb_energy * sys->prm.h * sys->prm.h * sys->prm.h;
+    CHK(gather<T>(sys, in, g.stride, g.n_orb, sys->tab_cur, ekb_h3));
+    StencilArgs<T> a = base_args<T>(sys, (const T*)sys->w.veff0, g.n_orb);
+    a.u = in;
+    a.psi0 = in;
+    a.out = out;
+    HIPCHK(launch_stencil<T>(a, MODE_APPLY, false, g.ty, g.px, sys->stream));
+    if (g.n_ions > 0)
+        HIPCHK(launch_kb_fixup<T>(out, g.stride, g.n_orb, tables(sys, sys->tab_cur), (const cx_t<T>*)sys->w.cnl, 1.0,
+                                  0.0, nullptr, sys->stream));
+    return ME_OK;
+}
+
+constexpr double CP_TOL = 1e-12;     // max |residual| of the position constraint
+constexpr int CP_MAX_ITER = 12;
+
+template <typename T>
+me_status cp_begin_impl(me_system* sys) {
+    using C = cx_t<T>;
+    const Geometry& g = sys->g;
+    HIPCHK(hipMemsetAsync(sys->w.bufA, 0, (size_t)g.n_orb * g.stride * g.bc, sys->stream));   // psi' = 0
+    CHK(make_veff(sys, 0.0, false));
+    CHK(apply_h_self<T>(sys, (const C*)sys->w.psi, (C*)sys->w.bufB));
+    return ME_OK;
+}
+
+template <typename T>
+me_status cp_step_impl(me_system* sys, bool energy) {
+    using C = cx_t<T>;
+    const Geometry& g = sys->g;
+    const double dt = sys->dt_cp, mu = sys->mu_cp;
+    const double h3 = sys->prm.h * sys->prm.h * sys->prm.h;
+    const int n = g.n_orb, N = (int)g.N, ld = (int)g.stride;
+    const int next = sys->tab_cur ^ 1;
+    C* psi = (C*)sys->w.psi;
+    C* pdot = (C*)sys->w.bufA;
+    C* trial = (C*)sys->w.bufB;                 // H psi on entry
+    C *A = (C*)sys->w.cpA, *B = (C*)sys->w.cpB, *X = (C*)sys->w.cpX, *Q = (C*)sys->w.cpQ, *Y = (C*)sys->w.cpY;
+    const rocblas_operation NN = rocblas_operation_none, CH = rocblas_operation_conjugate_transpose;
+    // 1. ions R(t+dt); V_loc and projector tables there
+    HIPCHK(launch_ions_predict(sys->w.pos, sys->w.vel, sys->w.frc, sys->w.mass, g.n_ions, dt, sys->prm.freeze_ions,
+                               sys->w.pos_next, sys->stream));
+    CHK(ion_fields(sys, sys->w.pos_next, sys->w.vloc_next));
+    CHK(build_tables(sys, sys->w.pos_next, next));
+    // 2-3. unconstrained orbitals, the constraint matrices, the rotation
+    HIPCHK(launch_cp_predict<T>(trial, psi, pdot, g.stride, n, g.N, dt, dt * dt / (2.0 * mu), sys->stream));
+    BLASCHK(cgemm(sys->blas, CH, NN, n, n, N, h3, trial, ld, trial, ld, 0.0, A, n));
+    BLASCHK(cgemm(sys->blas, CH, NN, n, n, N, h3, psi, ld, trial, ld, 0.0, B, n));
+    HIPCHK(launch_cp_solve_x<T>(A, B, n, CP_TOL, CP_MAX_ITER, sys->w.cpX64, sys->w.cpR64, sys->w.cp_part, X,
+                                sys->w.cp_info, sys->stream));
+    BLASCHK(cgemm(sys->blas, NN, NN, N, n, n, 1.0, psi, ld, X, n, 1.0, trial, ld));
+    // 4. half-step velocities; the new orbitals become the state
+    HIPCHK(launch_cp_halfvel<T>(pdot, trial, psi, g.stride, n, g.N, 1.0 / dt, sys->stream));
+    std::swap(sys->w.psi, sys->w.bufB);
+    psi = (C*)sys->w.psi;
+    C* hpsi = (C*)sys->w.bufB;
+    // 5. density, potentials and forces at the new configuration; ions finished
+    CHK(density_vhxc(sys, energy));
+    CHK(forces_parts(sys, sys->w.pos_next, next));
+    HIPCHK(launch_ions_finish(sys->w.pos, sys->w.vel, sys->w.frc, sys->w.pos_next, sys->w.floc, sys->w.fnl,
+                              sys->w.fion, sys->w.mass, g.n_ions, dt, sys->prm.freeze_ions, sys->stream));
+    std::swap(sys->w.vloc_cur, sys->w.vloc_next);
+    sys->tab_cur = next;
+    sys->step += 1;
+    CHK(make_veff(sys, 0.0, false));
+    CHK(apply_h_self<T>(sys, psi, hpsi));
+    // 6. velocity half kick and the velocity constraint
+    HIPCHK(launch_cp_kick<T>(pdot, hpsi, g.stride, n, g.N, dt / (2.0 * mu), sys->stream));
+    BLASCHK(cgemm(sys->blas, CH, NN, n, n, N, h3, psi, ld, pdot, ld, 0.0, Q, n));
+    HIPCHK(launch_cp_velocity_matrix<T>(Q, n, Y, sys->stream));
+    BLASCHK(cgemm(sys->blas, NN, NN, N, n, n, 1.0, psi, ld, Y, n, 1.0, pdot, ld));
+    if (energy) HIPCHK(launch_cp_sq_partial<T>(pdot, g.stride, n, g.N, sys->w.fict_part, sys->stream));
+    return finalize(sys, false, energy, energy ? sys->w.fict_part : nullptr, sys->prm.occ * mu * h3,
+                    sys->w.cp_info);
+}
+
 }  // namespace
 
 // ================================================================== C ABI
@@ -1559,6 +1705,7 @@ me_status me_init_system(const me_params* p, void* workspace, size_t ws_bytes, v
 me_status me_destroy(me_system* sys) {
     if (!sys) return ME_OK;
     hipStreamSynchronize(sys->stream);
+    if (sys->blas) rocblas_destroy_handle(sys->blas);
     if (sys->info) rocfft_execution_info_destroy(sys->info);
     if (sys->r2c) rocfft_plan_destroy(sys->r2c);
     if (sys->c2r) rocfft_plan_destroy(sys->c2r);
@@ -1591,6 +1738,7 @@ me_status me_set_state(me_system* sys, const void* psi_dev, int64_t orb_stride) 
         CHK(initial_fields(sys));
         sys->step = 0;
         sys->has_state = true;
+        sys->cp_ready = false;
         HIPCHK(hipStreamSynchronize(sys->stream));
         return ME_OK;
     } catch (...) {
@@ -1676,6 +1824,57 @@ me_status me_propagate_step(me_system* sys, const double* ctrl, me_step_report* 
     }
 }
 
+me_status me_cp_begin(me_system* sys, double mu_cp, double dt) {
+    if (!sys) return ME_EINVAL;
+    if (!sys->has_state) { sys->err = "no state: call me_set_state first"; return ME_ESTATE; }
+    if (!(mu_cp > 0.0) || !std::isfinite(mu_cp) || !std::isfinite(dt) || dt == 0.0) {
+        sys->err = "mu_cp must be positive and dt finite and nonzero";
+        return ME_EINVAL;
+    }
+    if (sys->g.N > INT32_MAX || sys->g.stride > INT32_MAX) {
+        sys->err = "grid too large for 32-bit GEMM sizes";
+        return ME_EUNSUPPORTED;
+    }
+    try {
+        if (!sys->blas) {
+            rocblas_handle h = nullptr;
+            if (rocblas_create_handle(&h) != rocblas_status_success) {
+                sys->err = "rocblas_create_handle failed";
+                return ME_EDEVICE;
+            }
+            sys->blas = h;
+        }
+        BLASCHK(rocblas_set_stream(sys->blas, sys->stream));
+        sys->mu_cp = mu_cp;
+        sys->dt_cp = dt;
+        const me_status st = sys->g.f64 ? cp_begin_impl<double>(sys) : cp_begin_impl<float>(sys);
+        sys->cp_ready = st == ME_OK;
+        return st;
+    } catch (...) {
+        sys->err = "internal error";
+        return ME_EDEVICE;
+    }
+}
+
+me_status me_cp_step(me_system* sys, me_step_report* rep) {
+    if (!sys) return ME_EINVAL;
+    if (!sys->cp_ready) { sys->err = "call me_cp_begin first (after the last state change)"; return ME_ESTATE; }
+    try {
+        BLASCHK(rocblas_set_stream(sys->blas, sys->stream));
+        me_status st = sys->g.f64 ? cp_step_impl<double>(sys, rep != nullptr) : cp_step_impl<float>(sys, rep != nullptr);
+        if (st != ME_OK) {
+            sys->cp_ready = false;
+            return st;
+        }
+        if (rep) return read_report(sys, rep);
+        return ME_OK;
+    } catch (...) {
+        sys->cp_ready = false;
+        sys->err = "internal error";
+        return ME_EDEVICE;
+    }
+}
+
 me_status me_report(me_system* sys, me_step_report* rep) {
     if (!sys || !rep) return ME_EINVAL;
     if (!sys->has_state) { sys->err = "no state"; return ME_ESTATE; }
@@ -1735,6 +1934,7 @@ me_status me_get_potential(me_system* sys, int32_t which, double* v_dev) {
 
 me_status me_set_static_potential(me_system* sys, const double* dv_dev) {
     if (!sys) return ME_EINVAL;
+    sys->cp_ready = false;          // H changed: the stored H psi is stale
     if (dv_dev) {
         HIPCHK(hipMemcpyAsync(sys->w.vstatic, dv_dev, sys->g.N * 8, hipMemcpyDeviceToDevice, sys->stream));
         sys->static_set = true;
@@ -1837,10 +2037,12 @@ me_status me_load_checkpoint(me_system* sys, const void* buf_dev) {
                                      sys->stream));
     HIPCHK(hipMemsetAsync(sys->w.rep, 0, SLOT_COUNT * 8, sys->stream));
     sys->has_state = true;
+    sys->cp_ready = false;
     return ME_OK;
 }
 
 me_status me_set_static_potential_coarse(me_system* sys, const double* coarse_dev, int32_t m) {
+    if (sys) sys->cp_ready = false;
     if (!sys || m < 1 || sys->g.nx % m) return ME_EINVAL;
     if (!coarse_dev) return me_set_static_potential(sys, nullptr);
     HIPCHK(launch_coarse_to_fine(coarse_dev, m, sys->g.nx, sys->w.vstatic, sys->stream));

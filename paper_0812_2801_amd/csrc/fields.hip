@@ -676,6 +676,10 @@ __global__ void __launch_bounds__(256) report_kernel(FinalizeArgs a) {
         if (bd[0]) a.rep[SLOT_UNSTABLE] = 1.0;
     }
     if (tid == 0 && a.nl_flag != nullptr && *a.nl_flag != 0) a.rep[SLOT_UNSTABLE] = 2.0;
+    if (tid == 0 && a.cp_info != nullptr) {
+        a.rep[SLOT_CP_ITERS] = a.cp_info[0];
+        a.rep[SLOT_CP_RES] = a.cp_info[1];
+    }
     __syncthreads();
     if (!a.energy) return;
     // sequential partial sums in fixed order
@@ -692,6 +696,10 @@ __global__ void __launch_bounds__(256) report_kernel(FinalizeArgs a) {
     ek = block_sum256(ek, sh); eh = block_sum256(eh, sh); ex = block_sum256(ex, sh);
     el = block_sum256(el, sh); en = block_sum256(en, sh); ei = block_sum256(ei, sh);
     er = block_sum256(er, sh); q = block_sum256(q, sh);
+    double fe = 0.0;
+    if (a.fict_part != nullptr)
+        for (int64_t k = tid; k < a.fict_n; k += 256) fe += a.fict_part[k];
+    fe = block_sum256(fe, sh);
     double ke = 0.0, fmx = 0.0;
     if (tid == 0) {
         for (int J = 0; J < a.n_ions; ++J) {
@@ -710,7 +718,8 @@ __global__ void __launch_bounds__(256) report_kernel(FinalizeArgs a) {
         r[SLOT_EKS] = ((((r[SLOT_EKIN] + r[SLOT_ELOC]) + r[SLOT_EH]) + r[SLOT_EX]) + r[SLOT_ENL]) +
                       r[SLOT_EION];
         r[SLOT_EIONKIN] = ke;
-        r[SLOT_ETOT] = r[SLOT_EKS] + ke;
+        r[SLOT_EFICT] = a.fict_part != nullptr ? a.fict_scale * fe : 0.0;
+        r[SLOT_ETOT] = (r[SLOT_EKS] + ke) + r[SLOT_EFICT];
         r[SLOT_FMAX] = fmx;
         r[SLOT_CHARGE] = a.dv * q;
     }

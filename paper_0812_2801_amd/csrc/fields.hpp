@@ -7,6 +7,7 @@ namespace me {
 enum ReportSlot : int {
     SLOT_EKIN = 0, SLOT_ELOC, SLOT_EH, SLOT_EX, SLOT_ENL, SLOT_EION, SLOT_EKS,
     SLOT_EIONKIN, SLOT_ETOT, SLOT_NORM_DEV, SLOT_FMAX, SLOT_CHARGE, SLOT_UNSTABLE,
+    SLOT_EFICT, SLOT_CP_ITERS, SLOT_CP_RES,
     SLOT_COUNT
 };
 
@@ -35,6 +36,12 @@ struct FinalizeArgs {
     const double* frc;
     const double* mass;
     int n_ions;
+    // Car-Parrinello step only (nullptr otherwise): partial sums of |psi'|^2,
+    // their weight f mu_cp h^3 (the fictitious kinetic energy, added to the
+    // total), and the constraint solve's (corrections, residual)
+    const double* fict_part; int64_t fict_n;
+    double fict_scale;
+    const double* cp_info;
 };
 
 struct EwaldPlan {

@@ -11,7 +11,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 import workloads as W                                      # noqa: E402
-from oracle import Model, adjoint, dynamics                # noqa: E402
+from oracle import Model, adjoint, cp, dynamics            # noqa: E402
 from paper_0812_2801_amd import binding as B               # noqa: E402
 
 lib = B.load(sys.argv[1])
@@ -192,6 +192,36 @@ elif scenario == "adjoint":
     tol = 1e-9 if prec == "f64" else 2e-3
     assert dj < tol * max(1.0, abs(J0)) and dge < tol and dgv < tol
     ok(lib.me_destroy(h))
+elif scenario == "cp":
+    # Car-Parrinello steps against the oracle's RATTLE / velocity Verlet
+    mu_cp, dt = 50.0, 0.25
+    for c in (W.C1, W.C1.replace(name="odd", n=20, n_orb=5, n_ions=5, placement="lattice", jitter=0.2, seed=77)):
+        inp = W.make_inputs(c)
+        h = new_system(c, inp)
+        psi = orbitals(c, inp)
+        ok(lib.me_set_state(h, psi.ctypes.data, c.n_points), h)
+        ok(lib.me_cp_begin(h, mu_cp, dt), h)
+        rep = B.StepReport()
+        m = Model.from_config(c)
+        st = cp.init_state(m, inp["psi"], inp["pos"])
+        for k in range(4):
+            ok(lib.me_cp_step(h, ctypes.byref(rep)), h)
+            st = cp.cp_step(m, st, mu_cp, dt)
+        psi_out, f = state(h, c)
+        compare(f"cp {c.name} 4 steps", c, psi_out, f, st)
+        e = cp.energy(m, st, mu_cp)
+        de, dfict = abs(rep.e_total - e["total"]), abs(rep.e_fictitious - e["fictitious"])
+        print(f"cp {c.name}: |dE_total| {de:.2e} |dE_fict| {dfict:.2e} (E_fict {e['fictitious']:.3e}) "
+              f"constraint residual {rep.cp_constraint_residual:.1e}", flush=True)
+        assert de < (1e-9 if prec == "f64" else 1e-3) * max(1.0, abs(e["total"]))
+        assert dfict < (1e-9 if prec == "f64" else 1e-3) * max(1e-3, e["fictitious"])
+        assert 0.0 <= rep.cp_constraint_residual < 1e-11
+        s_ = m.overlaps(psi_out.reshape(st.psi.shape).astype(np.complex128))
+        assert np.abs(s_ - np.eye(c.n_orb)).max() < (1e-12 if prec == "f64" else 2e-5)
+        # any other step ends the CP run
+        ok(lib.me_propagate_step(h, None, None), h)
+        assert lib.me_cp_step(h, None) == B.ME_ESTATE
+        ok(lib.me_destroy(h))
 else:
     raise SystemExit(f"unknown scenario {scenario}")
 

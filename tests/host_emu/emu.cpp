@@ -661,6 +661,73 @@ extern "C" void* mock_new_stream() {
 }
 extern "C" long mock_memsets_in_capture() { return g_memset_in_capture; }
 extern "C" long mock_launches() { return g_launches; }
+static std::set<void*> g_blas;
 extern "C" long mock_live_handles() {
-    return (long)(g_streams.size() + g_events.size() + g_graphs.size() + g_execs.size() + g_infos.size());
+    return (long)(g_streams.size() + g_events.size() + g_graphs.size() + g_execs.size() + g_infos.size() +
+                  g_blas.size());
+}
+
+// ------------------------------------------------------------ rocBLAS by direct loops
+#include <rocblas/rocblas.h>
+struct MockBlas { MockStream* stream = nullptr; };
+rocblas_status rocblas_create_handle(rocblas_handle* h) {
+    *h = new MockBlas();
+    g_blas.insert(*h);
+    return rocblas_status_success;
+}
+rocblas_status rocblas_destroy_handle(rocblas_handle h) {
+    if (!g_blas.count(h)) FAIL("destroying an invalid rocBLAS handle");
+    g_blas.erase(h);
+    delete h;
+    return rocblas_status_success;
+}
+rocblas_status rocblas_set_stream(rocblas_handle h, MockStream* s) {
+    if (!g_blas.count(h)) FAIL("invalid rocBLAS handle");
+    S(s, "rocblas_set_stream");
+    h->stream = s;
+    return rocblas_status_success;
+}
+template <class R>
+static rocblas_status gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
+                           std::complex<R> alpha, const std::complex<R>* A, int lda, const std::complex<R>* B, int ldb,
+                           std::complex<R> beta, std::complex<R>* C, int ldc) {
+    if (!g_blas.count(h)) FAIL("invalid rocBLAS handle");
+    if (ta == rocblas_operation_transpose || tb == rocblas_operation_transpose) FAIL("unexpected gemm operation");
+    const bool ca = ta == rocblas_operation_conjugate_transpose, cb = tb == rocblas_operation_conjugate_transpose;
+    if (m < 0 || n < 0 || k < 0 || ldc < std::max(1, m) || lda < std::max(1, ca ? k : m) || ldb < std::max(1, cb ? n : k))
+        FAIL("gemm sizes: m %d n %d k %d lda %d ldb %d ldc %d", m, n, k, lda, ldb, ldc);
+    submit(S(h->stream, "rocblas gemm"), [=]() {
+        std::vector<std::complex<R>> col(m);
+        for (int j = 0; j < n; ++j) {
+            std::fill(col.begin(), col.end(), std::complex<R>(0));
+            for (int p = 0; p < k; ++p) {
+                const std::complex<R> b = cb ? std::conj(B[j + (size_t)p * ldb]) : B[p + (size_t)j * ldb];
+                for (int i = 0; i < m; ++i) {
+                    const std::complex<R> a = ca ? std::conj(A[p + (size_t)i * lda]) : A[i + (size_t)p * lda];
+                    col[i] += a * b;
+                }
+            }
+            for (int i = 0; i < m; ++i) {
+                std::complex<R>& c = C[i + (size_t)j * ldc];
+                c = alpha * col[i] + (beta == std::complex<R>(0) ? std::complex<R>(0) : beta * c);
+            }
+        }
+    });
+    return rocblas_status_success;
+}
+rocblas_status rocblas_cgemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, rocblas_int m, rocblas_int n,
+                             rocblas_int k, const rocblas_float_complex* alpha, const rocblas_float_complex* A,
+                             rocblas_int lda, const rocblas_float_complex* B, rocblas_int ldb,
+                             const rocblas_float_complex* beta, rocblas_float_complex* C, rocblas_int ldc) {
+    using c = std::complex<float>;
+    return gemm<float>(h, ta, tb, m, n, k, c(alpha->x, alpha->y), reinterpret_cast<const c*>(A), lda,
+                       reinterpret_cast<const c*>(B), ldb, c(beta->x, beta->y), reinterpret_cast<c*>(C), ldc);
+}
+rocblas_status rocblas_zgemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, rocblas_int m, rocblas_int n,
+                             rocblas_int k, const rocblas_double_complex* alpha, const rocblas_double_complex* A,
+                             rocblas_int lda, const rocblas_double_complex* B, rocblas_int ldb,
+                             const rocblas_double_complex* beta, rocblas_double_complex* C, rocblas_int ldc) {
+    using c = std::complex<double>;
+    return gemm<double>(h, ta, tb, m, n, k, c(alpha->x, alpha->y), reinterpret_cast<const c*>(A), lda,
+                        reinterpret_cast<const c*>(B), ldb, c(beta->x, beta->y), reinterpret_cast<c*>(C), ldc);
 }

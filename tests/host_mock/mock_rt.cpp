@@ -266,6 +266,45 @@ rocfft_status rocfft_execute(const rocfft_plan, void**, void**, rocfft_execution
     return rocfft_status_success;
 }
 
+// rocBLAS: handles checked, every GEMM recorded as a node on the handle's stream
+#include <rocblas/rocblas.h>
+struct MockBlas { MockStream* stream = nullptr; };
+static std::set<void*> g_blas;
+rocblas_status rocblas_create_handle(rocblas_handle* h) {
+    *h = new MockBlas();
+    g_blas.insert(*h);
+    return rocblas_status_success;
+}
+rocblas_status rocblas_destroy_handle(rocblas_handle h) {
+    if (!g_blas.count(h)) FAIL("destroying an invalid rocBLAS handle");
+    g_blas.erase(h);
+    delete h;
+    return rocblas_status_success;
+}
+rocblas_status rocblas_set_stream(rocblas_handle h, MockStream* s) {
+    if (!g_blas.count(h)) FAIL("invalid rocBLAS handle");
+    h->stream = S(s, "rocblas_set_stream");
+    return rocblas_status_success;
+}
+static rocblas_status gemm_node(rocblas_handle h, int m, int n, int k, int lda, int ldb, int ldc) {
+    if (!g_blas.count(h)) FAIL("invalid rocBLAS handle");
+    if (m < 0 || n < 0 || k < 0 || lda < 1 || ldb < 1 || ldc < m) FAIL("gemm sizes");
+    node(S(h->stream, "rocblas gemm"));
+    return rocblas_status_success;
+}
+rocblas_status rocblas_cgemm(rocblas_handle h, rocblas_operation, rocblas_operation, rocblas_int m, rocblas_int n,
+                             rocblas_int k, const rocblas_float_complex*, const rocblas_float_complex*, rocblas_int lda,
+                             const rocblas_float_complex*, rocblas_int ldb, const rocblas_float_complex*,
+                             rocblas_float_complex*, rocblas_int ldc) {
+    return gemm_node(h, m, n, k, lda, ldb, ldc);
+}
+rocblas_status rocblas_zgemm(rocblas_handle h, rocblas_operation, rocblas_operation, rocblas_int m, rocblas_int n,
+                             rocblas_int k, const rocblas_double_complex*, const rocblas_double_complex*,
+                             rocblas_int lda, const rocblas_double_complex*, rocblas_int ldb,
+                             const rocblas_double_complex*, rocblas_double_complex*, rocblas_int ldc) {
+    return gemm_node(h, m, n, k, lda, ldb, ldc);
+}
+
 extern "C" void* mock_new_stream() {
     hipStream_t s;
     hipStreamCreateWithFlags(&s, 0);
@@ -274,4 +313,7 @@ extern "C" void* mock_new_stream() {
 extern "C" long mock_ops() { return g_ops; }
 extern "C" long mock_memsets_in_capture() { return g_memset_in_capture; }
 // handles still alive (streams include the caller's own)
-extern "C" long mock_live_handles() { return (long)(g_streams.size() + g_events.size() + g_graphs.size() + g_execs.size() + g_infos.size()); }
+extern "C" long mock_live_handles() {
+    return (long)(g_streams.size() + g_events.size() + g_graphs.size() + g_execs.size() + g_infos.size() +
+                  g_blas.size());
+}

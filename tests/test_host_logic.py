@@ -23,7 +23,7 @@ def _stubs():
     """Launcher stubs from the declarations in the kernel headers: each records
     a node on its stream (the last parameter) and returns hipSuccess."""
     out = ["namespace me {"]
-    for f in ("common.hpp", "fields.hpp", "adjoint.hpp"):
+    for f in ("common.hpp", "fields.hpp", "adjoint.hpp", "cp.hpp"):
         src = open(os.path.join(CSRC, f)).read()
         for m in re.finditer(r"(template <typename T>\s*)?hipError_t\s+(\w+)\(([^;]*?)\);", src, re.S):
             tmpl, name, params = m.group(1) or "", m.group(2), m.group(3)
@@ -36,6 +36,8 @@ def _stubs():
         "int local_force_chunks(int64_t) { return 512; }",
         "size_t ewald_scratch_doubles(int n) { return (size_t)(n > 0 ? n : 1) * 32; }",
         "int ewald_sg_blocks(int ng) { return ng > 0 ? (ng + 255) / 256 : 1; }",
+        "int cp_solve_blocks(int n) { return (n * n + 255) / 256; }",
+        "int64_t cp_sq_blocks(int64_t N) { return (N + 255) / 256; }",
         "}",
     ]
     return "\n".join(out) + "\n"
