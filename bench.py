@@ -19,6 +19,13 @@ grid size (32^3 to 96^3) and orbital count (8 to 256), FP32, advanced
 together, every Horner stage one persistent launch over all systems, steps
 replayed from a captured hipGraph, launch shape from the autotuner.
 
+A third workload (``cp``) times the paper's comparison scheme on the same
+96^3 system: Car-Parrinello with RATTLE / velocity Verlet (one H psi and five
+O(N_W^2 N_C) GEMMs per step), mu_cp = 200 and dt_cp = 0.184 au, and reports
+the cost of one atomic unit of simulated time for both schemes.
+``--cp-series`` adds the system-size series (grids 48^3 to 128^3, orbitals
+and ions in proportion to the volume) behind the cost crossover.
+
 Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
 """
 from __future__ import annotations
@@ -139,6 +146,78 @@ def run_batch(steps, warmup, eager_steps, autotune):
                     "kernel_avg_ms": avg_ms, "algorithmic_bytes_per_launch": avg_bytes},
         "max_norm_dev": norm_dev,
     }
+
+
+# Car-Parrinello parameters: the paper's benzene comparison uses mu = 15,
+# dt = 3.15 for the modified Ehrenfest scheme and mu_cp = 750, dt = 7.26 for
+# CP; the same ratios on this workload's mu = 4, dt = 0.08 give these.
+CP_MU = 4.0 * 750.0 / 15.0
+CP_DT = 0.08 * 7.26 / 3.15
+
+
+def cp_config(n: int):
+    """The single-system workload scaled to an n^3 grid: orbitals and ions in
+    proportion to the volume (multiples of 8 orbitals)."""
+    import workloads as W
+    f = (n / 96.0) ** 3
+    return W.C2.replace(name=f"cp{n}", n=n, n_orb=max(8, int(round(128 * f / 8.0)) * 8),
+                        n_ions=max(2, int(round(64 * f))), seed=812 + 7 + n)
+
+
+def time_scheme(cfg, scheme: str, steps: int, warmup: int = 2) -> float:
+    """ms per step of 'ehrenfest' or 'cp' on cfg (FP32, device-generated orbitals)."""
+    import torch
+    import workloads as W
+    from paper_0812_2801_amd import binding as B
+    p, keep = B.params_from_config(cfg, W.ion_positions(cfg), precision="f32")
+    s = B.System(p, keep, device="cuda:0")
+    psi = W.initial_orbitals_device(cfg, "cuda:0")
+    s.set_state(psi)
+    del psi
+    if scheme == "cp":
+        s.cp_begin(CP_MU, CP_DT)
+        step = s.cp_step
+    else:
+        step = s.step
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    rep = s.report()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    if not math.isfinite(rep["e_total"]):
+        raise RuntimeError(f"{scheme} on {cfg.name}: non-finite energy")
+    return ms
+
+
+def run_cp(steps: int, ehrenfest_ms: float, series: bool):
+    """CP on the 96^3 workload; the cost per atomic unit of simulated time of
+    both schemes (ms per step / dt); with `series`, the same over system size."""
+    import workloads as W
+    cp_ms = time_scheme(W.C2, "cp", steps)
+    out = {"workload": "96^3 h=0.25, 64 ions, 128 FP32 orbitals; Car-Parrinello with RATTLE / velocity Verlet, "
+                       f"mu_cp={CP_MU:g}, dt_cp={CP_DT:.4f}",
+           "ms_per_step": cp_ms, "dt": CP_DT, "ms_per_au": cp_ms / CP_DT,
+           "ehrenfest_ms_per_au": ehrenfest_ms / 0.08,
+           "ehrenfest_over_cp_cost_per_au": (ehrenfest_ms / 0.08) / (cp_ms / CP_DT)}
+    if series:
+        rows = []
+        for n in (48, 64, 80, 96, 112, 128):
+            cfg = cp_config(n)
+            e_ms = time_scheme(cfg, "ehrenfest", 10)
+            c_ms = time_scheme(cfg, "cp", 10)
+            row = {"n": n, "n_orb": cfg.n_orb, "n_ions": cfg.n_ions, "ehrenfest_ms_per_step": e_ms,
+                   "cp_ms_per_step": c_ms, "ehrenfest_over_cp_cost_per_au": (e_ms / 0.08) / (c_ms / CP_DT)}
+            print(f"# cp series {row}", file=sys.stderr, flush=True)
+            rows.append(row)
+        out["series"] = rows
+    return out
 
 
 def run_adjoint(every: int = 10):
@@ -270,6 +349,11 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
     ap.add_argument("--batch-only", action="store_true", help="run only the batched workload (profiling)")
+    ap.add_argument("--no-cp", action="store_true", help="skip the Car-Parrinello comparison")
+    ap.add_argument("--cp-steps", type=int, default=20)
+    ap.add_argument("--cp-series", action="store_true", help="add the system-size series of both schemes")
+    ap.add_argument("--cp-only", action="store_true",
+                    help="only the Car-Parrinello comparison (Ehrenfest timed at the same sizes)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -281,6 +365,11 @@ def main():
         return
     if args.batch_only:           # profiling aid: the batched workload alone
         print(json.dumps({"batched": run_batch(args.batch_steps, 8, 6, not args.no_autotune)}))
+        return
+    if args.cp_only:
+        import workloads as W
+        e_ms = time_scheme(W.C2, "ehrenfest", args.cp_steps)
+        print(json.dumps({"cp": run_cp(args.cp_steps, e_ms, args.cp_series)}))
         return
 
     import numpy as np
@@ -309,6 +398,11 @@ def main():
     if not args.no_batch:
         batch = run_batch(args.batch_steps, 8, 6, not args.no_autotune)
         print(f"# batch: {batch['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+
+    cp_run = None
+    if not args.no_cp:
+        cp_run = run_cp(args.cp_steps, main_run["ms_per_step"], args.cp_series)
+        print(f"# cp: {cp_run['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
 
     adj = None
     if not args.no_adjoint:
@@ -378,6 +472,8 @@ def main():
                              "stencil_avg_ms": bf_run["kernel_ms"] / max(1, bf_run["launches"])}
     if adj is not None:
         out["adjoint"] = adj
+    if cp_run is not None:
+        out["cp"] = cp_run
     if batch is not None:
         out["batched"] = batch
         out["batched_vs_single_system"] = batch["value"] / value

@@ -209,6 +209,10 @@ Geometry make_geometry(const me_params* p) {
 
 }  // namespace
 
+// the CP overlaps (N_W x N_W, sums over every grid point) run as this many
+// batched GEMMs over slices of the points, plus one for the remainder
+constexpr int CP_KSPLIT = 256;
+
 struct Layout {
     void *psi, *bufA, *bufB, *veff0, *veff1, *cnl;
     double *vloc_cur, *vloc_next, *vstatic, *hist[3], *rho, *vh;
@@ -228,10 +232,11 @@ struct Layout {
     void* inter[2][MAX_TAYLOR];
     void *psi_half, *psi_next, *lamA, *lamB, *ubA, *ubB;
     double *vbar[4], *wbar1, *wbar2, *gfine, *rhobar_T, *rhobar, *hv, *dpart, *scal;
-    // Car-Parrinello comparison step: N_W x N_W matrices (orbital precision),
-    // FP64 constraint-solve scratch, fictitious kinetic energy partials
-    void *cpA, *cpB, *cpX, *cpQ, *cpY;
-    double2 *cpX64, *cpR64;
+    // Car-Parrinello comparison step: overlap matrices A, B, Q and the solve
+    // scratch in FP64, the rotations X, Y in the orbital precision, the
+    // K-split partial overlaps, fictitious kinetic energy partials
+    double2 *cpA, *cpB, *cpQ, *cpX64, *cpR64;
+    void *cpX, *cpY, *cp_gpart;
     double *cp_part, *cp_info, *fict_part;
     size_t total;
 };
@@ -299,13 +304,14 @@ static Layout carve(const Geometry& g, char* base) {
     L.rep = c.take<double>(SLOT_COUNT * 8);
     L.scal0 = c.take<double>(64);
     const size_t mat = (size_t)g.n_orb * g.n_orb;
-    L.cpA = c.take<void>(mat * g.bc);
-    L.cpB = c.take<void>(mat * g.bc);
-    L.cpX = c.take<void>(mat * g.bc);
-    L.cpQ = c.take<void>(mat * g.bc);
-    L.cpY = c.take<void>(mat * g.bc);
+    L.cpA = c.take<double2>(mat * 16);
+    L.cpB = c.take<double2>(mat * 16);
+    L.cpQ = c.take<double2>(mat * 16);
     L.cpX64 = c.take<double2>(mat * 16);
     L.cpR64 = c.take<double2>(mat * 16);
+    L.cpX = c.take<void>(mat * g.bc);
+    L.cpY = c.take<void>(mat * g.bc);
+    L.cp_gpart = c.take<void>((size_t)(CP_KSPLIT + 1) * mat * g.bc);
     L.cp_part = c.take<double>((size_t)cp_solve_blocks(g.n_orb) * 8);
     L.cp_info = c.take<double>(2 * 8);
     L.fict_part = c.take<double>((size_t)g.nblk256 * 8);
@@ -1468,6 +1474,51 @@ rocblas_status cgemm(rocblas_handle h, rocblas_operation ta, rocblas_operation t
                          reinterpret_cast<rocblas_double_complex*>(C), ldc);
 }
 
+rocblas_status cgemm_batched(rocblas_handle h, int m, int n, int k, const float2* A, int lda, int64_t sa,
+                             const float2* B, int ldb, int64_t sb, float2* C, int ldc, int64_t sc, int batch) {
+    const rocblas_float_complex al(1.0f, 0.0f), be(0.0f, 0.0f);
+    return rocblas_cgemm_strided_batched(h, rocblas_operation_conjugate_transpose, rocblas_operation_none, m, n, k,
+                                         &al, reinterpret_cast<const rocblas_float_complex*>(A), lda, sa,
+                                         reinterpret_cast<const rocblas_float_complex*>(B), ldb, sb, &be,
+                                         reinterpret_cast<rocblas_float_complex*>(C), ldc, sc, batch);
+}
+rocblas_status cgemm_batched(rocblas_handle h, int m, int n, int k, const double2* A, int lda, int64_t sa,
+                             const double2* B, int ldb, int64_t sb, double2* C, int ldc, int64_t sc, int batch) {
+    const rocblas_double_complex al(1.0, 0.0), be(0.0, 0.0);
+    return rocblas_zgemm_strided_batched(h, rocblas_operation_conjugate_transpose, rocblas_operation_none, m, n, k,
+                                         &al, reinterpret_cast<const rocblas_double_complex*>(A), lda, sa,
+                                         reinterpret_cast<const rocblas_double_complex*>(B), ldb, sb, &be,
+                                         reinterpret_cast<rocblas_double_complex*>(C), ldc, sc, batch);
+}
+
+// out = h^3 X^H Y (N_W x N_W, FP64) for orbital sets X, Y of the system: the
+// grid points are cut into CP_KSPLIT slices, each slice's product is one
+// batch of a strided batched GEMM (the library then spreads the work over
+// the whole GPU instead of running a few output tiles down all the points),
+// the remainder is one more product, and the partial matrices are summed in
+// FP64 in a fixed order
+template <typename T>
+me_status cp_overlap(me_system* sys, const cx_t<T>* X, const cx_t<T>* Y, double2* out) {
+    using C = cx_t<T>;
+    const Geometry& g = sys->g;
+    const int n = g.n_orb, ld = (int)g.stride;
+    const int64_t kc = g.N / CP_KSPLIT, rem = g.N - kc * CP_KSPLIT;
+    C* part = (C*)sys->w.cp_gpart;
+    int nb = 0;
+    if (kc > 0) {
+        BLASCHK(cgemm_batched(sys->blas, n, n, (int)kc, X, ld, kc, Y, ld, kc, part, n, (int64_t)n * n, CP_KSPLIT));
+        nb = CP_KSPLIT;
+    }
+    if (rem > 0) {
+        const int64_t o = kc * CP_KSPLIT;
+        BLASCHK(cgemm_batched(sys->blas, n, n, (int)rem, X + o, ld, 0, Y + o, ld, 0, part + (int64_t)nb * n * n, n,
+                              0, 1));
+        ++nb;
+    }
+    HIPCHK(launch_cp_reduce<T>(part, nb, n, sys->prm.h * sys->prm.h * sys->prm.h, out, sys->stream));
+    return ME_OK;
+}
+
 // out = H in for the system's n_orb orbitals (stride g.stride), with the
 // current v_eff (veff0) and projector tables
 template <typename T>
@@ -1510,8 +1561,9 @@ me_status cp_step_impl(me_system* sys, bool energy) {
     C* psi = (C*)sys->w.psi;
     C* pdot = (C*)sys->w.bufA;
     C* trial = (C*)sys->w.bufB;                 // H psi on entry
-    C *A = (C*)sys->w.cpA, *B = (C*)sys->w.cpB, *X = (C*)sys->w.cpX, *Q = (C*)sys->w.cpQ, *Y = (C*)sys->w.cpY;
-    const rocblas_operation NN = rocblas_operation_none, CH = rocblas_operation_conjugate_transpose;
+    double2 *A = sys->w.cpA, *B = sys->w.cpB, *Q = sys->w.cpQ;
+    C *X = (C*)sys->w.cpX, *Y = (C*)sys->w.cpY;
+    const rocblas_operation NN = rocblas_operation_none;
     // 1. ions R(t+dt); V_loc and projector tables there
     HIPCHK(launch_ions_predict(sys->w.pos, sys->w.vel, sys->w.frc, sys->w.mass, g.n_ions, dt, sys->prm.freeze_ions,
                                sys->w.pos_next, sys->stream));
@@ -1519,8 +1571,8 @@ me_status cp_step_impl(me_system* sys, bool energy) {
     CHK(build_tables(sys, sys->w.pos_next, next));
     // 2-3. unconstrained orbitals, the constraint matrices, the rotation
     HIPCHK(launch_cp_predict<T>(trial, psi, pdot, g.stride, n, g.N, dt, dt * dt / (2.0 * mu), sys->stream));
-    BLASCHK(cgemm(sys->blas, CH, NN, n, n, N, h3, trial, ld, trial, ld, 0.0, A, n));
-    BLASCHK(cgemm(sys->blas, CH, NN, n, n, N, h3, psi, ld, trial, ld, 0.0, B, n));
+    CHK(cp_overlap<T>(sys, trial, trial, A));
+    CHK(cp_overlap<T>(sys, psi, trial, B));
     HIPCHK(launch_cp_solve_x<T>(A, B, n, CP_TOL, CP_MAX_ITER, sys->w.cpX64, sys->w.cpR64, sys->w.cp_part, X,
                                 sys->w.cp_info, sys->stream));
     BLASCHK(cgemm(sys->blas, NN, NN, N, n, n, 1.0, psi, ld, X, n, 1.0, trial, ld));
@@ -1541,7 +1593,7 @@ me_status cp_step_impl(me_system* sys, bool energy) {
     CHK(apply_h_self<T>(sys, psi, hpsi));
     // 6. velocity half kick and the velocity constraint
     HIPCHK(launch_cp_kick<T>(pdot, hpsi, g.stride, n, g.N, dt / (2.0 * mu), sys->stream));
-    BLASCHK(cgemm(sys->blas, CH, NN, n, n, N, h3, psi, ld, pdot, ld, 0.0, Q, n));
+    CHK(cp_overlap<T>(sys, psi, pdot, Q));
     HIPCHK(launch_cp_velocity_matrix<T>(Q, n, Y, sys->stream));
     BLASCHK(cgemm(sys->blas, NN, NN, N, n, n, 1.0, psi, ld, Y, n, 1.0, pdot, ld));
     if (energy) HIPCHK(launch_cp_sq_partial<T>(pdot, g.stride, n, g.N, sys->w.fict_part, sys->stream));

@@ -1,8 +1,10 @@
 // Car-Parrinello comparison step: orbital updates of RATTLE / velocity
 // Verlet and the position-constraint solve (eq. EoM_CP; the electronic
 // integrator the paper uses for its CP runs).  The O(N_W^2 N_C) overlap and
-// rotation products run as library GEMMs (api.hip); these kernels are the
-// O(N_W N_C) streams and the O(N_W^3) constraint iteration.
+// rotation products run as library GEMMs (api.hip), the overlaps split over
+// the grid points into batches whose partial matrices are summed here in FP64;
+// these kernels are that sum, the O(N_W N_C) streams and the O(N_W^3)
+// constraint iteration.
 #include "cp.hpp"
 
 namespace me {
@@ -71,9 +73,6 @@ __device__ __forceinline__ double2 cfma_conj(double2 a, double2 b, double2 c) { 
     return make_double2(c.x + (a.x * b.x + a.y * b.y), c.y + (a.x * b.y - a.y * b.x));
 }
 
-template <typename T>
-__device__ __forceinline__ double2 to_d2(cx_t<T> v) { return make_double2((double)v.x, (double)v.y); }
-
 __device__ __forceinline__ double block_max256(double v, double* sh) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -84,9 +83,28 @@ __device__ __forceinline__ double block_max256(double v, double* sh) {
     return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
 }
 
-// info[1] < 0 while the iteration runs; the corrections stop once it is set
 template <typename T>
-__global__ void __launch_bounds__(CP_B) cp_x_init_kernel(const cx_t<T>* __restrict__ A, int n,
+__global__ void __launch_bounds__(CP_B) cp_reduce_kernel(const cx_t<T>* __restrict__ part, int nb, int nn,
+                                                         double scale, double2* __restrict__ out) {
+    const int e = blockIdx.x * CP_B + threadIdx.x;
+    if (e >= nn) return;
+    double re = 0.0, im = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        const cx_t<T> v = part[(int64_t)b * nn + e];
+        re += (double)v.x;
+        im += (double)v.y;
+    }
+    out[e] = make_double2(scale * re, scale * im);
+}
+
+template <typename T>
+hipError_t launch_cp_reduce(const cx_t<T>* part, int nb, int n, double scale, double2* out, hipStream_t s) {
+    cp_reduce_kernel<T><<<cp_solve_blocks(n), CP_B, 0, s>>>(part, nb, n * n, scale, out);
+    return hipGetLastError();
+}
+
+// info[1] < 0 while the iteration runs; the corrections stop once it is set
+__global__ void __launch_bounds__(CP_B) cp_x_init_kernel(const double2* __restrict__ A, int n,
                                                          double2* __restrict__ X, double* __restrict__ info) {
     const int e = blockIdx.x * CP_B + threadIdx.x;
     if (e == 0) {
@@ -95,14 +113,13 @@ __global__ void __launch_bounds__(CP_B) cp_x_init_kernel(const cx_t<T>* __restri
     }
     if (e >= n * n) return;
     const int i = e % n, j = e / n;
-    const double2 a = to_d2<T>(A[e]);
+    const double2 a = A[e];
     X[e] = make_double2(0.5 * ((i == j ? 1.0 : 0.0) - a.x), -0.5 * a.y);
 }
 
 // R = A + B^H X + X B + X X - I for this block's elements; part[block] = max |R|
-template <typename T>
-__global__ void __launch_bounds__(CP_B) cp_x_residual_kernel(const cx_t<T>* __restrict__ A,
-                                                             const cx_t<T>* __restrict__ B, int n,
+__global__ void __launch_bounds__(CP_B) cp_x_residual_kernel(const double2* __restrict__ A,
+                                                             const double2* __restrict__ B, int n,
                                                              const double2* __restrict__ X, double2* __restrict__ R,
                                                              double* __restrict__ part, const double* __restrict__ info) {
     __shared__ double sh[4];
@@ -111,13 +128,13 @@ __global__ void __launch_bounds__(CP_B) cp_x_residual_kernel(const cx_t<T>* __re
     double worst = 0.0;
     if (e < n * n) {
         const int i = e % n, j = e / n;
-        double2 r = to_d2<T>(A[e]);
+        double2 r = A[e];
         if (i == j) r.x -= 1.0;
         for (int k = 0; k < n; ++k) {
             const double2 xkj = X[k + (int64_t)j * n];
             const double2 xik = X[i + (int64_t)k * n];
-            r = cfma_conj(to_d2<T>(B[k + (int64_t)i * n]), xkj, r);      // (B^H X)_ij
-            r = cfma(xik, to_d2<T>(B[k + (int64_t)j * n]), r);           // (X B)_ij
+            r = cfma_conj(B[k + (int64_t)i * n], xkj, r);                // (B^H X)_ij
+            r = cfma(xik, B[k + (int64_t)j * n], r);                     // (X B)_ij
             r = cfma(xik, xkj, r);                                       // (X X)_ij
         }
         R[e] = r;
@@ -161,12 +178,12 @@ __global__ void __launch_bounds__(CP_B) cp_x_out_kernel(const double2* __restric
 int cp_solve_blocks(int n) { return (n * n + CP_B - 1) / CP_B; }
 
 template <typename T>
-hipError_t launch_cp_solve_x(const cx_t<T>* A, const cx_t<T>* B, int n, double tol, int max_iter, double2* X64,
+hipError_t launch_cp_solve_x(const double2* A, const double2* B, int n, double tol, int max_iter, double2* X64,
                              double2* R64, double* part, cx_t<T>* X, double* info, hipStream_t s) {
     const int nb = cp_solve_blocks(n);
-    cp_x_init_kernel<T><<<nb, CP_B, 0, s>>>(A, n, X64, info);
+    cp_x_init_kernel<<<nb, CP_B, 0, s>>>(A, n, X64, info);
     for (int it = 0; it <= max_iter; ++it) {
-        cp_x_residual_kernel<T><<<nb, CP_B, 0, s>>>(A, B, n, X64, R64, part, info);
+        cp_x_residual_kernel<<<nb, CP_B, 0, s>>>(A, B, n, X64, R64, part, info);
         cp_x_update_kernel<<<nb, CP_B, 0, s>>>(n, tol, it, max_iter, X64, R64, part, nb, info);
     }
     cp_x_out_kernel<T><<<nb, CP_B, 0, s>>>(X64, n, X);
@@ -175,17 +192,17 @@ hipError_t launch_cp_solve_x(const cx_t<T>* A, const cx_t<T>* B, int n, double t
 
 // ------------------------------------------------------------ velocity matrix
 template <typename T>
-__global__ void __launch_bounds__(CP_B) cp_velocity_matrix_kernel(const cx_t<T>* __restrict__ Q, int n,
+__global__ void __launch_bounds__(CP_B) cp_velocity_matrix_kernel(const double2* __restrict__ Q, int n,
                                                                   cx_t<T>* __restrict__ Y) {
     const int e = blockIdx.x * CP_B + threadIdx.x;
     if (e >= n * n) return;
     const int i = e % n, j = e / n;
-    const cx_t<T> a = Q[e], b = Q[j + (int64_t)i * n];
-    Y[e] = cx_t<T>{(T)(-0.5) * (a.x + b.x), (T)(-0.5) * (a.y - b.y)};
+    const double2 a = Q[e], b = Q[j + (int64_t)i * n];
+    Y[e] = cx_t<T>{(T)(-0.5 * (a.x + b.x)), (T)(-0.5 * (a.y - b.y))};
 }
 
 template <typename T>
-hipError_t launch_cp_velocity_matrix(const cx_t<T>* Q, int n, cx_t<T>* Y, hipStream_t s) {
+hipError_t launch_cp_velocity_matrix(const double2* Q, int n, cx_t<T>* Y, hipStream_t s) {
     cp_velocity_matrix_kernel<T><<<cp_solve_blocks(n), CP_B, 0, s>>>(Q, n, Y);
     return hipGetLastError();
 }
@@ -225,9 +242,10 @@ hipError_t launch_cp_sq_partial(const cx_t<T>* psidot, int64_t stride, int n_orb
     template hipError_t launch_cp_halfvel<T>(cx_t<T>*, const cx_t<T>*, const cx_t<T>*, int64_t, int, int64_t, \
                                              double, hipStream_t);                                            \
     template hipError_t launch_cp_kick<T>(cx_t<T>*, const cx_t<T>*, int64_t, int, int64_t, double, hipStream_t); \
-    template hipError_t launch_cp_solve_x<T>(const cx_t<T>*, const cx_t<T>*, int, double, int, double2*,       \
+    template hipError_t launch_cp_reduce<T>(const cx_t<T>*, int, int, double, double2*, hipStream_t);         \
+    template hipError_t launch_cp_solve_x<T>(const double2*, const double2*, int, double, int, double2*,       \
                                              double2*, double*, cx_t<T>*, double*, hipStream_t);             \
-    template hipError_t launch_cp_velocity_matrix<T>(const cx_t<T>*, int, cx_t<T>*, hipStream_t);             \
+    template hipError_t launch_cp_velocity_matrix<T>(const double2*, int, cx_t<T>*, hipStream_t);             \
     template hipError_t launch_cp_sq_partial<T>(const cx_t<T>*, int64_t, int, int64_t, double*, hipStream_t);
 ME_CP_INST(double)
 ME_CP_INST(float)

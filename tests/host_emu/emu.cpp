@@ -731,3 +731,31 @@ rocblas_status rocblas_zgemm(rocblas_handle h, rocblas_operation ta, rocblas_ope
     return gemm<double>(h, ta, tb, m, n, k, c(alpha->x, alpha->y), reinterpret_cast<const c*>(A), lda,
                         reinterpret_cast<const c*>(B), ldb, c(beta->x, beta->y), reinterpret_cast<c*>(C), ldc);
 }
+rocblas_status rocblas_cgemm_strided_batched(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, rocblas_int m,
+                                             rocblas_int n, rocblas_int k, const rocblas_float_complex* alpha,
+                                             const rocblas_float_complex* A, rocblas_int lda, rocblas_stride sa,
+                                             const rocblas_float_complex* B, rocblas_int ldb, rocblas_stride sb,
+                                             const rocblas_float_complex* beta, rocblas_float_complex* C,
+                                             rocblas_int ldc, rocblas_stride sc, rocblas_int batch) {
+    if (batch < 1) FAIL("batch count %d", batch);
+    for (int b = 0; b < batch; ++b) {
+        const rocblas_status st =
+            rocblas_cgemm(h, ta, tb, m, n, k, alpha, A + b * sa, lda, B + b * sb, ldb, beta, C + b * sc, ldc);
+        if (st != rocblas_status_success) return st;
+    }
+    return rocblas_status_success;
+}
+rocblas_status rocblas_zgemm_strided_batched(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, rocblas_int m,
+                                             rocblas_int n, rocblas_int k, const rocblas_double_complex* alpha,
+                                             const rocblas_double_complex* A, rocblas_int lda, rocblas_stride sa,
+                                             const rocblas_double_complex* B, rocblas_int ldb, rocblas_stride sb,
+                                             const rocblas_double_complex* beta, rocblas_double_complex* C,
+                                             rocblas_int ldc, rocblas_stride sc, rocblas_int batch) {
+    if (batch < 1) FAIL("batch count %d", batch);
+    for (int b = 0; b < batch; ++b) {
+        const rocblas_status st =
+            rocblas_zgemm(h, ta, tb, m, n, k, alpha, A + b * sa, lda, B + b * sb, ldb, beta, C + b * sc, ldc);
+        if (st != rocblas_status_success) return st;
+    }
+    return rocblas_status_success;
+}

@@ -3,6 +3,7 @@
 #pragma once
 #include <cstdint>
 typedef int32_t rocblas_int;
+typedef int64_t rocblas_stride;
 typedef enum { rocblas_status_success = 0, rocblas_status_invalid_value = 3 } rocblas_status;
 typedef enum {
     rocblas_operation_none = 111,
@@ -31,3 +32,15 @@ rocblas_status rocblas_zgemm(rocblas_handle h, rocblas_operation ta, rocblas_ope
                              rocblas_int k, const rocblas_double_complex* alpha, const rocblas_double_complex* A,
                              rocblas_int lda, const rocblas_double_complex* B, rocblas_int ldb,
                              const rocblas_double_complex* beta, rocblas_double_complex* C, rocblas_int ldc);
+rocblas_status rocblas_cgemm_strided_batched(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, rocblas_int m,
+                                             rocblas_int n, rocblas_int k, const rocblas_float_complex* alpha,
+                                             const rocblas_float_complex* A, rocblas_int lda, rocblas_stride sa,
+                                             const rocblas_float_complex* B, rocblas_int ldb, rocblas_stride sb,
+                                             const rocblas_float_complex* beta, rocblas_float_complex* C,
+                                             rocblas_int ldc, rocblas_stride sc, rocblas_int batch);
+rocblas_status rocblas_zgemm_strided_batched(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, rocblas_int m,
+                                             rocblas_int n, rocblas_int k, const rocblas_double_complex* alpha,
+                                             const rocblas_double_complex* A, rocblas_int lda, rocblas_stride sa,
+                                             const rocblas_double_complex* B, rocblas_int ldb, rocblas_stride sb,
+                                             const rocblas_double_complex* beta, rocblas_double_complex* C,
+                                             rocblas_int ldc, rocblas_stride sc, rocblas_int batch);

@@ -305,6 +305,25 @@ rocblas_status rocblas_zgemm(rocblas_handle h, rocblas_operation, rocblas_operat
     return gemm_node(h, m, n, k, lda, ldb, ldc);
 }
 
+rocblas_status rocblas_cgemm_strided_batched(rocblas_handle h, rocblas_operation, rocblas_operation, rocblas_int m,
+                                             rocblas_int n, rocblas_int k, const rocblas_float_complex*,
+                                             const rocblas_float_complex*, rocblas_int lda, rocblas_stride,
+                                             const rocblas_float_complex*, rocblas_int ldb, rocblas_stride,
+                                             const rocblas_float_complex*, rocblas_float_complex*, rocblas_int ldc,
+                                             rocblas_stride, rocblas_int batch) {
+    if (batch < 1) FAIL("batch count");
+    return gemm_node(h, m, n, k, lda, ldb, ldc);
+}
+rocblas_status rocblas_zgemm_strided_batched(rocblas_handle h, rocblas_operation, rocblas_operation, rocblas_int m,
+                                             rocblas_int n, rocblas_int k, const rocblas_double_complex*,
+                                             const rocblas_double_complex*, rocblas_int lda, rocblas_stride,
+                                             const rocblas_double_complex*, rocblas_int ldb, rocblas_stride,
+                                             const rocblas_double_complex*, rocblas_double_complex*, rocblas_int ldc,
+                                             rocblas_stride, rocblas_int batch) {
+    if (batch < 1) FAIL("batch count");
+    return gemm_node(h, m, n, k, lda, ldb, ldc);
+}
+
 extern "C" void* mock_new_stream() {
     hipStream_t s;
     hipStreamCreateWithFlags(&s, 0);
