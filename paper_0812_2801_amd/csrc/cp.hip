@@ -83,23 +83,33 @@ __device__ __forceinline__ double block_max256(double v, double* sh) {
     return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
 }
 
+// 64 elements per workgroup; wave w sums the partials b = w, w + 4, ... of
+// its element, and the four wave sums are added in wave order
 template <typename T>
 __global__ void __launch_bounds__(CP_B) cp_reduce_kernel(const cx_t<T>* __restrict__ part, int nb, int nn,
                                                          double scale, double2* __restrict__ out) {
-    const int e = blockIdx.x * CP_B + threadIdx.x;
-    if (e >= nn) return;
+    __shared__ double2 sh[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + lane;
     double re = 0.0, im = 0.0;
-    for (int b = 0; b < nb; ++b) {
-        const cx_t<T> v = part[(int64_t)b * nn + e];
-        re += (double)v.x;
-        im += (double)v.y;
+    if (e < nn)
+        for (int b = wv; b < nb; b += 4) {
+            const cx_t<T> v = part[(int64_t)b * nn + e];
+            re += (double)v.x;
+            im += (double)v.y;
+        }
+    sh[wv][lane] = make_double2(re, im);
+    __syncthreads();
+    if (wv == 0 && e < nn) {
+        const double r = ((sh[0][lane].x + sh[1][lane].x) + sh[2][lane].x) + sh[3][lane].x;
+        const double i = ((sh[0][lane].y + sh[1][lane].y) + sh[2][lane].y) + sh[3][lane].y;
+        out[e] = make_double2(scale * r, scale * i);
     }
-    out[e] = make_double2(scale * re, scale * im);
 }
 
 template <typename T>
 hipError_t launch_cp_reduce(const cx_t<T>* part, int nb, int n, double scale, double2* out, hipStream_t s) {
-    cp_reduce_kernel<T><<<cp_solve_blocks(n), CP_B, 0, s>>>(part, nb, n * n, scale, out);
+    cp_reduce_kernel<T><<<(n * n + 63) / 64, CP_B, 0, s>>>(part, nb, n * n, scale, out);
     return hipGetLastError();
 }
 

@@ -48,6 +48,8 @@ def stats(csv_path, out, command):
              "| kernel | calls | avg µs | total % |", "|---|---:|---:|---:|"]
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:25]:
         name = r["Name"].split("(")[0].replace("|", "/")
+        if name.startswith("Cijk_") and len(name) > 60:        # library GEMM: tile and MFMA fields only
+            name = "_".join(name.split("_")[:6]) + "_..."
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                      f"{100 * float(r['TotalDurationNs']) / tot:.1f} |")
     open(out, "w").write("\n".join(lines) + "\n")
