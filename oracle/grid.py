@@ -45,6 +45,28 @@ def central_second_difference_coeffs(order: int = 8):
 FD8 = tuple(float(x) for x in central_second_difference_coeffs(8))
 
 
+def central_first_difference_coeffs(order: int = 8):
+    """Exact rational a_1..a_{order/2} of f'(0) ~ (1/h) sum_m a_m (f(m h) - f(-m h)):
+    the moment conditions sum_m 2 m^(2k-1) a_m = delta_{k,1}, k = 1..order/2."""
+    p = order // 2
+    a = [[Fraction(2 * m ** (2 * k - 1)) for m in range(1, p + 1)] for k in range(1, p + 1)]
+    b = [Fraction(1) if k == 1 else Fraction(0) for k in range(1, p + 1)]
+    n = p
+    for i in range(n):
+        piv = next(r for r in range(i, n) if a[r][i] != 0)
+        a[i], a[piv] = a[piv], a[i]
+        b[i], b[piv] = b[piv], b[i]
+        for r in range(n):
+            if r != i and a[r][i] != 0:
+                f = a[r][i] / a[i][i]
+                a[r] = [x - f * y for x, y in zip(a[r], a[i])]
+                b[r] = b[r] - f * b[i]
+    return [b[i] / a[i][i] for i in range(n)]
+
+
+FD8_FIRST = tuple(float(x) for x in central_first_difference_coeffs(8))
+
+
 class Grid:
     """Periodic cube of n^3 points with spacing h (origin at a corner)."""
 
@@ -87,6 +109,18 @@ class Grid:
             for m in range(1, 5):
                 out = out + c[m] * (np.roll(f, m, axis=ax) + np.roll(f, -m, axis=ax))
         return out / (self.h * self.h)
+
+    def gradient(self, f: np.ndarray) -> np.ndarray:
+        """8th-order central first differences of f [..., z, y, x] along x, y, z;
+        returns [3, ...]."""
+        a = FD8_FIRST
+        out = []
+        for ax in (-1, -2, -3):
+            g = np.zeros_like(f)
+            for m in range(1, 5):
+                g = g + a[m - 1] * (np.roll(f, -m, axis=ax) - np.roll(f, m, axis=ax))
+            out.append(g / self.h)
+        return np.array(out)
 
     def kinetic(self, f: np.ndarray) -> np.ndarray:
         """T f = -1/2 Laplacian f (eq. new_EoM(a))."""

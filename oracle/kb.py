@@ -79,6 +79,19 @@ def force_columns(grid: Grid, sph: List[Sphere], sigma: float,
     return out
 
 
+def force_columns_gradient(grid: Grid, sph: List[Sphere], psi: np.ndarray) -> np.ndarray:
+    """The wave-function-gradient form of d c_JA / d R_J (the footnote of
+    sec. 5.1): d/dR_J of p_J(r - R_J) is -grad_r p_J, moved onto the orbital,
+    d[J, A, :] = h^3 sum_k p_J(r_k) (grad psi_A)(r_k) with the 8th-order
+    finite-difference gradient."""
+    g = grid.gradient(psi).reshape(3, psi.shape[0], -1)     # [3, A, N]
+    out = np.zeros((len(sph), psi.shape[0], 3), dtype=np.complex128)
+    for J, s in enumerate(sph):
+        for c in range(3):
+            out[J, :, c] = grid.dv * (g[c][:, s.idx] @ s.p)
+    return out
+
+
 def energy(c: np.ndarray, ekb: float, occ: float) -> float:
     """E_NL = f E_KB sum_{J,A} |c_JA|^2."""
     return occ * ekb * float(np.sum(np.abs(c) ** 2))

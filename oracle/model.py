@@ -118,12 +118,17 @@ class Model:
         return parts
 
     # ------------------------------------------------------------ forces
-    def forces(self, pos: np.ndarray, psi: np.ndarray, rho: np.ndarray) -> dict:
+    def forces(self, pos: np.ndarray, psi: np.ndarray, rho: np.ndarray, nl_form: str = "projector") -> dict:
+        """Hellmann-Feynman forces; nl_form "gradient" takes the nonlocal part
+        in the wave-function-gradient form (kb.force_columns_gradient)."""
         g = self.grid
         floc = potentials.local_forces(g, pos, self.zval, self.loc_a, rho)
         sph = self.spheres(pos)
         c = kb.contract(g, sph, psi)
-        dc = kb.force_columns(g, sph, self.kb_sigma, psi)
+        if nl_form == "gradient":
+            dc = kb.force_columns_gradient(g, sph, psi)
+        else:
+            dc = kb.force_columns(g, sph, self.kb_sigma, psi)
         fnl = kb.forces(c, dc, self.kb_energy, self.occ)
         _, fion = potentials.ewald(g.L, pos, self.zval)
         return {"local": floc, "nonlocal": fnl, "ion": fion,
