@@ -354,6 +354,8 @@ def main():
     ap.add_argument("--cp-series", action="store_true", help="add the system-size series of both schemes")
     ap.add_argument("--cp-only", action="store_true",
                     help="only the Car-Parrinello comparison (Ehrenfest timed at the same sizes)")
+    ap.add_argument("--dt-scan", action="store_true",
+                    help="only the largest stable time step against the grid spacing (Taylor-4, Taylor-8, CP)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -365,6 +367,10 @@ def main():
         return
     if args.batch_only:           # profiling aid: the batched workload alone
         print(json.dumps({"batched": run_batch(args.batch_steps, 8, 6, not args.no_autotune)}))
+        return
+    if args.dt_scan:
+        from paper_0812_2801_amd import scan
+        print(json.dumps({"dt_max_vs_spacing": scan.spacing_series()}))
         return
     if args.cp_only:
         import workloads as W

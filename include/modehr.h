@@ -96,6 +96,10 @@ typedef struct {
     int32_t precision;     /* me_precision */
     int32_t freeze_ions;   /* nonzero: ions do not move (forces still computed) */
     int32_t enable_adjoint;/* nonzero: reserve the adjoint buffers (requires freeze_ions) */
+    int32_t nl_force_form; /* nonlocal force: 0 the analytic derivative of the projector,
+                              1 the wave-function-gradient form (footnote of sec. 5.1):
+                              d c_JA / d R_J as h^3 sum p_J grad psi_A with the 8th-order
+                              finite-difference gradient */
 } me_params;
 
 /* Diagnostics of the current state.  Energies in hartree. */

@@ -167,6 +167,7 @@ me_status validate(const me_params* p, std::string& err) {
     if (p->taylor_order < 1 || p->taylor_order > MAX_TAYLOR) { err = "taylor_order must be in [1, 8]"; return ME_EINVAL; }
     if (p->precision < ME_F64 || p->precision > ME_F32_BF16X3) { err = "unknown precision"; return ME_EINVAL; }
     if (p->enable_adjoint && !p->freeze_ions) { err = "the adjoint needs frozen ions"; return ME_EUNSUPPORTED; }
+    if (p->nl_force_form != 0 && p->nl_force_form != 1) { err = "nl_force_form must be 0 or 1"; return ME_EINVAL; }
     const bool f64 = p->precision == ME_F64;
     const int px = choose_px(p->n[0], f64);
     if (choose_ty(p->n[0], p->n[1], px, f64 ? 16 : 8) < 0) { err = "grid x extent too large for one workgroup row"; return ME_EUNSUPPORTED; }
@@ -490,11 +491,11 @@ me_status forces_parts(me_system* sys, const double* pos, int t) {
                                sys->prm.h, sys->prm.loc_a, sys->w.floc_part, sys->w.floc, sys->stream));
     if (g.f64)
         HIPCHK(launch_kb_forces<double>((const double2*)sys->w.psi, g.stride, g.n_orb, g.n_ions, tables(sys, t), pos,
-                                        sys->geo, g.nx, g.ny, sys->prm.occ, sys->prm.kb_energy, sys->w.fnl,
+                                        sys->geo, g.nx, g.ny, g.nz, sys->prm.nl_force_form, sys->prm.occ, sys->prm.kb_energy, sys->w.fnl,
                                         sys->w.enl_part, sys->w.kbf_part, sys->stream));
     else
         HIPCHK(launch_kb_forces<float>((const float2*)sys->w.psi, g.stride, g.n_orb, g.n_ions, tables(sys, t), pos,
-                                       sys->geo, g.nx, g.ny, sys->prm.occ, sys->prm.kb_energy, sys->w.fnl,
+                                       sys->geo, g.nx, g.ny, g.nz, sys->prm.nl_force_form, sys->prm.occ, sys->prm.kb_energy, sys->w.fnl,
                                        sys->w.enl_part, sys->w.kbf_part, sys->stream));
     HIPCHK(launch_ewald(sys->ewp, pos, sys->w.zval, g.n_ions, sys->w.ewald_sg, sys->w.erec_part, sys->w.fion,
                         sys->w.eion_part, sys->w.ewald_part, sys->stream));
@@ -1538,7 +1539,23 @@ me_status apply_h_self(me_system* sys, const cx_t<T>* in, cx_t<T>* out) {
 }
 
 constexpr double CP_TOL = 1e-12;     // max |residual| of the position constraint
-constexpr int CP_MAX_ITER = 12;
+
+// Corrections of the constraint iteration: it contracts by about
+// q = dt^2 E_max / (2 mu_cp) per correction (I - B is of that size), E_max
+// estimated by the edge of the finite-difference kinetic spectrum
+// (-3/(2h^2) times the 1-D symbol at k = pi) plus 10 hartree for the
+// potentials; enough corrections to reach CP_TOL, at least 8, at most 60.
+int cp_max_iter(const me_system* sys) {
+    const double h = sys->prm.h;
+    const double c[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+    double sym = c[0];
+    for (int m = 1; m <= 4; ++m) sym += 2.0 * c[m] * ((m % 2) ? -1.0 : 1.0);
+    const double e_max = -1.5 * sym / (h * h) + 10.0;
+    const double q = sys->dt_cp * sys->dt_cp * e_max / (2.0 * sys->mu_cp);
+    if (q >= 0.95) return 60;
+    const int it = (int)std::ceil(std::log(CP_TOL) / std::log(std::max(q, 1e-3))) + 4;
+    return std::min(60, std::max(8, it));
+}
 
 template <typename T>
 me_status cp_begin_impl(me_system* sys) {
@@ -1573,7 +1590,7 @@ me_status cp_step_impl(me_system* sys, bool energy) {
     HIPCHK(launch_cp_predict<T>(trial, psi, pdot, g.stride, n, g.N, dt, dt * dt / (2.0 * mu), sys->stream));
     CHK(cp_overlap<T>(sys, trial, trial, A));
     CHK(cp_overlap<T>(sys, psi, trial, B));
-    HIPCHK(launch_cp_solve_x<T>(A, B, n, CP_TOL, CP_MAX_ITER, sys->w.cpX64, sys->w.cpR64, sys->w.cp_part, X,
+    HIPCHK(launch_cp_solve_x<T>(A, B, n, CP_TOL, cp_max_iter(sys), sys->w.cpX64, sys->w.cpR64, sys->w.cp_part, X,
                                 sys->w.cp_info, sys->stream));
     BLASCHK(cgemm(sys->blas, NN, NN, N, n, n, 1.0, psi, ld, X, n, 1.0, trial, ld));
     // 4. half-step velocities; the new orbitals become the state

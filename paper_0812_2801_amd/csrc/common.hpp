@@ -147,12 +147,15 @@ hipError_t launch_kb_gather_bf16x3(const float2* u, int64_t stride, int n_orb, i
                                    double ekb_h3, float2* cnl, hipStream_t s);
 
 // nonlocal forces and energy, FP64 accumulation:
-// fnl[J][3] = -2 f E_KB sum_A Re(conj(c_JA) d_JA); enl_part[J] = f E_KB sum_A |c_JA|^2
+// fnl[J][3] = -2 f E_KB sum_A Re(conj(c_JA) d_JA); enl_part[J] = f E_KB sum_A |c_JA|^2,
+// d_JA = d c_JA / d R_J: form 0 the analytic projector derivative
+// h^3 sum (r - R_J)/s^2 p_J psi_A, form 1 the wave-function-gradient form
+// h^3 sum p_J grad psi_A (8th-order finite differences)
 // scratch: [n_ions][ceil(n_orb/16)][4] doubles
 template <typename T>
 hipError_t launch_kb_forces(const cx_t<T>* psi, int64_t stride, int n_orb, int n_ions,
                             KbTables t, const double* pos, const KbGeom& g,
-                            int nx, int ny, double occ, double ekb,
+                            int nx, int ny, int nz, int form, double occ, double ekb,
                             double* fnl, double* enl_part, double* scratch, hipStream_t s);
 
 // rho[i] = occ * sum_A |psi_A[i]|^2 (FP64)

@@ -446,12 +446,17 @@ hipError_t launch_kb_gather_bf16x3(const float2* u, int64_t stride, int n_orb, i
 // F_J = -2 f E_KB h^6 / s^2 sum_A Re(conj(c) d), E_J = f E_KB h^6 sum_A |c|^2.
 constexpr int KBF_OB = 16;
 
-template <typename T>
+// 8th-order central first difference: f' ~ (1/h) sum_m a_m (f(x + m h) - f(x - m h))
+__device__ constexpr double FD1[4] = {4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
+
+// GRAD: the columns are h^3 sum p_J grad psi_A (finite-difference gradient,
+// the wave-function-gradient form) instead of h^3 sum p_J (r - R_J) psi_A
+template <typename T, bool GRAD>
 __global__ void __launch_bounds__(256) kb_forces_kernel(const cx_t<T>* __restrict__ psi, int64_t stride,
                                                         int n_orb, const int32_t* __restrict__ idx,
                                                         const int32_t* __restrict__ count, int kcap,
                                                         const double* __restrict__ pos, KbGeom g,
-                                                        int nx, int ny, double* __restrict__ part) {
+                                                        int nx, int ny, int nz, double* __restrict__ part) {
     __shared__ double red[4][4];
     const int J = blockIdx.x;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -474,9 +479,30 @@ __global__ void __launch_bounds__(256) kb_forces_kernel(const cx_t<T>* __restric
             const cx_t<T> zv = pa[lin];
             const double pr = w * (double)zv.x, pi = w * (double)zv.y;
             cr += pr; ci += pi;
-            xr += dx * pr; xi += dx * pi;
-            yr += dy * pr; yi += dy * pi;
-            zr += dz * pr; zi += dz * pi;
+            if constexpr (GRAD) {
+                const int64_t plane = (int64_t)nx * ny;
+                const int64_t row = lin - gx, col = lin - (int64_t)gy * nx, pil = lin - (int64_t)gz * plane;
+                double ax = 0, bx = 0, ay = 0, by = 0, az = 0, bz = 0;
+#pragma unroll
+                for (int m = 1; m <= 4; ++m) {
+                    const cx_t<T> xp = pa[row + wrap1(gx + m, nx)], xm = pa[row + wrap1(gx - m, nx)];
+                    const cx_t<T> yp = pa[col + (int64_t)wrap1(gy + m, ny) * nx];
+                    const cx_t<T> ym = pa[col + (int64_t)wrap1(gy - m, ny) * nx];
+                    const cx_t<T> zp = pa[pil + (int64_t)wrap1(gz + m, nz) * plane];
+                    const cx_t<T> zm = pa[pil + (int64_t)wrap1(gz - m, nz) * plane];
+                    const double a = FD1[m - 1];
+                    ax += a * ((double)xp.x - (double)xm.x); bx += a * ((double)xp.y - (double)xm.y);
+                    ay += a * ((double)yp.x - (double)ym.x); by += a * ((double)yp.y - (double)ym.y);
+                    az += a * ((double)zp.x - (double)zm.x); bz += a * ((double)zp.y - (double)zm.y);
+                }
+                xr += w * ax; xi += w * bx;
+                yr += w * ay; yi += w * by;
+                zr += w * az; zi += w * bz;
+            } else {
+                xr += dx * pr; xi += dx * pi;
+                yr += dy * pr; yi += dy * pi;
+                zr += dz * pr; zi += dz * pi;
+            }
         }
         cr = wsum_t(cr); ci = wsum_t(ci);
         xr = wsum_t(xr); xi = wsum_t(xi);
@@ -513,15 +539,22 @@ __global__ void kb_forces_reduce_kernel(const double* __restrict__ part, int nbl
 template <typename T>
 hipError_t launch_kb_forces(const cx_t<T>* psi, int64_t stride, int n_orb, int n_ions,
                             KbTables t, const double* pos, const KbGeom& g,
-                            int nx, int ny, double occ, double ekb,
+                            int nx, int ny, int nz, int form, double occ, double ekb,
                             double* fnl, double* enl_part, double* scratch, hipStream_t s) {
     if (n_ions == 0) return hipSuccess;
+    if (form != 0 && form != 1) return hipErrorInvalidValue;
     const int nblk = (n_orb + KBF_OB - 1) / KBF_OB;
     dim3 grid(n_ions, nblk);
-    kb_forces_kernel<T><<<grid, 256, 0, s>>>(psi, stride, n_orb, t.idx, t.count, t.kcap, pos, g, nx, ny, scratch);
+    if (form == 1)
+        kb_forces_kernel<T, true><<<grid, 256, 0, s>>>(psi, stride, n_orb, t.idx, t.count, t.kcap, pos, g, nx, ny,
+                                                       nz, scratch);
+    else
+        kb_forces_kernel<T, false><<<grid, 256, 0, s>>>(psi, stride, n_orb, t.idx, t.count, t.kcap, pos, g, nx, ny,
+                                                        nz, scratch);
     const double h6 = g.h * g.h * g.h * g.h * g.h * g.h;
-    kb_forces_reduce_kernel<<<(n_ions + 63) / 64, 64, 0, s>>>(scratch, nblk, n_ions, -2.0 * occ * ekb * h6 * g.inv_s2,
-                                                             occ * ekb * h6, fnl, enl_part);
+    const double kf = -2.0 * occ * ekb * h6 * (form == 1 ? 1.0 / g.h : g.inv_s2);
+    kb_forces_reduce_kernel<<<(n_ions + 63) / 64, 64, 0, s>>>(scratch, nblk, n_ions, kf, occ * ekb * h6, fnl,
+                                                             enl_part);
     return hipGetLastError();
 }
 
@@ -531,7 +564,7 @@ template hipError_t launch_kb_fixup<double>(cx_t<double>*, int64_t, int, KbTable
 template hipError_t launch_kb_fixup<float>(cx_t<float>*, int64_t, int, KbTables, const cx_t<float>*, double, double, double*, hipStream_t);
 template hipError_t launch_kb_gather<double>(const cx_t<double>*, int64_t, int, int, KbTables, double, cx_t<double>*, hipStream_t);
 template hipError_t launch_kb_gather<float>(const cx_t<float>*, int64_t, int, int, KbTables, double, cx_t<float>*, hipStream_t);
-template hipError_t launch_kb_forces<double>(const cx_t<double>*, int64_t, int, int, KbTables, const double*, const KbGeom&, int, int, double, double, double*, double*, double*, hipStream_t);
-template hipError_t launch_kb_forces<float>(const cx_t<float>*, int64_t, int, int, KbTables, const double*, const KbGeom&, int, int, double, double, double*, double*, double*, hipStream_t);
+template hipError_t launch_kb_forces<double>(const cx_t<double>*, int64_t, int, int, KbTables, const double*, const KbGeom&, int, int, int, int, double, double, double*, double*, double*, hipStream_t);
+template hipError_t launch_kb_forces<float>(const cx_t<float>*, int64_t, int, int, KbTables, const double*, const KbGeom&, int, int, int, int, double, double, double*, double*, double*, hipStream_t);
 
 }  // namespace me

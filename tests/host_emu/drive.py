@@ -120,6 +120,17 @@ if scenario == "system":
         print(f"{c.name}: max|d(H psi)| {dh:.2e}", flush=True)
         assert dh <= (1e-10 if prec == "f64" else 1e-3) * max(1.0, np.abs(ref).max())
         ok(lib.me_destroy(h))
+        # the wave-function-gradient form of the nonlocal force, at the initial state
+        h = new_system(c, inp, nl_force_form=1)
+        ok(lib.me_set_state(h, psi.ctypes.data, c.n_points), h)
+        _, f = state(h, c)
+        m = Model.from_config(c)
+        st0 = dynamics.init_state(m, inp["psi"], inp["pos"])
+        want = m.forces(st0.pos, st0.psi, st0.rho, nl_form="gradient")["total"]
+        dfg = np.abs(f - want.ravel()).max()
+        print(f"{c.name}: gradient-form forces max|dF| {dfg:.2e}", flush=True)
+        assert dfg <= TOL_F
+        ok(lib.me_destroy(h))
 elif scenario == "batch":
     arr = (B.Params * len(UNEVEN))()
     keep, inps = [], []
