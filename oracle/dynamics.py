@@ -107,6 +107,32 @@ def aetrs_step(model: Model, st: State, eps: float = 0.0) -> State:
                  step=st.step + 1)
 
 
+def etrs_step(model: Model, st: State, eps: float = 0.0, iterations: int = 2) -> State:
+    """The enforced time-reversal-symmetry propagator that AETRS approximates
+    (sec. 5.1): the second exponential uses H(t+dt) built from the density of
+    the orbitals it produces.  Here: the AETRS result (extrapolated v_Hxc) is
+    the prediction, then `iterations` corrections recompute the second
+    exponential from the half-step orbitals with v_Hxc of the latest
+    density.  iterations = 0 is AETRS."""
+    pos1, h0, h1 = step_hamiltonians(model, st, eps)
+    tau = model.dt / (2.0 * model.mu)
+    half = taylor(model, tau, h0[0], h0[1], st.psi)
+    psi1 = taylor(model, tau, h1[0], h1[1], half)
+    ext = eps * model.field_x() if eps != 0.0 else 0.0
+    for _ in range(iterations):
+        veff1 = model.vloc(pos1) + model.v_hxc(model.density(psi1)) + ext
+        psi1 = taylor(model, tau, veff1, h1[1], half)
+    rho1 = model.density(psi1)
+    hist = (st.hist + [model.v_hxc(rho1)])[-3:]
+    f1 = model.forces(pos1, psi1, rho1)["total"]
+    if model.freeze_ions:
+        vel1 = st.vel.copy()
+    else:
+        vel1 = st.vel + (st.force + f1) * model.dt / (2.0 * model.mass[:, None])
+    return State(psi=psi1, pos=pos1, vel=vel1, force=f1, rho=rho1, hist=hist,
+                 step=st.step + 1)
+
+
 def total_energy(model: Model, st: State) -> dict:
     parts = model.energy(st.pos, st.psi, st.rho)
     parts["ion_kinetic"] = 0.5 * float(np.sum(model.mass[:, None] * st.vel ** 2))
