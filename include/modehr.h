@@ -100,6 +100,11 @@ typedef struct {
                               1 the wave-function-gradient form (footnote of sec. 5.1):
                               d c_JA / d R_J as h^3 sum p_J grad psi_A with the 8th-order
                               finite-difference gradient */
+    int32_t etrs_iterations; /* 0: AETRS (eq. aetrs: H(t+dt) with the extrapolated v_Hxc);
+                                k in 1..8: ETRS, the second exponential redone k times from
+                                the half-step orbitals with v_Hxc of the latest density
+                                (needs one more orbital buffer; not with batches or the
+                                adjoint) */
 } me_params;
 
 /* Diagnostics of the current state.  Energies in hartree. */

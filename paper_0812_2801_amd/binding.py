@@ -43,7 +43,7 @@ class Params(ctypes.Structure):
         ("kb_energy", c_double), ("n_orb", c_int32), ("occ", c_double),
         ("mu", c_double), ("dt", c_double), ("taylor_order", c_int32),
         ("precision", c_int32), ("freeze_ions", c_int32), ("enable_adjoint", c_int32),
-        ("nl_force_form", c_int32),
+        ("nl_force_form", c_int32), ("etrs_iterations", c_int32),
     ]
 
 
@@ -138,7 +138,8 @@ def _dptr(a: np.ndarray):
 
 def make_params(*, n, h, pos, mass, zval, n_orb, mu, dt, vel=None, loc_a=0.5,
                 kb_sigma=0.4, kb_rcut=1.2, kb_energy=2.0, occ=2.0, taylor_order=4,
-                precision="f64", freeze_ions=False, enable_adjoint=False, nl_force_form=0):
+                precision="f64", freeze_ions=False, enable_adjoint=False, nl_force_form=0,
+                etrs_iterations=0):
     """Params plus the host arrays it points to (keep both alive)."""
     pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
     mass = np.ascontiguousarray(mass, dtype=np.float64).ravel()
@@ -164,6 +165,7 @@ def make_params(*, n, h, pos, mass, zval, n_orb, mu, dt, vel=None, loc_a=0.5,
     p.freeze_ions = int(bool(freeze_ions))
     p.enable_adjoint = int(bool(enable_adjoint))
     p.nl_force_form = int(nl_force_form)
+    p.etrs_iterations = int(etrs_iterations)
     return p, keep
 
 

@@ -96,6 +96,7 @@ struct Geometry {
     int ewald_ng;
     bool adjoint;
     int taylor;
+    int etrs;          // ETRS corrections of the second exponential (0: AETRS)
 };
 
 int env_int(const char* name, int dflt) {
@@ -168,6 +169,8 @@ me_status validate(const me_params* p, std::string& err) {
     if (p->precision < ME_F64 || p->precision > ME_F32_BF16X3) { err = "unknown precision"; return ME_EINVAL; }
     if (p->enable_adjoint && !p->freeze_ions) { err = "the adjoint needs frozen ions"; return ME_EUNSUPPORTED; }
     if (p->nl_force_form != 0 && p->nl_force_form != 1) { err = "nl_force_form must be 0 or 1"; return ME_EINVAL; }
+    if (p->etrs_iterations < 0 || p->etrs_iterations > 8) { err = "etrs_iterations must be in [0, 8]"; return ME_EINVAL; }
+    if (p->etrs_iterations > 0 && p->enable_adjoint) { err = "the adjoint is defined for AETRS"; return ME_EUNSUPPORTED; }
     const bool f64 = p->precision == ME_F64;
     const int px = choose_px(p->n[0], f64);
     if (choose_ty(p->n[0], p->n[1], px, f64 ? 16 : 8) < 0) { err = "grid x extent too large for one workgroup row"; return ME_EUNSUPPORTED; }
@@ -204,6 +207,7 @@ Geometry make_geometry(const me_params* p) {
     g.nblk256 = (g.N + 255) / 256;
     g.fft_work = (size_t)(2 * g.nhalf) * 16;
     g.adjoint = p->enable_adjoint != 0;
+    g.etrs = p->etrs_iterations;
     g.taylor = p->taylor_order;
     return g;
 }
@@ -232,6 +236,7 @@ struct Layout {
     // half-step and next orbitals, adjoint orbitals, and FP64 grid buffers
     void* inter[2][MAX_TAYLOR];
     void *psi_half, *psi_next, *lamA, *lamB, *ubA, *ubB;
+    void* etrs_half;     // ETRS: the orbitals after the first exponential
     double *vbar[4], *wbar1, *wbar2, *gfine, *rhobar_T, *rhobar, *hv, *dpart, *scal;
     // Car-Parrinello comparison step: overlap matrices A, B, Q and the solve
     // scratch in FP64, the rotations X, Y in the orbital precision, the
@@ -316,6 +321,7 @@ static Layout carve(const Geometry& g, char* base) {
     L.cp_part = c.take<double>((size_t)cp_solve_blocks(g.n_orb) * 8);
     L.cp_info = c.take<double>(2 * 8);
     L.fict_part = c.take<double>((size_t)g.nblk256 * 8);
+    if (g.etrs > 0) L.etrs_half = c.take<void>(orb);
     if (g.adjoint) {
         for (int e = 0; e < 2; ++e)
             for (int k = 0; k < g.taylor - 1; ++k) L.inter[e][k] = c.take<void>(orb);
@@ -895,7 +901,26 @@ template <typename T>
 me_status step_impl(me_system* sys, double eps, bool energy) {
     CHK(step_pre(sys, eps));
     // 3-4. AETRS: exp(-i tau H(t+dt)) exp(-i tau H(t))
-    CHK(two_exponentials<T>(sys));
+    if (sys->g.etrs == 0) {
+        CHK(two_exponentials<T>(sys));
+        return step_post(sys, energy);
+    }
+    // ETRS: the AETRS result predicts psi(t+dt); each correction rebuilds
+    // v_eff of the second exponential from its density and redoes that
+    // exponential from the half-step orbitals
+    const Geometry& g = sys->g;
+    const size_t orb = (size_t)g.n_orb * g.stride * g.bc;
+    const int next = sys->tab_cur ^ 1;
+    CHK(exponential<T>(sys, (const T*)sys->w.veff0, sys->tab_cur, false));
+    HIPCHK(hipMemcpyAsync(sys->w.etrs_half, sys->w.psi, orb, hipMemcpyDeviceToDevice, sys->stream));
+    CHK(exponential<T>(sys, (const T*)sys->w.veff1, next, true));
+    for (int k = 0; k < g.etrs; ++k) {
+        CHK(density_vhxc(sys, false, false));          // v_Hxc of the prediction into w.vh
+        HIPCHK(launch_veff<T>(sys->w.vloc_cur, sys->w.vloc_next, sys->w.vh, sys->w.vh, sys->w.vh, 1, g.nx, g.N,
+                              sys->prm.h, Lx(sys), eps, nullptr, (T*)sys->w.veff1, sys->stream));
+        HIPCHK(hipMemcpyAsync(sys->w.psi, sys->w.etrs_half, orb, hipMemcpyDeviceToDevice, sys->stream));
+        CHK(exponential<T>(sys, (const T*)sys->w.veff1, next, true));
+    }
     return step_post(sys, energy);
 }
 
@@ -2207,6 +2232,7 @@ me_status me_init_batch(const me_params* ps, int32_t n_sys, void* workspace, siz
             return ME_EINVAL;
         }
         if (ps[i].enable_adjoint) { g_init_error = "batches do not run the adjoint"; return ME_EUNSUPPORTED; }
+        if (ps[i].etrs_iterations) { g_init_error = "batches run AETRS"; return ME_EUNSUPPORTED; }
         if (ps[i].n[0] > 192) { g_init_error = "batched grids are limited to 192 points per row"; return ME_EUNSUPPORTED; }
     }
     me_batch* b = new (std::nothrow) me_batch();

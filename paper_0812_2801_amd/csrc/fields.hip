@@ -330,15 +330,20 @@ __global__ void veff_kernel(const double* __restrict__ vloc0, const double* __re
     const double a = hn[i];
     double ext = 0.0;
     if (eps != 0.0) ext = eps * (h * (double)(i % nx) - 0.5 * Lx);
-    double v0 = vloc0[i] + a;
-    double vt;
-    if (nhist >= 3) vt = (3.0 * a - 3.0 * hn1[i]) + hn2[i];
-    else if (nhist == 2) vt = 2.0 * a - hn1[i];
-    else vt = a;
-    double v1 = vloc1[i] + vt;
-    if (eps != 0.0) { v0 += ext; v1 += ext; }
-    veff0[i] = (T)v0;
-    if (veff1 != nullptr) veff1[i] = (T)v1;
+    if (veff0 != nullptr) {
+        double v0 = vloc0[i] + a;
+        if (eps != 0.0) v0 += ext;
+        veff0[i] = (T)v0;
+    }
+    if (veff1 != nullptr) {
+        double vt;
+        if (nhist >= 3) vt = (3.0 * a - 3.0 * hn1[i]) + hn2[i];
+        else if (nhist == 2) vt = 2.0 * a - hn1[i];
+        else vt = a;
+        double v1 = vloc1[i] + vt;
+        if (eps != 0.0) v1 += ext;
+        veff1[i] = (T)v1;
+    }
 }
 
 // ------------------------------------------------------------ local forces

@@ -233,6 +233,36 @@ elif scenario == "cp":
         ok(lib.me_propagate_step(h, None, None), h)
         assert lib.me_cp_step(h, None) == B.ME_ESTATE
         ok(lib.me_destroy(h))
+elif scenario == "etrs":
+    # ETRS (two corrections of the second exponential) under a field, against
+    # the oracle; batches and the adjoint refuse it
+    for c in (W.C1, W.C1.replace(name="odd", n=20, n_orb=5, n_ions=5, placement="lattice", jitter=0.2, seed=77)):
+        inp = W.make_inputs(c)
+        h = new_system(c, inp, etrs_iterations=2)
+        psi = orbitals(c, inp)
+        ok(lib.me_set_state(h, psi.ctypes.data, c.n_points), h)
+        m = Model.from_config(c)
+        st = dynamics.init_state(m, inp["psi"], inp["pos"])
+        rep = B.StepReport()
+        for n in range(3):
+            e = ctypes.c_double(0.01 * (n + 1))
+            ok(lib.me_propagate_step(h, ctypes.byref(e), ctypes.byref(rep)), h)
+            st = dynamics.etrs_step(m, st, e.value, iterations=2)
+        psi_out, f = state(h, c)
+        compare(f"etrs {c.name} 3 steps", c, psi_out, f, st)
+        ok(lib.me_destroy(h))
+    c = W.C1
+    inp = W.make_inputs(c)
+    p, keep = B.params_from_config(c, inp["pos"], precision=prec, etrs_iterations=1, enable_adjoint=True)
+    size = ctypes.c_size_t(0)
+    assert lib.me_workspace_size(ctypes.byref(p), ctypes.byref(size)) == B.ME_EUNSUPPORTED
+    p, keep = B.params_from_config(c, inp["pos"], precision=prec, etrs_iterations=9)
+    assert lib.me_workspace_size(ctypes.byref(p), ctypes.byref(size)) == B.ME_EINVAL
+    arr = (B.Params * 1)()
+    arr[0], keep = B.params_from_config(c, inp["pos"], precision=prec, etrs_iterations=1)
+    ok(lib.me_batch_workspace_size(arr, 1, ctypes.byref(size)))
+    hb = ctypes.c_void_p()
+    assert lib.me_init_batch(arr, 1, buf(size.value), size.value, stream, ctypes.byref(hb)) == B.ME_EUNSUPPORTED
 else:
     raise SystemExit(f"unknown scenario {scenario}")
 

@@ -23,7 +23,8 @@ CLANG = "/opt/rocm/llvm/bin/clang++"
 ASAN_RT = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
 
 SCENARIOS = [("system", "f64"), ("system", "f32"), ("system", "f32_bf16x3"), ("batch", "f64"),
-             ("batch", "f32"), ("adjoint", "f64"), ("adjoint", "f32"), ("cp", "f64"), ("cp", "f32")]
+             ("batch", "f32"), ("adjoint", "f64"), ("adjoint", "f32"), ("cp", "f64"), ("cp", "f32"),
+             ("etrs", "f64")]
 
 pytestmark = pytest.mark.skipif(not (os.path.exists(CLANG) and ASAN_RT), reason="needs ROCm clang++ and its ASan runtime")
 
