@@ -24,6 +24,9 @@ ab initio molecular dynamics", arXiv:0812.2801):
 * ``adjoint``   -- reverse-mode derivative of an AETRS trajectory.
 * ``cp``        -- the Car-Parrinello comparison scheme (eq. L_CP, eq. EoM_CP)
                    with RATTLE / velocity Verlet for the orbitals.
+* ``stability`` -- time-step limits of the Taylor exponential and of CP.
+* ``toy``       -- the two-band toy model (eq. L_toy) by RK4: the modified
+                   Ehrenfest, CP and gsBO motions, d_R, d_F, Delta t_max.
 
 Conventions: arrays of grid functions have axes (z, y, x) with x fastest;
 grid point (ix, iy, iz) sits at r = h*(ix, iy, iz); the inner product is the
@@ -31,4 +34,4 @@ grid quadrature h^3 sum conj(a) b.
 """
 from .grid import Grid  # noqa: F401
 from .model import Model  # noqa: F401
-from . import dynamics, potentials, kb, adjoint, cp  # noqa: F401
+from . import dynamics, potentials, kb, adjoint, cp, toy  # noqa: F401
