@@ -25,6 +25,9 @@ ab initio molecular dynamics", arXiv:0812.2801):
 * ``cp``        -- the Car-Parrinello comparison scheme (eq. L_CP, eq. EoM_CP)
                    with RATTLE / velocity Verlet for the orbitals.
 * ``stability`` -- time-step limits of the Taylor exponential and of CP.
+* ``finite``    -- the finite box (union of atom-centred spheres, zero
+                   boundary condition) with free-space Hartree and ionic
+                   potentials.
 * ``toy``       -- the two-band toy model (eq. L_toy) by RK4: the modified
                    Ehrenfest, CP and gsBO motions, d_R, d_F, Delta t_max.
 
@@ -34,4 +37,4 @@ grid quadrature h^3 sum conj(a) b.
 """
 from .grid import Grid  # noqa: F401
 from .model import Model  # noqa: F401
-from . import dynamics, potentials, kb, adjoint, cp, toy  # noqa: F401
+from . import dynamics, potentials, kb, adjoint, cp, toy, finite  # noqa: F401

@@ -66,6 +66,8 @@ class Config:
     seed: int = 812
     control_sigma: float = 0.0  # > 0: per-step control amplitudes are drawn
     coarse_n: int = 0           # > 0: coarse static-potential perturbation grid
+    finite_radius: float = 0.0  # > 0: finite box, the union of spheres of this radius around the ions
+    ring_radius: float = 2.64   # placement "ring": atoms on a circle in the xy-plane through the centre
 
     @property
     def L(self) -> float:
@@ -98,7 +100,29 @@ C5 = Config("c5_adjoint_64", n=64, h=0.25, n_ions=32, n_orb=64, mu=1.0,
             freeze_ions=True, seed=812 + 5, precision="f32",
             control_sigma=0.01, coarse_n=16)
 
-CONFIGS = {"c1": C1, "c2": C2, "c4": C4, "c5": C5}
+# Finite boxes (the union of 7.6-bohr spheres around the atoms of the
+# paper's molecular runs, at its converged spacing 0.35 bohr): a six-atom
+# ring of the benzene carbon radius, twelve orbitals; F0 is a small case
+# for the oracle (two atoms, 3.5-bohr spheres, 24^3 points).
+F3 = Config("f3_ring_finite_72", n=72, h=0.35, n_ions=6, n_orb=12, mu=4.0, dt=0.08, steps=20,
+            placement="ring", jitter=0.05, finite_radius=7.6, seed=812 + 33, precision="f32")
+F0 = Config("f0_pair_finite_24", n=24, h=0.6, n_ions=2, n_orb=4, mu=1.0, dt=0.02, steps=4,
+            placement="ring", ring_radius=0.8, jitter=0.05, finite_radius=3.5, seed=812 + 30)
+
+CONFIGS = {"c1": C1, "c2": C2, "c4": C4, "c5": C5, "f3": F3}
+
+# Two-band toy model (eq. L_toy) with the N2 constants in atomic units: bond
+# length 1.09768 A, reduced mass of 14N2, harmonic wavenumber 2358.57 cm^-1;
+# the gap G0 = 0.30 Ha and the gap coordinate's mass and force constant
+# (M_G = M_R, K_G = 20 Ha) are not given by the paper.
+_M_N2 = 0.5 * 14.003074 * AMU_IN_ME
+TOY_N2 = dict(R0=1.09768 / 0.529177210903, M_R=_M_N2, K_R=_M_N2 * (2358.57 / 219474.6313632) ** 2,
+              G0=0.30, M_G=_M_N2, K_G=20.0)
+# the sweep of Fig. 1 (c, d): four gsBO periods sampled 400 times; 256
+# log-spaced masses per scheme; RK4 substeps per sample on a 2^(1/3) ladder
+# from 512 down to 1, below a reference of 2048
+TOY_SWEEP = dict(periods=4.0, n_samples=400, n_mu=256, mu_ehrenfest=(0.02, 20.0), mu_cp=(2.0, 2000.0),
+                 ladder_steps=28, finest=2048, ratio=2 ** (1 / 3))
 
 
 def batch_configs(n_systems: int = 16, seed: int = 812 + 3,
@@ -158,6 +182,10 @@ def ion_positions(cfg: Config, rng: Optional[np.random.Generator] = None) -> np.
                 continue
             acc.append(cand)
         pos = np.array(acc)
+    elif cfg.placement == "ring":
+        ang = 2.0 * math.pi * np.arange(cfg.n_ions) / cfg.n_ions
+        pos = np.stack([cfg.ring_radius * np.cos(ang), cfg.ring_radius * np.sin(ang), np.zeros(cfg.n_ions)], axis=1)
+        pos = pos + 0.5 * L + rng.uniform(-cfg.jitter, cfg.jitter, size=pos.shape)
     elif cfg.placement == "lattice":
         side = math.ceil(cfg.n_ions ** (1.0 / 3.0) - 1e-9)
         a = L / side
@@ -178,6 +206,42 @@ def _gsq_smoothing(n: int, h: float) -> np.ndarray:
     return np.exp(-g2 * h * h)
 
 
+def box_mask(cfg: Config, pos: np.ndarray) -> np.ndarray:
+    """Finite box: 1 at grid points within cfg.finite_radius of an ion."""
+    n, h = cfg.n, cfg.h
+    ax = np.arange(n) * h
+    z, y, x = np.meshgrid(ax, ax, ax, indexing="ij")
+    m = np.zeros((n, n, n), dtype=bool)
+    for R in pos:
+        m |= (x - R[0]) ** 2 + (y - R[1]) ** 2 + (z - R[2]) ** 2 <= cfg.finite_radius ** 2
+    return m
+
+
+def _finite_orbitals(cfg: Config, rng: np.random.Generator, no: int) -> np.ndarray:
+    """Finite box: random combinations of atom-centred Gaussians times
+    (1, x, y, z) (width 1.2 bohr), zero outside the box, Loewdin-orthonormal."""
+    pos = ion_positions(cfg, rngs(cfg)[0])
+    n, h = cfg.n, cfg.h
+    if no > 4 * len(pos):
+        raise ValueError("a finite box holds at most 4 orbitals per ion here")
+    ax = np.arange(n) * h
+    z, y, x = np.meshgrid(ax, ax, ax, indexing="ij")
+    basis = []
+    for R in pos:
+        dx, dy, dz = x - R[0], y - R[1], z - R[2]
+        g = np.exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * 1.2 ** 2))
+        basis += [g, dx * g, dy * g, dz * g]
+    basis = np.stack(basis).reshape(len(basis), -1) * box_mask(cfg, pos).ravel()
+    c = rng.standard_normal((no, basis.shape[0])) + 1j * rng.standard_normal((no, basis.shape[0]))
+    flat = c @ basis
+    h3 = h ** 3
+    s = h3 * (flat.conj() @ flat.T)
+    s = 0.5 * (s + s.conj().T)
+    w, v = np.linalg.eigh(s)
+    xm = (v * (1.0 / np.sqrt(w))) @ v.conj().T
+    return (xm.T @ flat).reshape(no, n, n, n)
+
+
 def initial_orbitals(cfg: Config, rng: Optional[np.random.Generator] = None,
                      n_orb: Optional[int] = None) -> np.ndarray:
     """[n_orb, n, n, n] complex128, orthonormal under h^3 sum conj(a) b.
@@ -186,6 +250,8 @@ def initial_orbitals(cfg: Config, rng: Optional[np.random.Generator] = None,
     import scipy.fft as sfft
     if rng is None:
         rng = rngs(cfg)[1]
+    if cfg.finite_radius > 0:
+        return _finite_orbitals(cfg, rng, cfg.n_orb if n_orb is None else n_orb)
     n, h = cfg.n, cfg.h
     no = cfg.n_orb if n_orb is None else n_orb
     filt = _gsq_smoothing(n, h)
