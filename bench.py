@@ -334,6 +334,96 @@ def calibrate_copy(gib: float = 2.0, reps: int = 5):
     print(json.dumps({"copy_bytes_each": 2 * n * 4, "reps": reps}))
 
 
+def run_toy(oracle_sample: bool = True) -> dict:
+    """The Fig. 1 (c, d) sweep of the two-band toy model (eq. L_toy): every
+    (mass, RK4 step) trajectory of a scheme in one launch, timed with HIP
+    events on the launch stream; d_R, d_F and Delta t_max per mass.  With
+    oracle_sample, the oracle integrates one trajectory of the sweep (its
+    RK4 steps per second on one core)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_0812_2801_amd import toy
+    S = W.TOY_SWEEP
+    ladder = toy.substep_ladder(S["ladder_steps"], S["finest"], S["ratio"])
+
+    class Timer:
+        def start(self):
+            self.e0 = torch.cuda.Event(enable_timing=True)
+            self.e1 = torch.cuda.Event(enable_timing=True)
+            self.e0.record()
+
+        def stop(self):
+            self.e1.record()
+
+        def ms(self):
+            self.e1.synchronize()
+            return self.e0.elapsed_time(self.e1)
+
+    out = {"workload": f"{S['n_mu']} masses x {len(ladder)} RK4 steps per scheme, {S['periods']:g} gsBO periods, "
+                       f"{S['n_samples']} samples", "ladder": ladder}
+    for scheme in ("ehrenfest", "cp"):
+        mus = np.geomspace(*S["mu_" + scheme], S["n_mu"])
+        toy.sweep(scheme, mus[:2], ladder[:2], S["n_samples"], S["periods"])     # warm-up
+        tm = Timer()
+        r = toy.sweep(scheme, mus, ladder, S["n_samples"], S["periods"], timer=tm)
+        ms = tm.ms()
+        pick = slice(None, None, max(1, S["n_mu"] // 16))
+        out[scheme] = {
+            "kernel_ms": round(ms, 3), "n_traj": r["n_traj"], "rk4_steps": r["rk4_steps"],
+            "rk4_steps_per_s": r["rk4_steps"] / (ms * 1e-3),
+            "longest_trajectory_steps": S["n_samples"] * ladder[-1],
+            "mu": [round(float(x), 5) for x in r["mu"][pick]],
+            "d_R": [float(f"{x:.4g}") for x in r["d_R"][pick]],
+            "d_F": [float(f"{x:.4g}") for x in r["d_F"][pick]],
+            "dt_max": [None if not np.isfinite(x) else float(f"{x:.4g}") for x in r["dt_max"][pick]],
+        }
+    if oracle_sample:
+        from oracle import toy as T
+        P = T.ToyParams(**W.TOY_N2)
+        t_total = S["periods"] * P.period_R
+        sub = 16
+        t0 = time.perf_counter()
+        T.run(P, "ehrenfest", [1.0], sub, S["n_samples"], t_total)
+        el = time.perf_counter() - t0
+        out["cpu_oracle"] = {"rk4_steps_per_s": S["n_samples"] * sub / el, "cores": 1, "kind": "oracle",
+                             "sample": f"one Ehrenfest trajectory, {S['n_samples'] * sub} RK4 steps"}
+    return out
+
+
+def run_finite(steps: int = 50) -> dict:
+    """The finite-box workload (the 72^3 ring box): ms per MD step in FP32 and
+    FP64, beside the same grid run as a periodic cube."""
+    import torch
+    import workloads as W
+    from paper_0812_2801_amd import binding as B
+    cfg = W.F3
+    inp = W.make_inputs(cfg)
+    out = {"workload": f"{cfg.n}^3 h={cfg.h}, {cfg.n_ions}-atom ring, {cfg.n_orb} orbitals, box of "
+                       f"{cfg.finite_radius} b spheres",
+           "box_fraction": float(W.box_mask(cfg, inp["pos"]).mean()), "steps": steps}
+    psi = torch.from_numpy(inp["psi"].reshape(cfg.n_orb, -1))
+    for prec in ("f32", "f64"):
+        for kind, c in (("finite", cfg), ("periodic", cfg.replace(finite_radius=0.0))):
+            p, keep = B.params_from_config(c, inp["pos"], precision=prec)
+            s = B.System(p, keep, device="cuda:0")
+            s.set_state(psi)
+            e0 = s.report()["e_total"]
+            for _ in range(3):
+                s.step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                s.step()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            rep = s.report()
+            s.close()
+            out[f"{kind}_{prec}_ms_per_step"] = round(ms, 4)
+            out[f"{kind}_{prec}_energy_change"] = rep["e_total"] - e0
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -356,6 +446,10 @@ def main():
                     help="only the Car-Parrinello comparison (Ehrenfest timed at the same sizes)")
     ap.add_argument("--dt-scan", action="store_true",
                     help="only the largest stable time step against the grid spacing (Taylor-4, Taylor-8, CP)")
+    ap.add_argument("--finite", action="store_true",
+                    help="only the finite-box workload (union of atom-centred spheres, free-space Hartree)")
+    ap.add_argument("--toy", action="store_true",
+                    help="only the two-band toy-model sweep (d_R, d_F, Delta t_max against the mass)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -367,6 +461,12 @@ def main():
         return
     if args.batch_only:           # profiling aid: the batched workload alone
         print(json.dumps({"batched": run_batch(args.batch_steps, 8, 6, not args.no_autotune)}))
+        return
+    if args.finite:
+        print(json.dumps({"finite_box": run_finite()}))
+        return
+    if args.toy:
+        print(json.dumps({"toy_model": run_toy(not args.no_cpu)}))
         return
     if args.dt_scan:
         from paper_0812_2801_amd import scan

@@ -105,6 +105,16 @@ typedef struct {
                                 the half-step orbitals with v_Hxc of the latest density
                                 (needs one more orbital buffer; not with batches or the
                                 adjoint) */
+    double finite_radius;    /* 0: periodic cube.  > 0: finite box (sec. 5, the molecular
+                                runs): the grid points within this radius of an ion at
+                                its initial position; orbitals are zero outside (H acts as
+                                P H P), the Hartree potential is that of free space (the
+                                charge convolved with 1/|r|, cell average 2.380077/h at
+                                r = 0, by FFTs on the doubled grid), the local ionic
+                                potential and the ion-ion energy have no periodic images.
+                                The box must keep 4 grid points from every face of the
+                                cube; no external field (ctrl must be 0), no batches, no
+                                adjoint.  Needs the doubled-grid FFT buffers. */
 } me_params;
 
 /* Diagnostics of the current state.  Energies in hartree. */
@@ -339,6 +349,51 @@ me_status me_batch_timing_read(me_batch* b, int64_t* launches, double* total_ms,
  * failed me_init_batch on this thread. */
 const char* me_batch_last_error(const me_batch* b);
 me_status me_batch_destroy(me_batch* b);
+
+/* ------------------------------------------------------- two-band toy model
+ * The model of sec. 6 (eq. L_toy): electronic angles theta_1, theta_2, bond
+ * length R, gap coordinate G.  Equations of motion (Euler-Lagrange equations
+ * of eq. L_toy; the angles are first order in the modified Ehrenfest form):
+ *   mu theta_1' = (G/2) sin(theta_2 - R),  mu theta_2' = -(G/2) sin(theta_1 - R),
+ *   M_R R'' = -K_R (R - R_0) + (G/2)[sin(theta_1 - R) + sin(theta_2 - R)],
+ *   M_G G'' = -K_G (G - G_0) + (1/2)[cos(theta_1 - R) + cos(theta_2 - R)];
+ * CP instead: mu_CP theta_i'' = -(G/2) sin(theta_i - R).  Start (sec. 6): R
+ * and G 10 % above R_0 and G_0 at rest, theta_i = R(0), CP angles at rest.
+ * The gsBO reference (mu = 0, theta_i = R) is R_BO(t) = R_0 (1 + 0.1 cos(w t)),
+ * w = sqrt(K_R / M_R).  Atomic units; FP64 throughout. */
+typedef struct {
+    double R0, M_R, K_R;  /* bond: equilibrium length, mass, force constant */
+    double G0, M_G, K_G;  /* gap coordinate: the same three */
+} me_toy_params;
+
+/* Integrates n_traj independent trajectories over [0, t_total] by classical
+ * RK4, one per work-item (asynchronous on `stream`).  scheme 0: modified
+ * Ehrenfest, 1: CP.  Device arrays of n_traj: mu (mu or mu_CP, > 0),
+ * substeps (RK4 steps per sample, 1..max_substeps; dt = t_total /
+ * (n_samples * substeps)), window (samples per force average, >= 1); a
+ * trajectory whose entries break these bounds gets NaN outputs and is not
+ * run.  Outputs (device): samples (nullable) [n_samples + 1][4][n_traj]
+ * (theta_1, theta_2, R, G at t_j = j t_total / n_samples, trajectory
+ * fastest); d_R[n_traj] = 100 / (0.2 R_0) * rms_j (R(t_j) - R_BO(t_j)) over
+ * j = 1..n_samples; d_F[n_traj] = 100 / (0.2 K_R R_0) * rms over the
+ * complete windows of (force on R averaged over the window by the trapezoid
+ * rule on the run's own steps - gsBO force averaged over the window).
+ * ME_EINVAL for non-positive masses or K_R, t_total <= 0, n_samples < 1,
+ * max_substeps < 1, n_samples * max_substeps > 2^24 (the bound on the run
+ * time of one work-item), NULL outputs; n_traj = 0 does nothing. */
+me_status me_toy_run(const me_toy_params* p, int32_t scheme, int32_t n_traj, int32_t n_samples,
+                     double t_total, int32_t max_substeps, const double* mu_dev,
+                     const int32_t* substeps_dev, const int32_t* window_dev, double* samples_dev,
+                     double* d_R_dev, double* d_F_dev, void* stream);
+
+/* Distance of each trajectory from a reference (the Delta t_max criterion of
+ * sec. 6): dist[i] = max over the four coordinates c of
+ * 100 * rms_j (x_c[i](t_j) - x_c[ref[i]](t_j)) / (max_j - min_j of x_c[ref[i]]),
+ * j = 0..n_samples, over samples laid out as me_toy_run writes them.
+ * ref (device, n_traj entries in [0, n_traj); an entry outside gives NaN).
+ * ME_EINVAL for NULL arrays or n_samples < 1. */
+me_status me_toy_distance(int32_t n_traj, int32_t n_samples, const double* samples_dev,
+                          const int32_t* ref_dev, double* dist_dev, void* stream);
 
 #ifdef __cplusplus
 }

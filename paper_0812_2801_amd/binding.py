@@ -31,6 +31,7 @@ SYMBOLS = [
     "me_batch_workspace_size", "me_init_batch", "me_batch_system", "me_batch_set_tuning",
     "me_batch_get_tuning", "me_batch_autotune", "me_propagate_batch", "me_batch_timing_enable",
     "me_batch_timing_read", "me_batch_last_error", "me_batch_destroy",
+    "me_toy_run", "me_toy_distance",
 ]
 
 
@@ -43,7 +44,7 @@ class Params(ctypes.Structure):
         ("kb_energy", c_double), ("n_orb", c_int32), ("occ", c_double),
         ("mu", c_double), ("dt", c_double), ("taylor_order", c_int32),
         ("precision", c_int32), ("freeze_ions", c_int32), ("enable_adjoint", c_int32),
-        ("nl_force_form", c_int32), ("etrs_iterations", c_int32),
+        ("nl_force_form", c_int32), ("etrs_iterations", c_int32), ("finite_radius", c_double),
     ]
 
 
@@ -62,6 +63,12 @@ class BatchTuning(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ToyParams(ctypes.Structure):
+    """me_toy_params: the constants of eq. L_toy."""
+    _fields_ = [("R0", c_double), ("M_R", c_double), ("K_R", c_double),
+                ("G0", c_double), ("M_G", c_double), ("K_G", c_double)]
 
 
 class ModehrError(RuntimeError):
@@ -125,6 +132,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.me_batch_last_error.restype = c_char_p
     lib.me_batch_last_error.argtypes = [c_void_p]
     lib.me_batch_destroy.argtypes = [c_void_p]
+    lib.me_toy_run.argtypes = [POINTER(ToyParams), c_int32, c_int32, c_int32, c_double, c_int32, c_void_p, c_void_p,
+                               c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.me_toy_distance.argtypes = [c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
     for s in SYMBOLS:
         if s not in ("me_last_error", "me_strerror", "me_batch_last_error"):
             getattr(lib, s).restype = c_int32
@@ -139,7 +149,7 @@ def _dptr(a: np.ndarray):
 def make_params(*, n, h, pos, mass, zval, n_orb, mu, dt, vel=None, loc_a=0.5,
                 kb_sigma=0.4, kb_rcut=1.2, kb_energy=2.0, occ=2.0, taylor_order=4,
                 precision="f64", freeze_ions=False, enable_adjoint=False, nl_force_form=0,
-                etrs_iterations=0):
+                etrs_iterations=0, finite_radius=0.0):
     """Params plus the host arrays it points to (keep both alive)."""
     pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
     mass = np.ascontiguousarray(mass, dtype=np.float64).ravel()
@@ -166,6 +176,7 @@ def make_params(*, n, h, pos, mass, zval, n_orb, mu, dt, vel=None, loc_a=0.5,
     p.enable_adjoint = int(bool(enable_adjoint))
     p.nl_force_form = int(nl_force_form)
     p.etrs_iterations = int(etrs_iterations)
+    p.finite_radius = float(finite_radius)
     return p, keep
 
 
@@ -174,7 +185,8 @@ def params_from_config(cfg, pos, vel=None, precision=None, **over):
               zval=np.full(cfg.n_ions, cfg.zval), n_orb=cfg.n_orb, mu=cfg.mu, dt=cfg.dt,
               vel=vel, loc_a=cfg.loc_a, kb_sigma=cfg.kb_sigma, kb_rcut=cfg.kb_rcut,
               kb_energy=cfg.kb_energy, occ=cfg.occ,
-              precision=precision or cfg.precision, freeze_ions=cfg.freeze_ions)
+              precision=precision or cfg.precision, freeze_ions=cfg.freeze_ions,
+              finite_radius=getattr(cfg, "finite_radius", 0.0))
     kw.update(over)
     return make_params(**kw)
 
@@ -475,3 +487,54 @@ class Batch:
         by = c_double(0)
         self._check(self.lib.me_batch_timing_read(self.h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
         return n.value, ms.value, by.value
+
+
+# ------------------------------------------------------------- toy model
+TOY_SCHEMES = {"ehrenfest": 0, "cp": 1}
+
+
+def toy_params(R0, M_R, K_R, G0, M_G, K_G) -> ToyParams:
+    return ToyParams(R0, M_R, K_R, G0, M_G, K_G)
+
+
+def toy_run(p: ToyParams, scheme: str, mu, substeps, window, n_samples: int, t_total: float,
+            max_substeps: Optional[int] = None, samples: bool = True, device="cuda:0"):
+    """me_toy_run over len(mu) trajectories (mu, substeps, window: sequences
+    or tensors).  Returns {"d_R", "d_F", "samples" ([n_samples + 1, 4, n_traj]
+    or None)} as device tensors, ordered on torch's current stream."""
+    import torch
+    lib = load()
+    mu = torch.as_tensor(mu, dtype=torch.float64, device=device).contiguous()
+    n = mu.numel()
+    sub = torch.as_tensor(substeps, dtype=torch.int32, device=device).reshape(-1).expand(n).contiguous()
+    win = torch.as_tensor(window, dtype=torch.int32, device=device).reshape(-1).expand(n).contiguous()
+    if max_substeps is None:
+        max_substeps = int(sub.max().item()) if n else 1
+    d_R = torch.empty(n, dtype=torch.float64, device=device)
+    d_F = torch.empty(n, dtype=torch.float64, device=device)
+    S = torch.empty((n_samples + 1, 4, n), dtype=torch.float64, device=device) if samples else None
+    stream = torch.cuda.current_stream(mu.device).cuda_stream
+    st = lib.me_toy_run(ctypes.byref(p), c_int32(TOY_SCHEMES[scheme]), c_int32(n), c_int32(n_samples),
+                        c_double(t_total), c_int32(max_substeps), c_void_p(mu.data_ptr()), c_void_p(sub.data_ptr()),
+                        c_void_p(win.data_ptr()), c_void_p(S.data_ptr()) if S is not None else None,
+                        c_void_p(d_R.data_ptr()), c_void_p(d_F.data_ptr()), c_void_p(stream))
+    if st != ME_OK:
+        raise ModehrError(st, lib.me_last_error(None).decode())
+    return {"d_R": d_R, "d_F": d_F, "samples": S}
+
+
+def toy_distance(samples, ref):
+    """me_toy_distance: samples [n_samples + 1, 4, n_traj] (device), ref the
+    reference trajectory of each; returns the distances (device tensor)."""
+    import torch
+    lib = load()
+    n_samples = samples.shape[0] - 1
+    n = samples.shape[2]
+    ref = torch.as_tensor(ref, dtype=torch.int32, device=samples.device).reshape(-1).expand(n).contiguous()
+    dist = torch.empty(n, dtype=torch.float64, device=samples.device)
+    stream = torch.cuda.current_stream(samples.device).cuda_stream
+    st = lib.me_toy_distance(c_int32(n), c_int32(n_samples), c_void_p(samples.data_ptr()),
+                             c_void_p(ref.data_ptr()), c_void_p(dist.data_ptr()), c_void_p(stream))
+    if st != ME_OK:
+        raise ModehrError(st, lib.me_last_error(None).decode())
+    return dist

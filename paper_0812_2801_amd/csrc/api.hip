@@ -21,6 +21,8 @@
 #include "fields.hpp"
 #include "adjoint.hpp"
 #include "cp.hpp"
+#include "toy.hpp"
+#include "finite.hpp"
 
 using namespace me;
 
@@ -93,6 +95,9 @@ struct Geometry {
     int floc_chunks;
     int64_t nblk256;  // 256-point blocks of the grid
     size_t fft_work;
+    bool finite;          // union-of-spheres box, free-space potentials
+    int64_t npad, nhalf2; // doubled grid: points, complex half-spectrum
+    size_t fft_work2;
     int ewald_ng;
     bool adjoint;
     int taylor;
@@ -171,6 +176,20 @@ me_status validate(const me_params* p, std::string& err) {
     if (p->nl_force_form != 0 && p->nl_force_form != 1) { err = "nl_force_form must be 0 or 1"; return ME_EINVAL; }
     if (p->etrs_iterations < 0 || p->etrs_iterations > 8) { err = "etrs_iterations must be in [0, 8]"; return ME_EINVAL; }
     if (p->etrs_iterations > 0 && p->enable_adjoint) { err = "the adjoint is defined for AETRS"; return ME_EUNSUPPORTED; }
+    if (!(p->finite_radius >= 0.0) || !std::isfinite(p->finite_radius)) { err = "finite_radius must be >= 0"; return ME_EINVAL; }
+    if (p->finite_radius > 0.0) {
+        if (p->enable_adjoint) { err = "the adjoint runs on the periodic cube"; return ME_EUNSUPPORTED; }
+        if (p->n_ions < 1) { err = "a finite box needs ions"; return ME_EINVAL; }
+        if (!(p->kb_rcut < p->finite_radius)) { err = "the projector spheres must fit in the box: kb_rcut < finite_radius"; return ME_EINVAL; }
+        for (int J = 0; J < p->n_ions; ++J)
+            for (int c = 0; c < 3; ++c) {
+                const double lo = p->pos[3 * J + c] - p->finite_radius, hi = p->pos[3 * J + c] + p->finite_radius;
+                if (lo < 4.0 * p->h || hi > (p->n[c] - 5) * p->h) {
+                    err = "the finite box must keep 4 grid points from every face of the cube";
+                    return ME_EINVAL;
+                }
+            }
+    }
     const bool f64 = p->precision == ME_F64;
     const int px = choose_px(p->n[0], f64);
     if (choose_ty(p->n[0], p->n[1], px, f64 ? 16 : 8) < 0) { err = "grid x extent too large for one workgroup row"; return ME_EUNSUPPORTED; }
@@ -209,6 +228,10 @@ Geometry make_geometry(const me_params* p) {
     g.adjoint = p->enable_adjoint != 0;
     g.etrs = p->etrs_iterations;
     g.taylor = p->taylor_order;
+    g.finite = p->finite_radius > 0.0;
+    g.npad = g.finite ? 8 * g.N : 0;
+    g.nhalf2 = g.finite ? (int64_t)(g.nx + 1) * (2 * g.ny) * (2 * g.nz) : 0;
+    g.fft_work2 = g.finite ? (size_t)(2 * g.nhalf2) * 16 : 0;
     return g;
 }
 
@@ -223,6 +246,10 @@ struct Layout {
     double *vloc_cur, *vloc_next, *vstatic, *hist[3], *rho, *vh;
     double2 *rhok, *spec, *phase, *phaseT, *ewald_sg;
     void* fft_work;
+    uint8_t* mask;              // finite box: 1 inside
+    double *rpad_in, *rpad_out, *gk;
+    double2* cpad;
+    void* fft_work2;
     double *pos, *pos_next, *vel, *frc, *mass, *zval;
     int32_t* tidx[2];
     void* tp[2];
@@ -269,6 +296,14 @@ static Layout carve(const Geometry& g, char* base) {
     L.phase = c.take<double2>((size_t)std::max(1, g.n_ions) * (g.nx + g.ny + g.nz) * 16);
     L.phaseT = c.take<double2>((size_t)std::max(1, g.n_ions) * (g.nx + g.ny + g.nz) * 16);
     L.fft_work = c.take<void>(g.fft_work);
+    if (g.finite) {
+        L.mask = c.take<uint8_t>(g.N);
+        L.rpad_in = c.take<double>(g.npad * 8);
+        L.rpad_out = c.take<double>(g.npad * 8);
+        L.cpad = c.take<double2>(g.nhalf2 * 16);
+        L.gk = c.take<double>(g.nhalf2 * 8);
+        L.fft_work2 = c.take<void>(g.fft_work2);
+    }
     const size_t ion3 = (size_t)std::max(1, g.n_ions) * 3 * 8;
     L.pos = c.take<double>(ion3);
     L.pos_next = c.take<double>(ion3);
@@ -356,6 +391,8 @@ struct me_system {
     EwaldPlan ewp{};
     rocfft_plan r2c = nullptr, c2r = nullptr;
     rocfft_execution_info info = nullptr;
+    rocfft_plan r2c2 = nullptr, c2r2 = nullptr;      // doubled grid (finite box)
+    rocfft_execution_info info2 = nullptr;
     int tab_cur = 0;
     int hist_count = 0, hist_newest = 0;
     int norm_tiles = 0;          // tiles per orbital of the last norm partials
@@ -441,10 +478,33 @@ me_status fft_c2r(me_system* sys, double2* in, double* out) {
     return ME_OK;
 }
 
+// free-space Hartree potential of w.rho into w.vh: the charge on the
+// corner block of the doubled grid (zero elsewhere), times the spectrum of
+// the Coulomb kernel, back, and the corner block taken
+me_status hartree_free(me_system* sys) {
+    const Geometry& g = sys->g;
+    HIPCHK(launch_pad(sys->w.rho, g.nx, g.ny, g.nz, sys->w.rpad_in, sys->stream));
+    void* i1[1] = {sys->w.rpad_in};
+    void* o1[1] = {sys->w.cpad};
+    FFTCHK(rocfft_execute(sys->r2c2, i1, o1, sys->info2));
+    HIPCHK(launch_green_multiply(sys->w.cpad, sys->w.gk, g.nhalf2, sys->stream));
+    void* i2[1] = {sys->w.cpad};
+    void* o2[1] = {sys->w.rpad_out};
+    FFTCHK(rocfft_execute(sys->c2r2, i2, o2, sys->info2));
+    HIPCHK(launch_unpad(sys->w.rpad_out, g.nx, g.ny, g.nz, sys->w.vh, sys->stream));
+    return ME_OK;
+}
+
 // V_loc at positions `pos` (device) into `out` (+ the static potential).
-// Leaves the phase tables of `pos` in w.phase.
+// Leaves the phase tables of `pos` in w.phase (periodic cube).
 me_status ion_fields(me_system* sys, const double* pos, double* out) {
     const Geometry& g = sys->g;
+    if (g.finite) {
+        HIPCHK(launch_vloc_free(pos, sys->w.zval, g.n_ions, g.nx, g.ny, g.nz, sys->prm.h, sys->prm.loc_a, out,
+                                sys->stream));
+        if (sys->static_set) HIPCHK(launch_add(out, sys->w.vstatic, g.N, sys->stream));
+        return ME_OK;
+    }
     const double L[3] = {g.nx * sys->prm.h, g.ny * sys->prm.h, g.nz * sys->prm.h};
     HIPCHK(launch_phases(pos, g.n_ions, g.nx, g.ny, g.nz, L, sys->w.phase, sys->w.phaseT, sys->stream));
     HIPCHK(launch_vloc_spectrum(sys->w.phase, sys->w.phaseT, sys->w.zval, g.n_ions, g.nx, g.ny, g.nz, L,
@@ -472,9 +532,13 @@ me_status density_vhxc(me_system* sys, bool energy, bool push = true) {
         HIPCHK(launch_density<double>((const double2*)sys->w.psi, g.stride, g.n_orb, g.N, sys->prm.occ, sys->w.rho, sys->stream));
     else
         HIPCHK(launch_density<float>((const float2*)sys->w.psi, g.stride, g.n_orb, g.N, sys->prm.occ, sys->w.rho, sys->stream));
-    CHK(fft_r2c(sys, sys->w.rho, sys->w.rhok));
-    HIPCHK(launch_hartree_spectrum(sys->w.rhok, g.nx, g.ny, g.nz, L, sys->w.spec, sys->stream));
-    CHK(fft_c2r(sys, sys->w.spec, sys->w.vh));
+    if (g.finite) {
+        CHK(hartree_free(sys));
+    } else {
+        CHK(fft_r2c(sys, sys->w.rho, sys->w.rhok));
+        HIPCHK(launch_hartree_spectrum(sys->w.rhok, g.nx, g.ny, g.nz, L, sys->w.spec, sys->stream));
+        CHK(fft_c2r(sys, sys->w.spec, sys->w.vh));
+    }
     if (!push) {
         HIPCHK(launch_vhxc(sys->w.rho, sys->w.vh, g.N, sys->w.vh, energy ? sys->w.hxc_part : nullptr,
                            sys->stream));
@@ -493,8 +557,12 @@ me_status density_vhxc(me_system* sys, bool energy, bool push = true) {
 me_status forces_parts(me_system* sys, const double* pos, int t) {
     const Geometry& g = sys->g;
     const double L[3] = {g.nx * sys->prm.h, g.ny * sys->prm.h, g.nz * sys->prm.h};
-    HIPCHK(launch_local_forces(sys->w.rhok, sys->w.phaseT, sys->w.zval, g.n_ions, g.nx, g.ny, g.nz, L,
-                               sys->prm.h, sys->prm.loc_a, sys->w.floc_part, sys->w.floc, sys->stream));
+    if (g.finite)
+        HIPCHK(launch_local_forces_free(sys->w.rho, pos, sys->w.zval, g.n_ions, g.nx, g.ny, g.nz, sys->prm.h,
+                                        sys->prm.loc_a, sys->w.floc_part, sys->w.floc, sys->stream));
+    else
+        HIPCHK(launch_local_forces(sys->w.rhok, sys->w.phaseT, sys->w.zval, g.n_ions, g.nx, g.ny, g.nz, L,
+                                   sys->prm.h, sys->prm.loc_a, sys->w.floc_part, sys->w.floc, sys->stream));
     if (g.f64)
         HIPCHK(launch_kb_forces<double>((const double2*)sys->w.psi, g.stride, g.n_orb, g.n_ions, tables(sys, t), pos,
                                         sys->geo, g.nx, g.ny, g.nz, sys->prm.nl_force_form, sys->prm.occ, sys->prm.kb_energy, sys->w.fnl,
@@ -503,8 +571,11 @@ me_status forces_parts(me_system* sys, const double* pos, int t) {
         HIPCHK(launch_kb_forces<float>((const float2*)sys->w.psi, g.stride, g.n_orb, g.n_ions, tables(sys, t), pos,
                                        sys->geo, g.nx, g.ny, g.nz, sys->prm.nl_force_form, sys->prm.occ, sys->prm.kb_energy, sys->w.fnl,
                                        sys->w.enl_part, sys->w.kbf_part, sys->stream));
-    HIPCHK(launch_ewald(sys->ewp, pos, sys->w.zval, g.n_ions, sys->w.ewald_sg, sys->w.erec_part, sys->w.fion,
-                        sys->w.eion_part, sys->w.ewald_part, sys->stream));
+    if (g.finite)
+        HIPCHK(launch_ion_coulomb(pos, sys->w.zval, g.n_ions, sys->w.fion, sys->w.eion_part, sys->stream));
+    else
+        HIPCHK(launch_ewald(sys->ewp, pos, sys->w.zval, g.n_ions, sys->w.ewald_sg, sys->w.erec_part, sys->w.fion,
+                            sys->w.eion_part, sys->w.ewald_part, sys->stream));
     return ME_OK;
 }
 
@@ -617,11 +688,13 @@ me_status make_veff(me_system* sys, double eps, bool both) {
     if (g.f64)
         HIPCHK(launch_veff<double>(sys->w.vloc_cur, sys->w.vloc_next, hn, hn1, hn2, sys->hist_count, g.nx, g.N,
                                    sys->prm.h, Lx(sys), eps, (double*)sys->w.veff0,
-                                   both ? (double*)sys->w.veff1 : nullptr, sys->stream));
+                                   both ? (double*)sys->w.veff1 : nullptr, g.finite ? sys->w.mask : nullptr,
+                                   sys->stream));
     else
         HIPCHK(launch_veff<float>(sys->w.vloc_cur, sys->w.vloc_next, hn, hn1, hn2, sys->hist_count, g.nx, g.N,
                                   sys->prm.h, Lx(sys), eps, (float*)sys->w.veff0,
-                                  both ? (float*)sys->w.veff1 : nullptr, sys->stream));
+                                  both ? (float*)sys->w.veff1 : nullptr, g.finite ? sys->w.mask : nullptr,
+                                  sys->stream));
     return ME_OK;
 }
 
@@ -670,9 +743,9 @@ me_status finalize(me_system* sys, bool with_norm, bool energy, const double* fi
     f.enl_part = sys->w.enl_part;
     f.eion_part = sys->w.eion_part;
     f.erec_part = sys->w.erec_part;
-    f.erec_n = (g.n_ions > 0 && sys->ewp.ng > 0) ? ewald_sg_blocks(sys->ewp.ng) : 0;   // unwritten without ions
+    f.erec_n = (g.n_ions > 0 && sys->ewp.ng > 0 && !g.finite) ? ewald_sg_blocks(sys->ewp.ng) : 0;   // unwritten without ions
     f.ewald_rec_scale = 2.0 * M_PI / (sys->ew.L * sys->ew.L * sys->ew.L);
-    f.ewald_const = sys->ew.e_const;
+    f.ewald_const = g.finite ? 0.0 : sys->ew.e_const;
     f.vel = sys->w.vel;
     f.frc = sys->w.frc;
     f.mass = sys->w.mass;
@@ -917,7 +990,8 @@ me_status step_impl(me_system* sys, double eps, bool energy) {
     for (int k = 0; k < g.etrs; ++k) {
         CHK(density_vhxc(sys, false, false));          // v_Hxc of the prediction into w.vh
         HIPCHK(launch_veff<T>(sys->w.vloc_cur, sys->w.vloc_next, sys->w.vh, sys->w.vh, sys->w.vh, 1, g.nx, g.N,
-                              sys->prm.h, Lx(sys), eps, nullptr, (T*)sys->w.veff1, sys->stream));
+                              sys->prm.h, Lx(sys), eps, nullptr, (T*)sys->w.veff1,
+                              g.finite ? sys->w.mask : nullptr, sys->stream));
         HIPCHK(hipMemcpyAsync(sys->w.psi, sys->w.etrs_half, orb, hipMemcpyDeviceToDevice, sys->stream));
         CHK(exponential<T>(sys, (const T*)sys->w.veff1, next, true));
     }
@@ -1737,6 +1811,9 @@ me_status me_init_system(const me_params* p, void* workspace, size_t ws_bytes, v
             if (sys->info) rocfft_execution_info_destroy(sys->info);
             if (sys->r2c) rocfft_plan_destroy(sys->r2c);
             if (sys->c2r) rocfft_plan_destroy(sys->c2r);
+            if (sys->info2) rocfft_execution_info_destroy(sys->info2);
+            if (sys->r2c2) rocfft_plan_destroy(sys->r2c2);
+            if (sys->c2r2) rocfft_plan_destroy(sys->c2r2);
             delete sys;
             return s2;
         };
@@ -1786,6 +1863,47 @@ me_status me_init_system(const me_params* p, void* workspace, size_t ws_bytes, v
             sys->err = "rocfft execution info failed";
             return fail(ME_EDEVICE);
         }
+        if (sys->g.finite) {
+            // doubled-grid plans, the box mask at the initial positions and
+            // the spectrum of the Coulomb kernel (h^3 / (8N) folds in the
+            // inverse transform's normalisation and the quadrature weight)
+            const Geometry& g = sys->g;
+            size_t len2[3] = {(size_t)(2 * g.nx), (size_t)(2 * g.ny), (size_t)(2 * g.nz)};
+            if (rocfft_plan_create(&sys->r2c2, rocfft_placement_notinplace, rocfft_transform_type_real_forward,
+                                   rocfft_precision_double, 3, len2, 1, nullptr) != rocfft_status_success ||
+                rocfft_plan_create(&sys->c2r2, rocfft_placement_notinplace, rocfft_transform_type_real_inverse,
+                                   rocfft_precision_double, 3, len2, 1, nullptr) != rocfft_status_success) {
+                sys->err = "rocfft_plan_create failed (doubled grid)";
+                return fail(ME_EDEVICE);
+            }
+            size_t v1 = 0, v2 = 0;
+            rocfft_plan_get_work_buffer_size(sys->r2c2, &v1);
+            rocfft_plan_get_work_buffer_size(sys->c2r2, &v2);
+            if (std::max(v1, v2) > g.fft_work2) {
+                sys->err = "rocFFT work buffer (doubled grid) larger than reserved";
+                return fail(ME_EUNSUPPORTED);
+            }
+            if (rocfft_execution_info_create(&sys->info2) != rocfft_status_success ||
+                rocfft_execution_info_set_stream(sys->info2, sys->stream) != rocfft_status_success ||
+                (std::max(v1, v2) > 0 &&
+                 rocfft_execution_info_set_work_buffer(sys->info2, sys->w.fft_work2, g.fft_work2) !=
+                     rocfft_status_success)) {
+                sys->err = "rocfft execution info failed (doubled grid)";
+                return fail(ME_EDEVICE);
+            }
+            INITCHK(launch_box_mask(sys->w.pos, g.n_ions, g.nx, g.ny, g.nz, p->h, p->finite_radius, sys->w.mask,
+                                    sys->stream));
+            INITCHK(hipMemsetAsync(sys->w.rpad_in, 0, g.npad * 8, sys->stream));
+            INITCHK(launch_green_doubled(g.nx, g.ny, g.nz, p->h, sys->w.rpad_out, sys->stream));
+            void* gi[1] = {sys->w.rpad_out};
+            void* go[1] = {sys->w.cpad};
+            if (rocfft_execute(sys->r2c2, gi, go, sys->info2) != rocfft_status_success) {
+                sys->err = "rocfft_execute failed (Coulomb kernel)";
+                return fail(ME_EDEVICE);
+            }
+            INITCHK(launch_green_spectrum(sys->w.cpad, g.nhalf2, p->h * p->h * p->h / (double)g.npad, sys->w.gk,
+                                          sys->stream));
+        }
 #undef INITCHK
         *out = sys;
         return ME_OK;
@@ -1803,6 +1921,9 @@ me_status me_destroy(me_system* sys) {
     if (sys->info) rocfft_execution_info_destroy(sys->info);
     if (sys->r2c) rocfft_plan_destroy(sys->r2c);
     if (sys->c2r) rocfft_plan_destroy(sys->c2r);
+    if (sys->info2) rocfft_execution_info_destroy(sys->info2);
+    if (sys->r2c2) rocfft_plan_destroy(sys->r2c2);
+    if (sys->c2r2) rocfft_plan_destroy(sys->c2r2);
     for (auto& e : sys->ev) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
     for (auto& e : sys->ev_pool) hipEventDestroy(e);
     delete sys;
@@ -1824,6 +1945,12 @@ me_status me_set_state(me_system* sys, const void* psi_dev, int64_t orb_stride) 
         const Geometry& g = sys->g;
         HIPCHK(hipMemcpy2DAsync(sys->w.psi, g.stride * g.bc, psi_dev, orb_stride * g.bc, g.N * g.bc, g.n_orb,
                                 hipMemcpyDeviceToDevice, sys->stream));
+        if (g.finite) {     // the orbitals live on the box: values outside are dropped
+            if (g.f64)
+                HIPCHK(launch_mask_orbitals<double>((double2*)sys->w.psi, g.stride, g.n_orb, g.N, sys->w.mask, sys->stream));
+            else
+                HIPCHK(launch_mask_orbitals<float>((float2*)sys->w.psi, g.stride, g.n_orb, g.N, sys->w.mask, sys->stream));
+        }
         const size_t n3 = 3 * (size_t)g.n_ions * sizeof(double);
         if (g.n_ions > 0) {
             HIPCHK(hipMemcpyAsync(sys->w.pos, sys->pos0.data(), n3, hipMemcpyHostToDevice, sys->stream));
@@ -1906,6 +2033,7 @@ me_status me_propagate_step(me_system* sys, const double* ctrl, me_step_report* 
     if (!sys->has_state) { sys->err = "no state: call me_set_state first"; return ME_ESTATE; }
     const double eps = ctrl ? *ctrl : 0.0;
     if (!std::isfinite(eps)) { sys->err = "control amplitude must be finite"; return ME_EINVAL; }
+    if (eps != 0.0 && sys->g.finite) { sys->err = "the finite box runs without an external field"; return ME_EUNSUPPORTED; }
     try {
         me_status st = sys->g.f64 ? step_impl<double>(sys, eps, rep != nullptr)
                                   : step_impl<float>(sys, eps, rep != nullptr);
@@ -2233,6 +2361,7 @@ me_status me_init_batch(const me_params* ps, int32_t n_sys, void* workspace, siz
         }
         if (ps[i].enable_adjoint) { g_init_error = "batches do not run the adjoint"; return ME_EUNSUPPORTED; }
         if (ps[i].etrs_iterations) { g_init_error = "batches run AETRS"; return ME_EUNSUPPORTED; }
+        if (ps[i].finite_radius > 0.0) { g_init_error = "batches run periodic cubes"; return ME_EUNSUPPORTED; }
         if (ps[i].n[0] > 192) { g_init_error = "batched grids are limited to 192 points per row"; return ME_EUNSUPPORTED; }
     }
     me_batch* b = new (std::nothrow) me_batch();
@@ -2410,6 +2539,48 @@ me_status me_batch_destroy(me_batch* b) {
     hipStreamSynchronize(b->stream);
     for (hipStream_t w : b->workers) hipStreamSynchronize(w);
     batch_release(b);
+    return ME_OK;
+}
+
+// ============================================================ toy model
+// The two-band model of sec. 6 (eq. L_toy); kernels in toy.hip.
+
+me_status me_toy_run(const me_toy_params* p, int32_t scheme, int32_t n_traj, int32_t n_samples, double t_total,
+                     int32_t max_substeps, const double* mu, const int32_t* substeps, const int32_t* window,
+                     double* samples, double* d_R, double* d_F, void* stream) {
+    if (!p) { g_init_error = "p is NULL"; return ME_EINVAL; }
+    auto pos_fin = [](double x) { return x > 0.0 && std::isfinite(x); };
+    if (!pos_fin(p->M_R) || !pos_fin(p->M_G) || !pos_fin(p->K_R) || !std::isfinite(p->K_G) ||
+        !std::isfinite(p->R0) || !std::isfinite(p->G0)) {
+        g_init_error = "toy parameters: masses and K_R must be positive, all finite";
+        return ME_EINVAL;
+    }
+    if (scheme != 0 && scheme != 1) { g_init_error = "scheme must be 0 (Ehrenfest) or 1 (CP)"; return ME_EINVAL; }
+    if (!pos_fin(t_total)) { g_init_error = "t_total must be positive"; return ME_EINVAL; }
+    if (n_traj < 0 || n_samples < 1 || max_substeps < 1) {
+        g_init_error = "need n_traj >= 0, n_samples >= 1, max_substeps >= 1";
+        return ME_EINVAL;
+    }
+    if ((int64_t)n_samples * max_substeps > (int64_t(1) << 24)) {
+        g_init_error = "n_samples * max_substeps exceeds 2^24 steps per trajectory";
+        return ME_EINVAL;
+    }
+    if (n_traj == 0) return ME_OK;
+    if (!mu || !substeps || !window || !d_R || !d_F) { g_init_error = "NULL device array"; return ME_EINVAL; }
+    ToyArgs a{p->R0, p->M_R, p->K_R, p->G0, p->M_G, p->K_G, t_total, n_traj, n_samples, max_substeps,
+              mu, substeps, window, samples, d_R, d_F};
+    const hipError_t e = launch_toy(a, scheme == 1, (hipStream_t)stream);
+    if (e != hipSuccess) { g_init_error = hipGetErrorString(e); return ME_EDEVICE; }
+    return ME_OK;
+}
+
+me_status me_toy_distance(int32_t n_traj, int32_t n_samples, const double* samples, const int32_t* ref,
+                          double* dist, void* stream) {
+    if (n_traj < 0 || n_samples < 1) { g_init_error = "need n_traj >= 0, n_samples >= 1"; return ME_EINVAL; }
+    if (n_traj == 0) return ME_OK;
+    if (!samples || !ref || !dist) { g_init_error = "NULL device array"; return ME_EINVAL; }
+    const hipError_t e = launch_toy_distance(n_traj, n_samples, samples, ref, dist, (hipStream_t)stream);
+    if (e != hipSuccess) { g_init_error = hipGetErrorString(e); return ME_EDEVICE; }
     return ME_OK;
 }
 

@@ -324,9 +324,15 @@ __global__ void veff_kernel(const double* __restrict__ vloc0, const double* __re
                             const double* __restrict__ hn, const double* __restrict__ hn1,
                             const double* __restrict__ hn2, int nhist, int nx, int64_t N,
                             double h, double Lx, double eps, T* __restrict__ veff0,
-                            T* __restrict__ veff1) {
+                            T* __restrict__ veff1, const uint8_t* __restrict__ mask) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
+    if (mask != nullptr && mask[i] == 0) {
+        // outside the finite box: +inf tells the stencil to leave H psi zero
+        if (veff0 != nullptr) veff0[i] = (T)INFINITY;
+        if (veff1 != nullptr) veff1[i] = (T)INFINITY;
+        return;
+    }
     const double a = hn[i];
     double ext = 0.0;
     if (eps != 0.0) ext = eps * (h * (double)(i % nx) - 0.5 * Lx);
@@ -777,13 +783,13 @@ hipError_t launch_vhxc(const double* rho, const double* vh, int64_t N, double* v
 template <typename T>
 hipError_t launch_veff(const double* vloc0, const double* vloc1, const double* hn, const double* hn1,
                        const double* hn2, int nhist, int nx, int64_t N, double h, double Lx,
-                       double eps, T* veff0, T* veff1, hipStream_t s) {
+                       double eps, T* veff0, T* veff1, const uint8_t* mask, hipStream_t s) {
     veff_kernel<T><<<nb(N), 256, 0, s>>>(vloc0, vloc1, hn, hn1, hn2, nhist, nx, N, h, Lx, eps,
-                                         veff0, veff1);
+                                         veff0, veff1, mask);
     return hipGetLastError();
 }
-template hipError_t launch_veff<double>(const double*, const double*, const double*, const double*, const double*, int, int, int64_t, double, double, double, double*, double*, hipStream_t);
-template hipError_t launch_veff<float>(const double*, const double*, const double*, const double*, const double*, int, int, int64_t, double, double, double, float*, float*, hipStream_t);
+template hipError_t launch_veff<double>(const double*, const double*, const double*, const double*, const double*, int, int, int64_t, double, double, double, double*, double*, const uint8_t*, hipStream_t);
+template hipError_t launch_veff<float>(const double*, const double*, const double*, const double*, const double*, int, int, int64_t, double, double, double, float*, float*, const uint8_t*, hipStream_t);
 
 int local_force_chunks(int64_t N) {
     (void)N;

@@ -65,7 +65,7 @@ hipError_t launch_vhxc(const double* rho, const double* vh, int64_t N, double* v
 template <typename T>
 hipError_t launch_veff(const double* vloc0, const double* vloc1, const double* hn, const double* hn1,
                        const double* hn2, int nhist, int nx, int64_t N, double h, double Lx,
-                       double eps, T* veff0, T* veff1, hipStream_t s);
+                       double eps, T* veff0, T* veff1, const uint8_t* mask, hipStream_t s);
 int local_force_chunks(int64_t N);
 // part: [n_ions][local_force_chunks][3] scratch; floc: [n_ions][3]
 hipError_t launch_local_forces(const double2* rhok, const double2* phT, const double* zval,

@@ -271,8 +271,10 @@ __device__ __forceinline__ double zmarch(const cx_t<T>* __restrict__ u, const cx
                     acc += (double)ctr.x * (double)tre + (double)ctr.y * (double)tim;
                 } else {
                     const T vv = vq[0][p];
-                    const T hre = tre + vv * ctr.x;
-                    const T him = tim + vv * ctr.y;
+                    // v_eff = +inf marks points outside a finite box, where H psi is zero
+                    const bool inb = vv < (T)INFINITY;
+                    const T hre = inb ? tre + vv * ctr.x : (T)0;
+                    const T him = inb ? tim + vv * ctr.y : (T)0;
                     if constexpr (MODE == MODE_APPLY) {
                         res[p] = C{hre, him};
                     } else if constexpr (MODE == MODE_SCALED) {

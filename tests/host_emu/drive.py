@@ -11,7 +11,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 import workloads as W                                      # noqa: E402
-from oracle import Model, adjoint, cp, dynamics            # noqa: E402
+from oracle import Model, adjoint, cp, dynamics, finite, toy  # noqa: E402
 from paper_0812_2801_amd import binding as B               # noqa: E402
 
 lib = B.load(sys.argv[1])
@@ -263,6 +263,76 @@ elif scenario == "etrs":
     ok(lib.me_batch_workspace_size(arr, 1, ctypes.byref(size)))
     hb = ctypes.c_void_p()
     assert lib.me_init_batch(arr, 1, buf(size.value), size.value, stream, ctypes.byref(hb)) == B.ME_EUNSUPPORTED
+elif scenario == "finite":
+    # the finite box: masked H, free-space Hartree by the doubled-grid FFTs,
+    # isolated ions; three steps against the oracle's plain sums
+    c = W.F0
+    inp = W.make_inputs(c)
+    m = finite.FiniteModel.from_config(c, pos0=inp["pos"], radius=c.finite_radius)
+    st = dynamics.init_state(m, inp["psi"], inp["pos"])
+    h = new_system(c, inp)
+    psi = orbitals(c, inp)
+    ok(lib.me_set_state(h, psi.ctypes.data, c.n_points), h)
+    vh = np.zeros(c.n_points)
+    ok(lib.me_get_potential(h, 1, vh.ctypes.data), h)
+    dv = np.abs(vh.reshape(m.grid.shape) - st.hist[-1]).max()
+    print(f"finite: max|d v_Hxc| {dv:.2e}", flush=True)
+    assert dv <= (1e-11 if prec == "f64" else 2e-6) * np.abs(st.hist[-1]).max()   # FP32: the orbitals are rounded on input
+    rep = B.StepReport()
+    for _ in range(3):
+        ok(lib.me_propagate_step(h, None, ctypes.byref(rep)), h)
+        st = dynamics.aetrs_step(m, st)
+    psi_out, f = state(h, c)
+    compare("finite 3 steps", c, psi_out, f, st)
+    out = ~m.mask.astype(bool).ravel()
+    assert np.abs(psi_out[:, out]).max() == 0.0
+    e = dynamics.total_energy(m, st)
+    de = abs(rep.e_total - e["total"])
+    print(f"finite: |dE_total| {de:.2e} (E {e['total']:.6f})", flush=True)
+    assert de < (1e-9 if prec == "f64" else 1e-4) * max(1.0, abs(e["total"]))
+    e1 = ctypes.c_double(0.01)
+    assert lib.me_propagate_step(h, ctypes.byref(e1), None) == B.ME_EUNSUPPORTED
+    ok(lib.me_destroy(h))
+    p, keep = B.params_from_config(c, inp["pos"], precision=prec, finite_radius=6.0)
+    size = ctypes.c_size_t(0)
+    assert lib.me_workspace_size(ctypes.byref(p), ctypes.byref(size)) == B.ME_EINVAL     # box touches the faces
+elif scenario == "toy":
+    # the toy-model sweep against the oracle: both schemes, uneven substeps
+    # and windows, a trajectory with an invalid entry (NaN outputs), and the
+    # distance kernel
+    P = toy.ToyParams()
+    tp = B.ToyParams(P.R0, P.M_R, P.K_R, P.G0, P.M_G, P.K_G)
+    T, ns = 0.6 * P.period_R, 30
+    dp = lambda a: ctypes.c_void_p(a.ctypes.data)
+    for scheme, mus in (("ehrenfest", [1.5, 0.4, 0.1]), ("cp", [300.0, 60.0, 15.0])):
+        mu = np.array(mus + [mus[0], -1.0])
+        sub = np.array([3, 4, 20, 24, 3], np.int32)    # omega dt < 1 everywhere
+        win = np.array([2, 1, 3, 5, 2], np.int32)
+        n = mu.size
+        S = np.zeros((ns + 1, 4, n))
+        dR, dF = np.zeros(n), np.zeros(n)
+        ok(lib.me_toy_run(ctypes.byref(tp), B.TOY_SCHEMES[scheme], n, ns, T, 24, dp(mu), dp(sub), dp(win), dp(S),
+                          dp(dR), dp(dF), stream))
+        for i in range(n - 1):
+            r = toy.run(P, scheme, [mu[i]], int(sub[i]), ns, T, window=[int(win[i])])
+            ds = np.abs(S[:, :, i] - r["samples"][0]).max()
+            print(f"toy {scheme} mu={mu[i]} sub={sub[i]}: max|d samples| {ds:.2e} d_R {dR[i]:.6f} "
+                  f"({r['d_R'][0]:.6f}) d_F {dF[i]:.6f} ({r['d_F'][0]:.6f})", flush=True)
+            assert ds < 1e-12
+            assert abs(dR[i] - r["d_R"][0]) < 1e-10 * max(1.0, r["d_R"][0])
+            assert abs(dF[i] - r["d_F"][0]) < 1e-10 * max(1.0, r["d_F"][0])
+        assert np.isnan(dR[-1]) and np.isnan(dF[-1]) and np.isnan(S[:, :, -1]).all()
+        ref = np.array([3, 3, 3, 3, 7], np.int32)
+        dist = np.zeros(n)
+        ok(lib.me_toy_distance(n, ns, dp(S), dp(ref), dp(dist), stream))
+        want = toy.trajectory_distance(np.moveaxis(S, 2, 0)[:4], np.moveaxis(S, 2, 0)[3])
+        assert np.abs(dist[:4] - want).max() < 1e-12 * max(1.0, np.abs(want).max()), (dist, want)
+        assert dist[3] == 0.0 and np.isnan(dist[4])
+    bad = B.ToyParams(P.R0, 0.0, P.K_R, P.G0, P.M_G, P.K_G)
+    z = np.zeros(1)
+    assert lib.me_toy_run(ctypes.byref(bad), 0, 1, ns, T, 1, dp(z), dp(z), dp(z), None, dp(z), dp(z), stream) == B.ME_EINVAL
+    assert lib.me_toy_run(ctypes.byref(tp), 0, 1, 1 << 12, T, 1 << 13, dp(z), dp(z), dp(z), None, dp(z), dp(z),
+                          stream) == B.ME_EINVAL
 else:
     raise SystemExit(f"unknown scenario {scenario}")
 

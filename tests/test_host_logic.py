@@ -23,7 +23,7 @@ def _stubs():
     """Launcher stubs from the declarations in the kernel headers: each records
     a node on its stream (the last parameter) and returns hipSuccess."""
     out = ["namespace me {"]
-    for f in ("common.hpp", "fields.hpp", "adjoint.hpp", "cp.hpp"):
+    for f in ("common.hpp", "fields.hpp", "adjoint.hpp", "cp.hpp", "toy.hpp", "finite.hpp"):
         src = open(os.path.join(CSRC, f)).read()
         for m in re.finditer(r"(template <typename T>\s*)?hipError_t\s+(\w+)\(([^;]*?)\);", src, re.S):
             tmpl, name, params = m.group(1) or "", m.group(2), m.group(3)

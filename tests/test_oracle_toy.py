@@ -22,6 +22,12 @@ def test_n2_constants():
     assert abs(P.M_R / 1822.888486 - 7.0015) < 1e-3
 
 
+def test_workload_constants_are_the_oracles():
+    import workloads as W
+    for k, v in W.TOY_N2.items():
+        assert abs(getattr(P, k) - v) <= 1e-15 * abs(v), k
+
+
 def test_rk4_is_the_fourth_order_polynomial_on_linear_systems():
     rng = np.random.default_rng(3)
     A = rng.standard_normal((6, 6))

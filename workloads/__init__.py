@@ -103,10 +103,10 @@ C5 = Config("c5_adjoint_64", n=64, h=0.25, n_ions=32, n_orb=64, mu=1.0,
 # Finite boxes (the union of 7.6-bohr spheres around the atoms of the
 # paper's molecular runs, at its converged spacing 0.35 bohr): a six-atom
 # ring of the benzene carbon radius, twelve orbitals; F0 is a small case
-# for the oracle (two atoms, 3.5-bohr spheres, 24^3 points).
+# for the oracle (two atoms, 3.5-bohr spheres, 28^3 points).
 F3 = Config("f3_ring_finite_72", n=72, h=0.35, n_ions=6, n_orb=12, mu=4.0, dt=0.08, steps=20,
             placement="ring", jitter=0.05, finite_radius=7.6, seed=812 + 33, precision="f32")
-F0 = Config("f0_pair_finite_24", n=24, h=0.6, n_ions=2, n_orb=4, mu=1.0, dt=0.02, steps=4,
+F0 = Config("f0_pair_finite_28", n=28, h=0.6, n_ions=2, n_orb=4, mu=1.0, dt=0.02, steps=4,
             placement="ring", ring_radius=0.8, jitter=0.05, finite_radius=3.5, seed=812 + 30)
 
 CONFIGS = {"c1": C1, "c2": C2, "c4": C4, "c5": C5, "f3": F3}
