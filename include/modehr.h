@@ -168,6 +168,8 @@ me_status me_get_state(me_system* sys, void* psi_dev, int64_t orb_stride);
 
 /* hpsi_out = H psi_in for n_orb orbitals of the handle's precision, with the
  * current Hamiltonian H(t) (eq. new_EoM(a): kinetic + v_eff + nonlocal).
+ * On a finite box the output is zero outside the box (P H psi_in; input
+ * values outside the box enter through the stencil of points inside it).
  * Input and output must not overlap.  n_orb >= 1, orb_stride >= N. */
 me_status me_apply_H(me_system* sys, const void* psi_in_dev, void* hpsi_out_dev,
                      int32_t n_orb, int64_t orb_stride);
@@ -372,9 +374,10 @@ typedef struct {
  * substeps (RK4 steps per sample, 1..max_substeps; dt = t_total /
  * (n_samples * substeps)), window (samples per force average, >= 1); a
  * trajectory whose entries break these bounds gets NaN outputs and is not
- * run.  Outputs (device): samples (nullable) [n_samples + 1][4][n_traj]
- * (theta_1, theta_2, R, G at t_j = j t_total / n_samples, trajectory
- * fastest); d_R[n_traj] = 100 / (0.2 R_0) * rms_j (R(t_j) - R_BO(t_j)) over
+ * run.  Outputs (device): samples (nullable) [n_samples + 1][NV][n_traj],
+ * the whole state at t_j = j t_total / n_samples, trajectory fastest: NV = 6,
+ * (theta_1, theta_2, R, R', G, G') for Ehrenfest; NV = 8, (theta_1, theta_2,
+ * theta_1', theta_2', R, R', G, G') for CP; d_R[n_traj] = 100 / (0.2 R_0) * rms_j (R(t_j) - R_BO(t_j)) over
  * j = 1..n_samples; d_F[n_traj] = 100 / (0.2 K_R R_0) * rms over the
  * complete windows of (force on R averaged over the window by the trapezoid
  * rule on the run's own steps - gsBO force averaged over the window).
@@ -387,12 +390,14 @@ me_status me_toy_run(const me_toy_params* p, int32_t scheme, int32_t n_traj, int
                      double* d_R_dev, double* d_F_dev, void* stream);
 
 /* Distance of each trajectory from a reference (the Delta t_max criterion of
- * sec. 6): dist[i] = max over the four coordinates c of
+ * sec. 6, over all the dynamical variables): dist[i] = max over the n_vars
+ * state variables c of
  * 100 * rms_j (x_c[i](t_j) - x_c[ref[i]](t_j)) / (max_j - min_j of x_c[ref[i]]),
- * j = 0..n_samples, over samples laid out as me_toy_run writes them.
- * ref (device, n_traj entries in [0, n_traj); an entry outside gives NaN).
- * ME_EINVAL for NULL arrays or n_samples < 1. */
-me_status me_toy_distance(int32_t n_traj, int32_t n_samples, const double* samples_dev,
+ * j = 0..n_samples, over samples laid out as me_toy_run writes them (n_vars
+ * = NV of the scheme).  ref (device, n_traj entries in [0, n_traj); an entry
+ * outside gives NaN).  ME_EINVAL for NULL arrays, n_samples < 1 or n_vars
+ * outside [1, 8]. */
+me_status me_toy_distance(int32_t n_traj, int32_t n_samples, int32_t n_vars, const double* samples_dev,
                           const int32_t* ref_dev, double* dist_dev, void* stream);
 
 #ifdef __cplusplus

@@ -4,7 +4,7 @@ is integrated by RATTLE / velocity Verlet (sec. 5, the paragraph on the CP
 implementation, citing Tuckerman and Parrinello 1994).  TEST INFRASTRUCTURE
 ONLY, like the rest of this package.
 
-Equations of motion, as read here (reading R29):
+Equations of motion, as read here (the printed signs are garbled):
     mu_cp psi_A'' = -H psi_A + sum_B psi_B Lambda_BA,   <psi_A|psi_B> = delta_AB,
     M_J R_J''    = -grad_J E_KS,
 with Lambda Hermitian.  The conserved energy is

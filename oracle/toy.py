@@ -6,7 +6,7 @@ classical fourth-order Runge-Kutta method.  TEST INFRASTRUCTURE ONLY.
 
 Equations of motion, from the Euler-Lagrange equations of eq. L_toy (the
 theta part of the kinetic term is linear in the velocities, so the angles
-obey first-order equations; reading R32):
+obey first-order equations):
     mu theta_1' =  (G/2) sin(theta_2 - R)
     mu theta_2' = -(G/2) sin(theta_1 - R)
     M_R R''     = -K_R (R - R_0) + (G/2) [sin(theta_1 - R) + sin(theta_2 - R)]
@@ -21,7 +21,7 @@ omega_R = sqrt(K_R / M_R) -- the closed form used as the reference.
 Initial conditions (sec. 6): R and G 10 % above R_0 and G_0, at rest; the
 angles at the gsBO minimum theta_i = R(0); CP angles at rest.
 
-Distances (sec. 6, with the sampled readings R34):
+Distances (sec. 6, read on the samples of a run):
     d_R = 100 / Delta_R * sqrt(mean_j (R(t_j) - R_BO(t_j))^2)
 over the samples t_j = j t_s, j = 1..n_s, Delta_R = 0.2 R_0 the full
 variation of R_BO.  d_F compares the force on R averaged over consecutive
@@ -29,9 +29,11 @@ windows of length tau (between the electronic and the nuclear period: their
 geometric mean, rounded to whole samples) with the gsBO force averaged over
 the same windows, normalised by Delta_F = K_R Delta_R.  The force average of
 a run is the trapezoid rule over its own steps.  Delta t_max (sec. 6): the
-largest step whose trajectories of all four coordinates stay within a
-distance of 0.1 (the d-measure above, each coordinate normalised by its own
-variation in the reference) of a run with a much smaller step.
+largest step whose trajectories of all the dynamical variables -- every
+component of the integrated state, velocities included (six for the
+first-order angles, eight for CP) -- stay within a distance of 0.1 (the
+d-measure above, each variable normalised by its own variation in the
+reference) of a run with a much smaller step.
 """
 from __future__ import annotations
 
@@ -40,7 +42,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-# physical constants for the N2 molecule (reading R33): bond length 1.09768 A,
+# physical constants for the N2 molecule (the paper names the molecule, not the values): bond length 1.09768 A,
 # reduced mass of 14N2, harmonic wavenumber 2358.57 cm^-1; atomic units
 _BOHR_A = 0.529177210903
 _AMU_ME = 1822.888486
@@ -181,9 +183,10 @@ def averaging_window(p: ToyParams, scheme: str, mu: float, t_sample: float) -> i
 
 def run(p: ToyParams, scheme: str, mu, substeps: int, n_samples: int, t_total: float, window=None):
     """RK4 over [0, t_total] with dt = t_total / (n_samples * substeps) for a
-    set of mu (one trajectory each).  Returns the coordinates at every sample
-    (shape [n_mu, n_samples + 1, 4]), d_R and d_F per trajectory; `window`
-    (samples per force average) defaults to averaging_window per mu."""
+    set of mu (one trajectory each).  Returns the state at every sample
+    (shape [n_mu, n_samples + 1, 6 or 8], the layout of rhs()), d_R and d_F
+    per trajectory; `window` (samples per force average) defaults to
+    averaging_window per mu."""
     mu = np.atleast_1d(np.asarray(mu, dtype=np.float64))
     n = mu.size
     t_s = t_total / n_samples
@@ -193,8 +196,8 @@ def run(p: ToyParams, scheme: str, mu, substeps: int, n_samples: int, t_total: f
     window = np.broadcast_to(np.asarray(window, dtype=np.int64), (n,))
     y = initial_state(p, scheme, n)
     f = lambda v: rhs(p, scheme, mu, v)
-    samples = np.empty((n, n_samples + 1, 4))
-    samples[:, 0] = coords(scheme, y)
+    samples = np.empty((n, n_samples + 1, y.shape[1]))
+    samples[:, 0] = y
     sq_R = np.zeros(n)
     sq_F = np.zeros(n)
     n_blocks = np.zeros(n, dtype=np.int64)
@@ -208,9 +211,9 @@ def run(p: ToyParams, scheme: str, mu, substeps: int, n_samples: int, t_total: f
             facc += 0.5 * dt * (F + F1)
             F = F1
             step += 1
-        samples[:, j] = coords(scheme, y)
+        samples[:, j] = y
         t = j * t_s
-        sq_R += (samples[:, j, 2] - gsbo_R(p, t)) ** 2
+        sq_R += (coords(scheme, y)[:, 2] - gsbo_R(p, t)) ** 2
         done = (j % window) == 0
         if done.any():
             tau = window * t_s
@@ -226,8 +229,9 @@ def run(p: ToyParams, scheme: str, mu, substeps: int, n_samples: int, t_total: f
 
 
 def trajectory_distance(samples, ref):
-    """max over the four coordinates of 100 / Delta_x * rms(x - x_ref) over the
-    samples, Delta_x the coordinate's variation (max - min) in the reference."""
+    """max over the variables (last axis) of 100 / Delta_x * rms(x - x_ref)
+    over the samples, Delta_x the variable's variation (max - min) in the
+    reference."""
     samples = np.asarray(samples)
     ref = np.asarray(ref)
     span = ref.max(axis=-2) - ref.min(axis=-2)

@@ -134,7 +134,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.me_batch_destroy.argtypes = [c_void_p]
     lib.me_toy_run.argtypes = [POINTER(ToyParams), c_int32, c_int32, c_int32, c_double, c_int32, c_void_p, c_void_p,
                                c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
-    lib.me_toy_distance.argtypes = [c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.me_toy_distance.argtypes = [c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
     for s in SYMBOLS:
         if s not in ("me_last_error", "me_strerror", "me_batch_last_error"):
             getattr(lib, s).restype = c_int32
@@ -500,8 +500,9 @@ def toy_params(R0, M_R, K_R, G0, M_G, K_G) -> ToyParams:
 def toy_run(p: ToyParams, scheme: str, mu, substeps, window, n_samples: int, t_total: float,
             max_substeps: Optional[int] = None, samples: bool = True, device="cuda:0"):
     """me_toy_run over len(mu) trajectories (mu, substeps, window: sequences
-    or tensors).  Returns {"d_R", "d_F", "samples" ([n_samples + 1, 4, n_traj]
-    or None)} as device tensors, ordered on torch's current stream."""
+    or tensors).  Returns {"d_R", "d_F", "samples" ([n_samples + 1, NV, n_traj],
+    NV = 6 for Ehrenfest, 8 for CP, or None)} as device tensors, ordered on
+    torch's current stream."""
     import torch
     lib = load()
     mu = torch.as_tensor(mu, dtype=torch.float64, device=device).contiguous()
@@ -512,7 +513,8 @@ def toy_run(p: ToyParams, scheme: str, mu, substeps, window, n_samples: int, t_t
         max_substeps = int(sub.max().item()) if n else 1
     d_R = torch.empty(n, dtype=torch.float64, device=device)
     d_F = torch.empty(n, dtype=torch.float64, device=device)
-    S = torch.empty((n_samples + 1, 4, n), dtype=torch.float64, device=device) if samples else None
+    nv = 8 if scheme == "cp" else 6
+    S = torch.empty((n_samples + 1, nv, n), dtype=torch.float64, device=device) if samples else None
     stream = torch.cuda.current_stream(mu.device).cuda_stream
     st = lib.me_toy_run(ctypes.byref(p), c_int32(TOY_SCHEMES[scheme]), c_int32(n), c_int32(n_samples),
                         c_double(t_total), c_int32(max_substeps), c_void_p(mu.data_ptr()), c_void_p(sub.data_ptr()),
@@ -524,7 +526,7 @@ def toy_run(p: ToyParams, scheme: str, mu, substeps, window, n_samples: int, t_t
 
 
 def toy_distance(samples, ref):
-    """me_toy_distance: samples [n_samples + 1, 4, n_traj] (device), ref the
+    """me_toy_distance: samples [n_samples + 1, NV, n_traj] (device), ref the
     reference trajectory of each; returns the distances (device tensor)."""
     import torch
     lib = load()
@@ -533,7 +535,7 @@ def toy_distance(samples, ref):
     ref = torch.as_tensor(ref, dtype=torch.int32, device=samples.device).reshape(-1).expand(n).contiguous()
     dist = torch.empty(n, dtype=torch.float64, device=samples.device)
     stream = torch.cuda.current_stream(samples.device).cuda_stream
-    st = lib.me_toy_distance(c_int32(n), c_int32(n_samples), c_void_p(samples.data_ptr()),
+    st = lib.me_toy_distance(c_int32(n), c_int32(n_samples), c_int32(samples.shape[1]), c_void_p(samples.data_ptr()),
                              c_void_p(ref.data_ptr()), c_void_p(dist.data_ptr()), c_void_p(stream))
     if st != ME_OK:
         raise ModehrError(st, lib.me_last_error(None).decode())

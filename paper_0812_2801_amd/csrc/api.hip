@@ -2574,12 +2574,15 @@ me_status me_toy_run(const me_toy_params* p, int32_t scheme, int32_t n_traj, int
     return ME_OK;
 }
 
-me_status me_toy_distance(int32_t n_traj, int32_t n_samples, const double* samples, const int32_t* ref,
-                          double* dist, void* stream) {
-    if (n_traj < 0 || n_samples < 1) { g_init_error = "need n_traj >= 0, n_samples >= 1"; return ME_EINVAL; }
+me_status me_toy_distance(int32_t n_traj, int32_t n_samples, int32_t n_vars, const double* samples,
+                          const int32_t* ref, double* dist, void* stream) {
+    if (n_traj < 0 || n_samples < 1 || n_vars < 1 || n_vars > 8) {
+        g_init_error = "need n_traj >= 0, n_samples >= 1, 1 <= n_vars <= 8";
+        return ME_EINVAL;
+    }
     if (n_traj == 0) return ME_OK;
     if (!samples || !ref || !dist) { g_init_error = "NULL device array"; return ME_EINVAL; }
-    const hipError_t e = launch_toy_distance(n_traj, n_samples, samples, ref, dist, (hipStream_t)stream);
+    const hipError_t e = launch_toy_distance(n_traj, n_samples, n_vars, samples, ref, dist, (hipStream_t)stream);
     if (e != hipSuccess) { g_init_error = hipGetErrorString(e); return ME_EDEVICE; }
     return ME_OK;
 }

@@ -26,8 +26,8 @@ struct ToyConst {
 // state: Ehrenfest (theta_1, theta_2, R, R', G, G'); CP (theta_1, theta_2,
 // theta_1', theta_2', R, R', G, G')
 template <bool CP> struct Layout;
-template <> struct Layout<false> { static constexpr int NV = 6, IR = 2, IG = 4; };
-template <> struct Layout<true> { static constexpr int NV = 8, IR = 4, IG = 6; };
+template <> struct Layout<false> { static constexpr int NV = toy_state_size(false), IR = 2, IG = 4; };
+template <> struct Layout<true> { static constexpr int NV = toy_state_size(true), IR = 4, IG = 6; };
 
 template <bool CP>
 __device__ __forceinline__ void rhs(const ToyConst& c, const double* y, double* d, double& force_R) {
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(64) void toy_kernel(ToyArgs a) {
         a.d_R[i] = NAN;
         a.d_F[i] = NAN;
         if (a.samples)
-            for (int64_t k = 0; k < (int64_t)(a.n_samples + 1) * 4; ++k) a.samples[k * n + i] = NAN;
+            for (int64_t k = 0; k < (int64_t)(a.n_samples + 1) * NV; ++k) a.samples[k * n + i] = NAN;
         return;
     }
     const ToyConst c{a.R0, a.K_R, a.G0, a.K_G, 1.0 / a.M_R, 1.0 / a.M_G, 1.0 / mu};
@@ -81,12 +81,8 @@ __global__ __launch_bounds__(64) void toy_kernel(ToyArgs a) {
     for (int k = 0; k < NV; ++k) y[k] = 0.0;
     y[0] = y[1] = y[IR] = 1.1 * a.R0;
     y[IG] = 1.1 * a.G0;
-    if (a.samples) {
-        a.samples[0 * n + i] = y[0];
-        a.samples[1 * n + i] = y[1];
-        a.samples[2 * n + i] = y[IR];
-        a.samples[3 * n + i] = y[IG];
-    }
+    if (a.samples)
+        for (int k = 0; k < NV; ++k) a.samples[k * n + i] = y[k];
     double k1[NV], k2[NV], k3[NV], k4[NV], tmp[NV];
     double F0, Fx;
     rhs<CP>(c, y, k1, F0);
@@ -108,11 +104,8 @@ __global__ __launch_bounds__(64) void toy_kernel(ToyArgs a) {
         }
         const double t = j * t_s;
         if (a.samples) {
-            double* o = a.samples + (int64_t)j * 4 * n + i;
-            o[0] = y[0];
-            o[n] = y[1];
-            o[2 * n] = y[IR];
-            o[3 * n] = y[IG];
+            double* o = a.samples + (int64_t)j * NV * n + i;
+            for (int k = 0; k < NV; ++k) o[k * n] = y[k];
         }
         const double dR = y[IR] - (a.R0 + amp * cos(w * t));
         sq_R += dR * dR;
@@ -130,7 +123,7 @@ __global__ __launch_bounds__(64) void toy_kernel(ToyArgs a) {
     a.d_F[i] = 100.0 / (a.K_R * span) * sqrt(sq_F / (n_blocks > 0 ? n_blocks : 1));
 }
 
-__global__ __launch_bounds__(256) void toy_distance_kernel(int n_traj, int n_samples, const double* S,
+__global__ __launch_bounds__(256) void toy_distance_kernel(int n_traj, int n_samples, int n_vars, const double* S,
                                                            const int* ref, double* dist) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_traj) return;
@@ -142,10 +135,10 @@ __global__ __launch_bounds__(256) void toy_distance_kernel(int n_traj, int n_sam
     const int64_t n = n_traj;
     double worst = 0.0;
     bool nan = false;
-    for (int cidx = 0; cidx < 4; ++cidx) {
+    for (int cidx = 0; cidx < n_vars; ++cidx) {
         double sq = 0.0, lo = INFINITY, hi = -INFINITY;
         for (int j = 0; j <= n_samples; ++j) {
-            const int64_t row = ((int64_t)j * 4 + cidx) * n;
+            const int64_t row = ((int64_t)j * n_vars + cidx) * n;
             const double xr = S[row + r];
             const double d = S[row + i] - xr;
             sq += d * d;
@@ -171,10 +164,10 @@ hipError_t launch_toy(const ToyArgs& a, bool cp, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_toy_distance(int n_traj, int n_samples, const double* samples, const int* ref, double* dist,
-                               hipStream_t s) {
+hipError_t launch_toy_distance(int n_traj, int n_samples, int n_vars, const double* samples, const int* ref,
+                               double* dist, hipStream_t s) {
     if (n_traj <= 0) return hipSuccess;
-    toy_distance_kernel<<<(n_traj + 255) / 256, 256, 0, s>>>(n_traj, n_samples, samples, ref, dist);
+    toy_distance_kernel<<<(n_traj + 255) / 256, 256, 0, s>>>(n_traj, n_samples, n_vars, samples, ref, dist);
     return hipGetLastError();
 }
 

@@ -309,7 +309,7 @@ elif scenario == "toy":
         sub = np.array([3, 4, 20, 24, 3], np.int32)    # omega dt < 1 everywhere
         win = np.array([2, 1, 3, 5, 2], np.int32)
         n = mu.size
-        S = np.zeros((ns + 1, 4, n))
+        S = np.zeros((ns + 1, 8 if scheme == "cp" else 6, n))
         dR, dF = np.zeros(n), np.zeros(n)
         ok(lib.me_toy_run(ctypes.byref(tp), B.TOY_SCHEMES[scheme], n, ns, T, 24, dp(mu), dp(sub), dp(win), dp(S),
                           dp(dR), dp(dF), stream))
@@ -324,7 +324,7 @@ elif scenario == "toy":
         assert np.isnan(dR[-1]) and np.isnan(dF[-1]) and np.isnan(S[:, :, -1]).all()
         ref = np.array([3, 3, 3, 3, 7], np.int32)
         dist = np.zeros(n)
-        ok(lib.me_toy_distance(n, ns, dp(S), dp(ref), dp(dist), stream))
+        ok(lib.me_toy_distance(n, ns, S.shape[1], dp(S), dp(ref), dp(dist), stream))
         want = toy.trajectory_distance(np.moveaxis(S, 2, 0)[:4], np.moveaxis(S, 2, 0)[3])
         assert np.abs(dist[:4] - want).max() < 1e-12 * max(1.0, np.abs(want).max()), (dist, want)
         assert dist[3] == 0.0 and np.isnan(dist[4])

@@ -92,3 +92,16 @@ def test_toy_full_sweep(scheme):
     assert d_R[0] < 0.05 * d_R[-1]
     assert np.all(np.isfinite(dt_max[: S["n_mu"] // 2]))
     assert dt_max[0] < dt_max[S["n_mu"] // 2]
+
+
+@pytest.mark.parametrize("scheme,mu", [("ehrenfest", 0.3), ("cp", 5.0)])
+def test_dt_max_matches_oracle(scheme, mu):
+    # the Delta t_max selection on a short run that the oracle can afford
+    from paper_0812_2801_amd import toy
+    T, P = _oracle_params()
+    ladder = [1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 128]
+    n_s, periods = 60, 1.0
+    r = toy.sweep(scheme, [mu], ladder, n_s, periods)
+    want = T.dt_max(P, scheme, mu, n_s, periods * P.period_R, ladder[:-1], ladder[-1])
+    note(f"toy {scheme} mu {mu}: dt_max {r['dt_max'][0]} (oracle {want}); distances {r['dist'][:, 0].round(4)}")
+    assert want is not None and abs(r["dt_max"][0] - want) <= 1e-12 * want
