@@ -138,12 +138,22 @@ __global__ void __launch_bounds__(256) local_forces_free_kernel(const double* __
     }
 }
 
-__global__ void local_forces_free_sum_kernel(const double* __restrict__ part, double dv, double* __restrict__ floc) {
-    const int J = blockIdx.x;
-    if (threadIdx.x >= 3) return;
-    double s = 0.0;
-    for (int b = 0; b < FREE_FORCE_CHUNKS; ++b) s += part[((int64_t)J * FREE_FORCE_CHUNKS + b) * 3 + threadIdx.x];
-    floc[3 * J + threadIdx.x] = -dv * s;
+// one block per ion: each thread adds two chunks, then a tree in LDS (a
+// fixed order, so the result does not depend on timing)
+__global__ void __launch_bounds__(256) local_forces_free_sum_kernel(const double* __restrict__ part, double dv,
+                                                                    double* __restrict__ floc) {
+    static_assert(FREE_FORCE_CHUNKS == 512, "two chunks per thread of a 256-thread block");
+    __shared__ double red[3][256];
+    const int J = blockIdx.x, t = threadIdx.x;
+    const double* p = part + (int64_t)J * FREE_FORCE_CHUNKS * 3;
+    for (int k = 0; k < 3; ++k) red[k][t] = p[t * 3 + k] + p[(t + 256) * 3 + k];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (t < st)
+            for (int k = 0; k < 3; ++k) red[k][t] += red[k][t + st];
+        __syncthreads();
+    }
+    if (t < 3) floc[3 * J + t] = -dv * red[t][0];
 }
 
 __global__ void ion_coulomb_kernel(const double* __restrict__ pos, const double* __restrict__ zval, int n_ions,
@@ -223,7 +233,7 @@ hipError_t launch_local_forces_free(const double* rho, const double* pos, const 
                                     int ny, int nz, double h, double a, double* part, double* floc, hipStream_t s) {
     if (n_ions == 0) return hipSuccess;
     local_forces_free_kernel<<<FREE_FORCE_CHUNKS, 256, 0, s>>>(rho, pos, zval, n_ions, nx, ny, nz, h, a, part);
-    local_forces_free_sum_kernel<<<n_ions, 64, 0, s>>>(part, h * h * h, floc);
+    local_forces_free_sum_kernel<<<n_ions, 256, 0, s>>>(part, h * h * h, floc);
     return hipGetLastError();
 }
 

@@ -47,12 +47,17 @@ def stats(csv_path, out, command):
     lines = [f"# rocprofv3 kernel statistics", "", f"Command: `{command}`", "",
              "| kernel | calls | avg µs | total % |", "|---|---:|---:|---:|"]
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:25]:
-        name = r["Name"].split("(")[0].replace("|", "/")
+        name = _short(r["Name"]).replace("|", "/")
         if name.startswith("Cijk_") and len(name) > 60:        # library GEMM: tile and MFMA fields only
             name = "_".join(name.split("_")[:6]) + "_..."
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                      f"{100 * float(r['TotalDurationNs']) / tot:.1f} |")
     open(out, "w").write("\n".join(lines) + "\n")
+
+
+def _short(name: str) -> str:
+    """Kernel name without its argument list (anonymous namespaces dropped)."""
+    return name.replace("(anonymous namespace)::", "").split("(")[0]
 
 
 def traffic(fetch_dir, write_dir, cf_dir, cw_dir, copy_bytes, out, command):
@@ -82,7 +87,7 @@ def traffic(fetch_dir, write_dir, cf_dir, cw_dir, copy_bytes, out, command):
            "fetch_bytes_per_launch": statistics.mean(fetch) * kf * 1024.0,
            "write_bytes_per_launch": statistics.mean(write) * kw * 1024.0,
            "bytes_per_launch": per_launch,
-           "by_kernel": {k.split("(")[0]: {"fetch_KiB": statistics.mean(v),
+           "by_kernel": {_short(k): {"fetch_KiB": statistics.mean(v),
                                             "write_KiB": statistics.mean(w.get(k, [0.0]))}
                          for k, v in f.items()},
            "stencil_sha256_16": stencil_hash()}
@@ -99,7 +104,7 @@ def mfma(pmc_dir, pattern, n_simd, out, command):
         d = r["Dispatch_Id"]
         per[d][r["Counter_Name"]] = per[d].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
         per[d]["ns"] = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
-        names[d] = r["Kernel_Name"].split("(")[0]
+        names[d] = _short(r["Kernel_Name"])
     util, rate, dur = [], [], []
     for d, c in per.items():
         util.append(100.0 * c["SQ_VALU_MFMA_BUSY_CYCLES"] / (c["GRBM_GUI_ACTIVE"] * n_simd))
