@@ -164,12 +164,13 @@ def cp_config(n: int):
                         n_ions=max(2, int(round(64 * f))), seed=812 + 7 + n)
 
 
-def time_scheme(cfg, scheme: str, steps: int, warmup: int = 2) -> float:
-    """ms per step of 'ehrenfest' or 'cp' on cfg (FP32, device-generated orbitals)."""
+def time_scheme(cfg, scheme: str, steps: int, warmup: int = 2, **over) -> float:
+    """ms per step of 'ehrenfest' or 'cp' on cfg (FP32, device-generated
+    orbitals); `over` goes to the parameters (ETRS, force form)."""
     import torch
     import workloads as W
     from paper_0812_2801_amd import binding as B
-    p, keep = B.params_from_config(cfg, W.ion_positions(cfg), precision="f32")
+    p, keep = B.params_from_config(cfg, W.ion_positions(cfg), precision="f32", **over)
     s = B.System(p, keep, device="cuda:0")
     psi = W.initial_orbitals_device(cfg, "cuda:0")
     s.set_state(psi)
@@ -391,6 +392,18 @@ def run_toy(oracle_sample: bool = True) -> dict:
     return out
 
 
+def run_variants(steps: int = 20) -> dict:
+    """The propagator and force variants on the 96^3 x 128 FP32 workload:
+    AETRS, ETRS with one and two corrections, the wave-function-gradient
+    nonlocal force."""
+    import workloads as W
+    out = {"workload": "96^3 h=0.25, 64 ions, 128 FP32 orbitals", "steps": steps}
+    for name, over in (("aetrs", {}), ("etrs_1", {"etrs_iterations": 1}), ("etrs_2", {"etrs_iterations": 2}),
+                       ("aetrs_gradient_force", {"nl_force_form": 1})):
+        out[name + "_ms_per_step"] = round(time_scheme(W.C2, "ehrenfest", steps, **over), 4)
+    return out
+
+
 def run_finite(steps: int = 50) -> dict:
     """The finite-box workload (the 72^3 ring box): ms per MD step in FP32 and
     FP64, beside the same grid run as a periodic cube."""
@@ -446,6 +459,8 @@ def main():
                     help="only the Car-Parrinello comparison (Ehrenfest timed at the same sizes)")
     ap.add_argument("--dt-scan", action="store_true",
                     help="only the largest stable time step against the grid spacing (Taylor-4, Taylor-8, CP)")
+    ap.add_argument("--variants", action="store_true",
+                    help="only the propagator / force variants (ETRS, gradient-form force) on the 96^3 workload")
     ap.add_argument("--finite", action="store_true",
                     help="only the finite-box workload (union of atom-centred spheres, free-space Hartree)")
     ap.add_argument("--toy", action="store_true",
@@ -461,6 +476,9 @@ def main():
         return
     if args.batch_only:           # profiling aid: the batched workload alone
         print(json.dumps({"batched": run_batch(args.batch_steps, 8, 6, not args.no_autotune)}))
+        return
+    if args.variants:
+        print(json.dumps({"variants": run_variants()}))
         return
     if args.finite:
         print(json.dumps({"finite_box": run_finite()}))

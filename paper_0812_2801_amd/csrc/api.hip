@@ -247,6 +247,7 @@ struct Layout {
     double2 *rhok, *spec, *phase, *phaseT, *ewald_sg;
     void* fft_work;
     uint8_t* mask;              // finite box: 1 inside
+    int2* zr;                   // finite box: per y-tile plane range of the box (Horner stages)
     double *rpad_in, *rpad_out, *gk;
     double2* cpad;
     void* fft_work2;
@@ -298,6 +299,7 @@ static Layout carve(const Geometry& g, char* base) {
     L.fft_work = c.take<void>(g.fft_work);
     if (g.finite) {
         L.mask = c.take<uint8_t>(g.N);
+        L.zr = c.take<int2>((size_t)g.nyt * sizeof(int2));
         L.rpad_in = c.take<double>(g.npad * 8);
         L.rpad_out = c.take<double>(g.npad * 8);
         L.cpad = c.take<double2>(g.nhalf2 * 16);
@@ -383,6 +385,7 @@ static Layout carve(const Geometry& g, char* base) {
 struct me_system {
     me_params prm{};
     std::vector<double> pos0, vel0, mass, zval;
+    std::vector<int2> zr_host;      // finite box: per y-tile plane ranges
     Geometry g{};
     Layout w{};
     hipStream_t stream = nullptr;
@@ -644,6 +647,7 @@ me_status exponential(me_system* sys, const T* veff, int t, bool last) {
         a.psi0 = psi;
         a.out = out;
         a.alpha = (T)(-tau / k);
+        a.zr = g.finite ? sys->w.zr : nullptr;
         const bool norm = last && k == 1;
         a.partial = norm ? sys->w.norm_part : nullptr;
         if (norm) sys->norm_tiles = g.nyt * g.nzc;
@@ -1893,6 +1897,29 @@ me_status me_init_system(const me_params* p, void* workspace, size_t ws_bytes, v
             }
             INITCHK(launch_box_mask(sys->w.pos, g.n_ions, g.nx, g.ny, g.nz, p->h, p->finite_radius, sys->w.mask,
                                     sys->stream));
+            // per y-tile plane range holding every box point of its rows (a
+            // superset: the chord of each sphere at the row, one plane of
+            // margin); the Horner stages march only there, so the stage
+            // buffers start at zero and stay zero outside the box
+            sys->zr_host.assign(g.nyt, make_int2(0, 0));
+            for (int t = 0; t < g.nyt; ++t) {
+                int lo = g.nz, hi = 0;
+                for (int y = t * g.ty; y < (t + 1) * g.ty; ++y)
+                    for (int J = 0; J < g.n_ions; ++J) {
+                        const double dy = y * p->h - sys->pos0[3 * J + 1];
+                        const double rem = p->finite_radius * p->finite_radius - dy * dy;
+                        if (rem < 0.0) continue;
+                        const double c = std::sqrt(rem), Z = sys->pos0[3 * J + 2];
+                        lo = std::min(lo, std::max(0, (int)std::floor((Z - c) / p->h) - 1));
+                        hi = std::max(hi, std::min(g.nz, (int)std::ceil((Z + c) / p->h) + 2));
+                    }
+                sys->zr_host[t] = make_int2(lo, std::max(lo, hi));
+            }
+            INITCHK(hipMemcpyAsync(sys->w.zr, sys->zr_host.data(), (size_t)g.nyt * sizeof(int2), hipMemcpyHostToDevice,
+                                   sys->stream));
+            const size_t ob = (size_t)g.n_orb * g.stride * g.bc;
+            INITCHK(hipMemsetAsync(sys->w.bufA, 0, ob, sys->stream));
+            INITCHK(hipMemsetAsync(sys->w.bufB, 0, ob, sys->stream));
             INITCHK(hipMemsetAsync(sys->w.rpad_in, 0, g.npad * 8, sys->stream));
             INITCHK(launch_green_doubled(g.nx, g.ny, g.nz, p->h, sys->w.rpad_out, sys->stream));
             void* gi[1] = {sys->w.rpad_out};

@@ -82,6 +82,9 @@ struct StencilArgs {
     T kin;                   // -1/(2 h^2)
     T alpha;                 // Horner coefficient: c_k = i*alpha, alpha = -tau/k
     double* partial;         // [n_orb][nyt*nzc] norm or expectation partials, or nullptr
+    const int2* zr;          // finite box: per y-tile the planes [x, y) that hold every box
+                             // point of its rows (outputs elsewhere are left as they are,
+                             // zero by the box invariant), or nullptr: whole columns
 };
 
 // One system of a batched (persistent) stencil launch.

@@ -350,10 +350,15 @@ stencil_kernel(const cx_t<T>* __restrict__ u_all, const cx_t<T>* __restrict__ p0
     const int rest = b / a.nyt;
     const int zc = rest % a.nzc;
     const int A = rest / a.nzc;
-    const int z0 = zc * a.zchunk;
+    int z0 = zc * a.zchunk, z1 = z0 + a.zchunk;
+    if (a.zr != nullptr) {          // finite box: only the planes where the tile's rows meet it
+        const int2 r = a.zr[ytile];
+        z0 = max(z0, r.x);
+        z1 = max(z0, min(z1, r.y));
+    }
     const double acc = zmarch<T, PX, TY, 1, MODE, NORM>(
         u_all + (int64_t)A * a.stride, p0_all + (int64_t)A * a.stride, out_all + (int64_t)A * a.stride, v,
-        a.nx, a.ny, a.nz, TY, ytile * TY, TY, z0, z0 + a.zchunk, a.kin, a.alpha, tiles, true);
+        a.nx, a.ny, a.nz, TY, ytile * TY, TY, z0, z1, a.kin, a.alpha, tiles, true);
     if constexpr (NORM || MODE == MODE_EXPECT_T) {
         const double s = block_sum(acc, red);
         if (threadIdx.x == 0) partial[(int64_t)A * (a.nyt * a.nzc) + zc * a.nyt + ytile] = s;

@@ -52,6 +52,8 @@ struct dim3 {
 };
 struct float2 { float x, y; };
 struct double2 { double x, y; };
+struct int2 { int x, y; };
+inline int2 make_int2(int a, int b) { return {a, b}; }
 struct float4 { float x, y, z, w; };
 inline float2 make_float2(float a, float b) { return {a, b}; }
 inline double2 make_double2(double a, double b) { return {a, b}; }

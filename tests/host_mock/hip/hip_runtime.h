@@ -18,6 +18,8 @@ typedef enum { hipDeviceAttributeMultiprocessorCount = 1 } hipDeviceAttribute_t;
 #define hipEventDefault 0u
 struct float2 { float x, y; };
 struct double2 { double x, y; };
+struct int2 { int x, y; };
+inline int2 make_int2(int a, int b) { return {a, b}; }
 hipError_t hipStreamCreateWithFlags(hipStream_t*, unsigned);
 hipError_t hipStreamDestroy(hipStream_t);
 hipError_t hipStreamSynchronize(hipStream_t);
