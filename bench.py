@@ -488,7 +488,7 @@ def main():
         return
     if args.dt_scan:
         from paper_0812_2801_amd import scan
-        print(json.dumps({"dt_max_vs_spacing": scan.spacing_series()}))
+        print(json.dumps({"dt_max_vs_spacing": scan.spacing_series(), "dt_max_vs_mass": scan.mass_series()}))
         return
     if args.cp_only:
         import workloads as W

@@ -1,7 +1,9 @@
 """Largest stable time step of the modified-Ehrenfest step (AETRS with an
 order-K Taylor exponential, sec. 5.1) and of the Car-Parrinello step against
 the grid spacing -- the comparison of Fig. spacing: the Taylor propagator's
-limit grows with h^2, CP's Verlet limit with h.
+limit grows with h^2, CP's Verlet limit with h -- and against the mass
+parameter: mu enters the Taylor exponent as dt / (2 mu), so its limit grows
+as mu; CP's Verlet limit grows as sqrt(mu_CP).
 
 A trial runs `steps` steps on the GPU from orbitals with a small white-noise
 admixture (so that the highest-frequency modes, which go unstable first, are
@@ -15,6 +17,7 @@ and bisected to `rel_tol`.
 from __future__ import annotations
 
 import math
+import sys
 
 from . import binding as B
 
@@ -77,6 +80,13 @@ def stable(cfg, psi0, scheme: str, dt: float, steps: int, mu: float, mu_cp: floa
 
 def dt_max(cfg, psi0, scheme: str, mu: float, mu_cp: float, dt0: float, taylor: int = 4, steps: int = 150,
            rel_tol: float = 0.01, precision: str = "f64") -> float:
+    lo = _dt_max(cfg, psi0, scheme, mu, mu_cp, dt0, taylor, steps, rel_tol, precision)
+    print(f"# dt_max {scheme} n={cfg.n} taylor={taylor} mu={mu:g} mu_cp={mu_cp:g}: {lo:.5g}", file=sys.stderr,
+          flush=True)
+    return lo
+
+
+def _dt_max(cfg, psi0, scheme, mu, mu_cp, dt0, taylor, steps, rel_tol, precision) -> float:
     lo, hi = 0.0, dt0
     while stable(cfg, psi0, scheme, hi, steps, mu, mu_cp, taylor, precision):
         lo, hi = hi, 2.0 * hi
@@ -127,3 +137,24 @@ def spacing_series(ns=(32, 40, 48, 60), mu: float = 4.0, mu_cp: float = 200.0, s
     return {"mu": mu, "mu_cp": mu_cp, "steps": steps, "rows": rows,
             "slope_ehrenfest_t4": slope("ehrenfest_t4"), "slope_ehrenfest_t8": slope("ehrenfest_t8"),
             "slope_cp": slope("cp")}
+
+
+def _slope(xs, ys):
+    lx = [math.log(x) for x in xs]
+    ly = [math.log(y) for y in ys]
+    mx, my = sum(lx) / len(lx), sum(ly) / len(ly)
+    return sum((a - mx) * (b - my) for a, b in zip(lx, ly)) / sum((a - mx) ** 2 for a in lx)
+
+
+def mass_series(n: int = 40, mus=(2.0, 4.0, 8.0), mus_cp=(50.0, 200.0, 800.0), steps: int = 150):
+    """dt_max of Taylor-4 AETRS against mu and of CP against mu_CP on one
+    grid, with the log-log slopes (1 and 1/2 expected)."""
+    cfg = spacing_config(n)
+    psi0 = noisy_orbitals(cfg)
+    e = [dt_max(cfg, psi0, "ehrenfest", mu, 200.0, 0.05 * mu / 4.0, 4, steps) for mu in mus]
+    c = [dt_max(cfg, psi0, "cp", 4.0, mc, 0.5 * math.sqrt(mc / 200.0), 4, steps) for mc in mus_cp]
+    del psi0
+    return {"n": n, "h": cfg.h, "steps": steps,
+            "ehrenfest_t4": [{"mu": m, "dt_max": d} for m, d in zip(mus, e)],
+            "cp": [{"mu_cp": m, "dt_max": d} for m, d in zip(mus_cp, c)],
+            "slope_ehrenfest_t4_vs_mu": _slope(mus, e), "slope_cp_vs_mu_cp": _slope(mus_cp, c)}
