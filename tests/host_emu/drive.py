@@ -296,6 +296,16 @@ elif scenario == "finite":
     p, keep = B.params_from_config(c, inp["pos"], precision=prec, finite_radius=6.0)
     size = ctypes.c_size_t(0)
     assert lib.me_workspace_size(ctypes.byref(p), ctypes.byref(size)) == B.ME_EINVAL     # box touches the faces
+    # ETRS on the box: the corrections' v_Hxc comes from the free-space solve
+    h = new_system(c, inp, etrs_iterations=1)
+    ok(lib.me_set_state(h, psi.ctypes.data, c.n_points), h)
+    st = dynamics.init_state(m, inp["psi"], inp["pos"])
+    for _ in range(2):
+        ok(lib.me_propagate_step(h, None, None), h)
+        st = dynamics.etrs_step(m, st, 0.0, iterations=1)
+    psi_out, f = state(h, c)
+    compare("finite ETRS 2 steps", c, psi_out, f, st)
+    ok(lib.me_destroy(h))
 elif scenario == "toy":
     # the toy-model sweep against the oracle: both schemes, uneven substeps
     # and windows, a trajectory with an invalid entry (NaN outputs), and the

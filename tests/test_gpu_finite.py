@@ -86,3 +86,26 @@ def test_ring_box_fields_forces_and_invariants():
     p, keep = B.params_from_config(cfg, inp["pos"], finite_radius=10.0)
     with pytest.raises(B.ModehrError):
         B.System(p, keep)
+
+
+def test_small_box_etrs():
+    # the finite box with the ETRS propagator (v_Hxc of the predicted density
+    # from the free-space Poisson solve) against the oracle
+    import torch
+    from oracle import dynamics, finite
+    from paper_0812_2801_amd import binding as B
+    cfg = W.F0
+    note(f"finite box {cfg.name} ETRS")
+    inp = W.make_inputs(cfg)
+    p, keep = B.params_from_config(cfg, inp["pos"], precision="f64", etrs_iterations=1)
+    s = B.System(p, keep)
+    s.set_state(torch.from_numpy(inp["psi"].reshape(cfg.n_orb, -1)))
+    m = finite.FiniteModel.from_config(cfg, pos0=inp["pos"], radius=cfg.finite_radius)
+    st = dynamics.init_state(m, inp["psi"], inp["pos"])
+    for n in range(2):
+        s.step()
+        st = dynamics.etrs_step(m, st, 0.0, iterations=1)
+        dpsi = np.abs(to_np(s.get_state()).reshape(st.psi.shape) - st.psi).max()
+        note(f"  step {n}: max|dpsi| {dpsi:.2e}")
+        assert dpsi < 1e-10
+    s.close()

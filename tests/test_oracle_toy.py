@@ -157,3 +157,19 @@ def test_distances_vanish_as_mu_goes_to_zero():
     # at the smallest mass the Ehrenfest R(t) follows the gsBO motion closely
     assert out["ehrenfest"]["d_R"][2] < 1.0
     assert out["cp"]["d_R"][2] < 1.0
+
+
+def test_dt_max_is_the_threshold_of_the_ladder():
+    # the selected step passes (with every smaller one) and the next coarser
+    # step of the ladder fails the 0.1 distance criterion
+    T = P.period_R
+    ladder = [1, 2, 3, 4, 6, 8, 12, 16, 24, 32]
+    for scheme, mu in (("ehrenfest", 0.3), ("cp", 5.0)):
+        best = toy.dt_max(P, scheme, mu, 60, T, ladder, 128)
+        assert best is not None
+        s_best = int(round(T / (60 * best)))
+        ref = toy.run(P, scheme, [mu], 128, 60, T)["samples"][0]
+        d = {s: toy.trajectory_distance(toy.run(P, scheme, [mu], s, 60, T)["samples"][0], ref) for s in ladder}
+        assert all(d[s] < 0.1 for s in ladder if s >= s_best), (scheme, d)
+        coarser = [s for s in ladder if s < s_best]
+        assert coarser and d[max(coarser)] >= 0.1, (scheme, d)
