@@ -120,9 +120,10 @@ TOY_N2 = dict(R0=1.09768 / 0.529177210903, M_R=_M_N2, K_R=_M_N2 * (2358.57 / 219
               G0=0.30, M_G=_M_N2, K_G=20.0)
 # the sweep of Fig. 1 (c, d): four gsBO periods sampled 200 times; 256
 # log-spaced masses per scheme; RK4 substeps per sample on a 2^(1/3) ladder
-# from 512 down to 1, below a reference of 2048
+# from 128 down to 1 (the largest stable steps of these masses need 2 to 40),
+# below a reference of 512
 TOY_SWEEP = dict(periods=4.0, n_samples=200, n_mu=256, mu_ehrenfest=(0.02, 20.0), mu_cp=(2.0, 2000.0),
-                 ladder_steps=28, finest=2048, ratio=2 ** (1 / 3))
+                 ladder_steps=28, finest=512, ratio=2 ** (1 / 3))
 
 
 def batch_configs(n_systems: int = 16, seed: int = 812 + 3,
