@@ -4,8 +4,8 @@ ladder of RK4 time steps, every (mass, step) trajectory runs as one
 work-item of one launch (me_toy_run).  The finest step of each mass is its
 "exact" trajectory; me_toy_distance gives every other run's distance from
 it, and Delta t_max(mass) is the largest step of the ladder that, with every
-smaller step, stays below 0.1 (sec. 6: 0.1 % of each coordinate's
-variation).  d_R and d_F (Fig. 1 a, b) come from the exact runs.
+smaller step, stays below 0.1 (sec. 6: 0.1 % of the variation of each
+dynamical variable, velocities included).  d_R and d_F (Fig. 1 a, b) come from the exact runs.
 
 The default constants are those of the N2 molecule with a chosen gap
 coordinate (workloads.TOY_N2).

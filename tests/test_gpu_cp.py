@@ -49,9 +49,10 @@ def test_cp_steps_follow_the_oracle(prec, tol):
 
 def test_cp_invariants_at_64_cubed():
     """64^3, 32 moving ions, 48 FP32 orbitals: the constraint keeps the
-    orbitals orthonormal to the accuracy of the FP32 overlap GEMMs (sums over
-    262144 points: measured 1.9e-4 after 21 steps) and E_CP stays put (the
-    FP32 Ehrenfest step drifts by about 1e-4 of E as well)."""
+    orbitals orthonormal to the accuracy of the FP32 overlaps (sums over
+    262144 points, partial sums added in FP64: measured 1.3e-7 after 21
+    steps) and E_CP stays put (the FP32 Ehrenfest step drifts by about 1e-4
+    of E as well)."""
     import torch
     from oracle import Model
     cfg = W.C5.replace(name="cp64", n_orb=48, freeze_ions=False, seed=515)
@@ -69,6 +70,35 @@ def test_cp_invariants_at_64_cubed():
     note(f"  max|S - I| {dev:.2e}  max|E - E0| {worst:.2e} of {abs(e0):.3e}")
     assert dev < 1e-3
     assert worst < 5e-4 * abs(e0)
+    s.close()
+
+
+def test_cp_invariants_at_the_benchmark_shape():
+    """96^3, 64 moving ions, 128 FP32 orbitals, mu_CP = 200, dt = 0.1844 (the
+    benchmark's CP leg): after 10 steps the orbitals are orthonormal to the
+    accuracy of the FP32 overlaps and E_CP has not moved beyond the FP32
+    step's own drift."""
+    import torch
+    cfg = W.C2
+    note("cp invariants 96^3 x 128 f32")
+    from paper_0812_2801_amd import binding as B
+    p, keep = B.params_from_config(cfg, W.ion_positions(cfg), precision="f32")
+    s = B.System(p, keep)
+    s.set_state(W.initial_orbitals_device(cfg, "cuda:0"))
+    s.cp_begin(200.0, 0.08 * 7.26 / 3.15)
+    e0 = s.cp_step(report=True)["e_total"]
+    worst, res = 0.0, 0.0
+    for _ in range(9):
+        rep = s.cp_step(report=True)
+        worst = max(worst, abs(rep["e_total"] - e0))
+        res = max(res, rep["cp_constraint_residual"])
+    psi = s.get_state().to(torch.complex128)
+    ov = cfg.h ** 3 * (psi.conj() @ psi.T)
+    dev = (ov - torch.eye(cfg.n_orb, dtype=torch.complex128, device=ov.device)).abs().max().item()
+    note(f"  max|S - I| {dev:.2e}  max|E - E0| {worst:.2e} of {abs(e0):.3e}  constraint residual {res:.1e}")
+    assert dev < 1e-3
+    assert worst < 5e-4 * abs(e0)
+    assert res < 1e-8
     s.close()
 
 
