@@ -453,6 +453,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
     ap.add_argument("--batch-only", action="store_true", help="run only the batched workload (profiling)")
     ap.add_argument("--no-cp", action="store_true", help="skip the Car-Parrinello comparison")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the finite-box and toy-model summaries of the default run")
     ap.add_argument("--cp-steps", type=int, default=20)
     ap.add_argument("--cp-series", action="store_true", help="add the system-size series of both schemes")
     ap.add_argument("--cp-only", action="store_true",
@@ -534,6 +536,17 @@ def main():
         print(f"# adjoint: forward {adj['forward_ms']:.1f} ms, backward {adj['backward_ms']:.1f} ms",
               file=sys.stderr, flush=True)
 
+    extras = {}
+    if not args.no_extras:
+        # the finite-box and toy-model studies, summarised; a failure there is
+        # recorded and does not cost the headline line
+        for key, fn in (("finite_box", lambda: run_finite(20)), ("toy_model", lambda: run_toy(not args.no_cpu))):
+            try:
+                extras[key] = fn()
+            except Exception as e:          # noqa: BLE001
+                extras[key] = {"error": f"{type(e).__name__}: {e}"}
+            print(f"# {key} done", file=sys.stderr, flush=True)
+
     cpu = None
     errors = {}
     if not args.no_cpu:
@@ -601,6 +614,12 @@ def main():
     if batch is not None:
         out["batched"] = batch
         out["batched_vs_single_system"] = batch["value"] / value
+    if "toy_model" in extras and "error" not in extras["toy_model"]:
+        t = extras["toy_model"]
+        extras["toy_model"] = {k: t[k] for k in ("workload", "cpu_oracle") if k in t}
+        for sch in ("ehrenfest", "cp"):
+            extras["toy_model"][sch] = {k: t[sch][k] for k in ("kernel_ms", "n_traj", "rk4_steps", "rk4_steps_per_s")}
+    out.update(extras)
     print(json.dumps(out))
 
 
