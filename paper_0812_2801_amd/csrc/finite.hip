@@ -96,44 +96,62 @@ __global__ void unpad_kernel(const double* __restrict__ rpad, int nx, int ny, in
     vh[i] = rpad[(z * 2 * ny + y) * 2 * nx + x];
 }
 
-// block b of FREE_FORCE_CHUNKS takes a contiguous range of points; each
-// block reduces its three components per ion in a fixed order
+// block b of FREE_FORCE_CHUNKS takes a contiguous range of points and
+// reads it once per group of FF_IONS ions, each thread keeping the group's
+// 3 * FF_IONS sums in registers; the block then reduces them in a fixed
+// order (wave shuffles, then the four waves in turn)
+constexpr int FF_IONS = 8;
+
 __global__ void __launch_bounds__(256) local_forces_free_kernel(const double* __restrict__ rho,
                                                                 const double* __restrict__ pos,
                                                                 const double* __restrict__ zval, int n_ions,
                                                                 int nx, int ny, int nz, double h, double a,
                                                                 double* __restrict__ part) {
-    __shared__ double red[3][256];
+    __shared__ double red[4][3 * FF_IONS];
     const int64_t N = (int64_t)nx * ny * nz;
     const int64_t per = (N + FREE_FORCE_CHUNKS - 1) / FREE_FORCE_CHUNKS;
     const int64_t i0 = (int64_t)blockIdx.x * per, i1 = i0 + per < N ? i0 + per : N;
     const double c = 2.0 / (a * sqrt(M_PI));
-    for (int J = 0; J < n_ions; ++J) {
-        const double X = pos[3 * J], Y = pos[3 * J + 1], Z = pos[3 * J + 2], q = zval[J];
-        double f[3] = {0.0, 0.0, 0.0};
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int J0 = 0; J0 < n_ions; J0 += FF_IONS) {
+        const int nj = n_ions - J0 < FF_IONS ? n_ions - J0 : FF_IONS;
+        double f[FF_IONS][3];
+#pragma unroll
+        for (int j = 0; j < FF_IONS; ++j) f[j][0] = f[j][1] = f[j][2] = 0.0;
         for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
             const double r = rho[i];
             if (r == 0.0) continue;
-            const double dx = X - h * (double)(i % nx);
-            const double dy = Y - h * (double)((i / nx) % ny);
-            const double dz = Z - h * (double)(i / ((int64_t)nx * ny));
-            const double d2 = dx * dx + dy * dy + dz * dz;
-            if (d2 == 0.0) continue;
-            const double d = sqrt(d2);
-            const double vp = q * (erf(d / a) / d2 - c * exp(-d2 / (a * a)) / d);
-            const double w = r * vp / d;
-            f[0] += w * dx;
-            f[1] += w * dy;
-            f[2] += w * dz;
+            const double x = h * (double)(i % nx), y = h * (double)((i / nx) % ny);
+            const double z = h * (double)(i / ((int64_t)nx * ny));
+#pragma unroll
+            for (int j = 0; j < FF_IONS; ++j) {
+                if (j >= nj) break;
+                const int J = J0 + j;
+                const double dx = pos[3 * J] - x, dy = pos[3 * J + 1] - y, dz = pos[3 * J + 2] - z;
+                const double d2 = dx * dx + dy * dy + dz * dz;
+                if (d2 == 0.0) continue;
+                const double d = sqrt(d2);
+                const double vp = zval[J] * (erf(d / a) / d2 - c * exp(-d2 / (a * a)) / d);
+                const double w = r * vp / d;
+                f[j][0] += w * dx;
+                f[j][1] += w * dy;
+                f[j][2] += w * dz;
+            }
         }
-        for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = f[k];
+#pragma unroll
+        for (int j = 0; j < FF_IONS; ++j)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                double v = f[j][k];
+                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+                if (lane == 0) red[wv][3 * j + k] = v;
+            }
         __syncthreads();
-        for (int st = 128; st > 0; st >>= 1) {
-            if ((int)threadIdx.x < st)
-                for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + st];
-            __syncthreads();
+        if ((int)threadIdx.x < 3 * nj) {
+            const int j = threadIdx.x / 3, k = threadIdx.x % 3;
+            part[((int64_t)(J0 + j) * FREE_FORCE_CHUNKS + blockIdx.x) * 3 + k] =
+                ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
         }
-        if (threadIdx.x < 3) part[((int64_t)J * FREE_FORCE_CHUNKS + blockIdx.x) * 3 + threadIdx.x] = red[threadIdx.x][0];
         __syncthreads();
     }
 }

@@ -296,6 +296,19 @@ elif scenario == "finite":
     p, keep = B.params_from_config(c, inp["pos"], precision=prec, finite_radius=6.0)
     size = ctypes.c_size_t(0)
     assert lib.me_workspace_size(ctypes.byref(p), ctypes.byref(size)) == B.ME_EINVAL     # box touches the faces
+    # more ions than one pass of the local-force kernel takes (groups of 8)
+    c10 = c.replace(name="f10", n_ions=10, ring_radius=1.6, finite_radius=2.6, seed=1010)
+    inp10 = W.make_inputs(c10)
+    m10 = finite.FiniteModel.from_config(c10, pos0=inp10["pos"], radius=c10.finite_radius)
+    h10 = new_system(c10, inp10)
+    psi10 = orbitals(c10, inp10)                     # held: the copy is asynchronous
+    ok(lib.me_set_state(h10, psi10.ctypes.data, c10.n_points), h10)
+    _, f10 = state(h10, c10)
+    want10 = m10.forces(inp10["pos"], inp10["psi"], m10.density(inp10["psi"]))["total"]
+    d10 = np.abs(f10 - want10.ravel()).max()
+    print(f"finite 10 ions: forces max|dF| {d10:.2e}", flush=True)
+    assert d10 <= TOL_F * max(1.0, np.abs(want10).max())
+    ok(lib.me_destroy(h10))
     # ETRS on the box: the corrections' v_Hxc comes from the free-space solve
     h = new_system(c, inp, etrs_iterations=1)
     ok(lib.me_set_state(h, psi.ctypes.data, c.n_points), h)

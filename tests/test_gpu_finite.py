@@ -109,3 +109,17 @@ def test_small_box_etrs():
         note(f"  step {n}: max|dpsi| {dpsi:.2e}")
         assert dpsi < 1e-10
     s.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_box_with_many_ions_forces(prec, tol):
+    # 20 ions on a ring: the local-force kernel takes the ions in groups of 8
+    cfg = W.F3.replace(name="ring20", n=56, h=0.4, n_ions=20, n_orb=8, ring_radius=4.0, finite_radius=4.5,
+                       seed=2020)
+    note(f"finite box {cfg.name}: {cfg.n_ions} ions {prec}")
+    s, m, _, inp = _pair(cfg, prec, oracle_state=False)
+    want = m.forces(inp["pos"], inp["psi"], m.density(inp["psi"]))["total"]
+    df = np.abs(s.forces() - want).max()
+    note(f"  forces max|dF| {df:.2e} (max|F| {np.abs(want).max():.2e})")
+    assert df < tol * max(1.0, np.abs(want).max())
+    s.close()
