@@ -26,13 +26,16 @@ def test_zero_corrections_is_aetrs():
 
 def test_density_independent_hamiltonian_gives_aetrs():
     # occupation 0: rho = 0, v_Hxc = 0 at every step, so the extrapolated and
-    # the self-consistent potentials coincide
-    m, st = _c1()
-    m = copy.copy(m)
+    # the self-consistent potentials coincide; with moving ions and a field,
+    # the corrected exponential must still use V_loc(R(t+dt)) and the field
+    c = W.C1.replace(freeze_ions=False)
+    inp = W.make_inputs(c)
+    m = Model.from_config(c)
     m.occ = 0.0
-    st = dynamics.init_state(m, st.psi, st.pos)
-    a = dynamics.aetrs_step(m, st)
-    e = dynamics.etrs_step(m, st, iterations=3)
+    st = dynamics.init_state(m, inp["psi"], inp["pos"])
+    a = dynamics.aetrs_step(m, st, 0.05)
+    e = dynamics.etrs_step(m, st, 0.05, iterations=3)
+    assert np.abs(a.pos - st.pos).max() > 1e-9          # the ions do move (heavy ions, short step)
     assert np.abs(a.psi - e.psi).max() < 1e-14
 
 
