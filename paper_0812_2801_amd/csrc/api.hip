@@ -498,6 +498,76 @@ me_status hartree_free(me_system* sys) {
     return ME_OK;
 }
 
+// Finite box (finite_radius > 0): doubled-grid FFT plans, the box mask at
+// the initial positions, the per-y-tile plane ranges of the Horner stages and
+// the spectrum of the Coulomb kernel.  On failure sys->err is set; the
+// caller destroys what was created.
+me_status finite_setup(me_system* sys, const me_params* p) {
+    // doubled-grid plans, the box mask at the initial positions and
+    // the spectrum of the Coulomb kernel (h^3 / (8N) folds in the
+    // inverse transform's normalisation and the quadrature weight)
+    const Geometry& g = sys->g;
+    size_t len2[3] = {(size_t)(2 * g.nx), (size_t)(2 * g.ny), (size_t)(2 * g.nz)};
+    if (rocfft_plan_create(&sys->r2c2, rocfft_placement_notinplace, rocfft_transform_type_real_forward,
+                           rocfft_precision_double, 3, len2, 1, nullptr) != rocfft_status_success ||
+        rocfft_plan_create(&sys->c2r2, rocfft_placement_notinplace, rocfft_transform_type_real_inverse,
+                           rocfft_precision_double, 3, len2, 1, nullptr) != rocfft_status_success) {
+        sys->err = "rocfft_plan_create failed (doubled grid)";
+        return ME_EDEVICE;
+    }
+    size_t v1 = 0, v2 = 0;
+    rocfft_plan_get_work_buffer_size(sys->r2c2, &v1);
+    rocfft_plan_get_work_buffer_size(sys->c2r2, &v2);
+    if (std::max(v1, v2) > g.fft_work2) {
+        sys->err = "rocFFT work buffer (doubled grid) larger than reserved";
+        return ME_EUNSUPPORTED;
+    }
+    if (rocfft_execution_info_create(&sys->info2) != rocfft_status_success ||
+        rocfft_execution_info_set_stream(sys->info2, sys->stream) != rocfft_status_success ||
+        (std::max(v1, v2) > 0 &&
+         rocfft_execution_info_set_work_buffer(sys->info2, sys->w.fft_work2, g.fft_work2) !=
+             rocfft_status_success)) {
+        sys->err = "rocfft execution info failed (doubled grid)";
+        return ME_EDEVICE;
+    }
+    HIPCHK(launch_box_mask(sys->w.pos, g.n_ions, g.nx, g.ny, g.nz, p->h, p->finite_radius, sys->w.mask,
+                           sys->stream));
+    // per y-tile plane range holding every box point of its rows (a
+    // superset: the chord of each sphere at the row, one plane of
+    // margin); the Horner stages march only there, so the stage
+    // buffers start at zero and stay zero outside the box
+    sys->zr_host.assign(g.nyt, make_int2(0, 0));
+    for (int t = 0; t < g.nyt; ++t) {
+        int lo = g.nz, hi = 0;
+        for (int y = t * g.ty; y < (t + 1) * g.ty; ++y)
+            for (int J = 0; J < g.n_ions; ++J) {
+                const double dy = y * p->h - sys->pos0[3 * J + 1];
+                const double rem = p->finite_radius * p->finite_radius - dy * dy;
+                if (rem < 0.0) continue;
+                const double c = std::sqrt(rem), Z = sys->pos0[3 * J + 2];
+                lo = std::min(lo, std::max(0, (int)std::floor((Z - c) / p->h) - 1));
+                hi = std::max(hi, std::min(g.nz, (int)std::ceil((Z + c) / p->h) + 2));
+            }
+        sys->zr_host[t] = make_int2(lo, std::max(lo, hi));
+    }
+    HIPCHK(hipMemcpyAsync(sys->w.zr, sys->zr_host.data(), (size_t)g.nyt * sizeof(int2), hipMemcpyHostToDevice,
+                           sys->stream));
+    const size_t ob = (size_t)g.n_orb * g.stride * g.bc;
+    HIPCHK(hipMemsetAsync(sys->w.bufA, 0, ob, sys->stream));
+    HIPCHK(hipMemsetAsync(sys->w.bufB, 0, ob, sys->stream));
+    HIPCHK(hipMemsetAsync(sys->w.rpad_in, 0, g.npad * 8, sys->stream));
+    HIPCHK(launch_green_doubled(g.nx, g.ny, g.nz, p->h, sys->w.rpad_out, sys->stream));
+    void* gi[1] = {sys->w.rpad_out};
+    void* go[1] = {sys->w.cpad};
+    if (rocfft_execute(sys->r2c2, gi, go, sys->info2) != rocfft_status_success) {
+        sys->err = "rocfft_execute failed (Coulomb kernel)";
+        return ME_EDEVICE;
+    }
+    HIPCHK(launch_green_spectrum(sys->w.cpad, g.nhalf2, p->h * p->h * p->h / (double)g.npad, sys->w.gk,
+                                 sys->stream));
+    return ME_OK;
+}
+
 // V_loc at positions `pos` (device) into `out` (+ the static potential).
 // Leaves the phase tables of `pos` in w.phase (periodic cube).
 me_status ion_fields(me_system* sys, const double* pos, double* out) {
@@ -1868,68 +1938,8 @@ me_status me_init_system(const me_params* p, void* workspace, size_t ws_bytes, v
             return fail(ME_EDEVICE);
         }
         if (sys->g.finite) {
-            // doubled-grid plans, the box mask at the initial positions and
-            // the spectrum of the Coulomb kernel (h^3 / (8N) folds in the
-            // inverse transform's normalisation and the quadrature weight)
-            const Geometry& g = sys->g;
-            size_t len2[3] = {(size_t)(2 * g.nx), (size_t)(2 * g.ny), (size_t)(2 * g.nz)};
-            if (rocfft_plan_create(&sys->r2c2, rocfft_placement_notinplace, rocfft_transform_type_real_forward,
-                                   rocfft_precision_double, 3, len2, 1, nullptr) != rocfft_status_success ||
-                rocfft_plan_create(&sys->c2r2, rocfft_placement_notinplace, rocfft_transform_type_real_inverse,
-                                   rocfft_precision_double, 3, len2, 1, nullptr) != rocfft_status_success) {
-                sys->err = "rocfft_plan_create failed (doubled grid)";
-                return fail(ME_EDEVICE);
-            }
-            size_t v1 = 0, v2 = 0;
-            rocfft_plan_get_work_buffer_size(sys->r2c2, &v1);
-            rocfft_plan_get_work_buffer_size(sys->c2r2, &v2);
-            if (std::max(v1, v2) > g.fft_work2) {
-                sys->err = "rocFFT work buffer (doubled grid) larger than reserved";
-                return fail(ME_EUNSUPPORTED);
-            }
-            if (rocfft_execution_info_create(&sys->info2) != rocfft_status_success ||
-                rocfft_execution_info_set_stream(sys->info2, sys->stream) != rocfft_status_success ||
-                (std::max(v1, v2) > 0 &&
-                 rocfft_execution_info_set_work_buffer(sys->info2, sys->w.fft_work2, g.fft_work2) !=
-                     rocfft_status_success)) {
-                sys->err = "rocfft execution info failed (doubled grid)";
-                return fail(ME_EDEVICE);
-            }
-            INITCHK(launch_box_mask(sys->w.pos, g.n_ions, g.nx, g.ny, g.nz, p->h, p->finite_radius, sys->w.mask,
-                                    sys->stream));
-            // per y-tile plane range holding every box point of its rows (a
-            // superset: the chord of each sphere at the row, one plane of
-            // margin); the Horner stages march only there, so the stage
-            // buffers start at zero and stay zero outside the box
-            sys->zr_host.assign(g.nyt, make_int2(0, 0));
-            for (int t = 0; t < g.nyt; ++t) {
-                int lo = g.nz, hi = 0;
-                for (int y = t * g.ty; y < (t + 1) * g.ty; ++y)
-                    for (int J = 0; J < g.n_ions; ++J) {
-                        const double dy = y * p->h - sys->pos0[3 * J + 1];
-                        const double rem = p->finite_radius * p->finite_radius - dy * dy;
-                        if (rem < 0.0) continue;
-                        const double c = std::sqrt(rem), Z = sys->pos0[3 * J + 2];
-                        lo = std::min(lo, std::max(0, (int)std::floor((Z - c) / p->h) - 1));
-                        hi = std::max(hi, std::min(g.nz, (int)std::ceil((Z + c) / p->h) + 2));
-                    }
-                sys->zr_host[t] = make_int2(lo, std::max(lo, hi));
-            }
-            INITCHK(hipMemcpyAsync(sys->w.zr, sys->zr_host.data(), (size_t)g.nyt * sizeof(int2), hipMemcpyHostToDevice,
-                                   sys->stream));
-            const size_t ob = (size_t)g.n_orb * g.stride * g.bc;
-            INITCHK(hipMemsetAsync(sys->w.bufA, 0, ob, sys->stream));
-            INITCHK(hipMemsetAsync(sys->w.bufB, 0, ob, sys->stream));
-            INITCHK(hipMemsetAsync(sys->w.rpad_in, 0, g.npad * 8, sys->stream));
-            INITCHK(launch_green_doubled(g.nx, g.ny, g.nz, p->h, sys->w.rpad_out, sys->stream));
-            void* gi[1] = {sys->w.rpad_out};
-            void* go[1] = {sys->w.cpad};
-            if (rocfft_execute(sys->r2c2, gi, go, sys->info2) != rocfft_status_success) {
-                sys->err = "rocfft_execute failed (Coulomb kernel)";
-                return fail(ME_EDEVICE);
-            }
-            INITCHK(launch_green_spectrum(sys->w.cpad, g.nhalf2, p->h * p->h * p->h / (double)g.npad, sys->w.gk,
-                                          sys->stream));
+            const me_status fs = finite_setup(sys, p);
+            if (fs != ME_OK) return fail(fs);
         }
 #undef INITCHK
         *out = sys;
