@@ -76,7 +76,7 @@ def test_toy_full_sweep(scheme):
     assert abs(got["dist"][0, 0] - r["dist"][k, m]) <= 1e-12 * max(1.0, r["dist"][k, m])
     # sampled trajectories of the sweep's shape against the oracle
     from paper_0812_2801_amd import binding as B
-    pick = mus[S["n_mu"] // 4::64]          # masses whose RK4 at this step is stable (omega dt < 1)
+    pick = mus[S["n_mu"] // 4::S["n_mu"] // 4]   # masses whose RK4 at this step is stable (omega dt < 1)
     t_s = r["t_total"] / S["n_samples"]
     win = [toy.window(toy.params(), scheme, float(x), t_s) for x in pick]
     o = T.run(P, scheme, pick, s, S["n_samples"], r["t_total"], window=win)

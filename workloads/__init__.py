@@ -118,11 +118,11 @@ CONFIGS = {"c1": C1, "c2": C2, "c4": C4, "c5": C5, "f3": F3}
 _M_N2 = 0.5 * 14.003074 * AMU_IN_ME
 TOY_N2 = dict(R0=1.09768 / 0.529177210903, M_R=_M_N2, K_R=_M_N2 * (2358.57 / 219474.6313632) ** 2,
               G0=0.30, M_G=_M_N2, K_G=20.0)
-# the sweep of Fig. 1 (c, d): four gsBO periods sampled 200 times; 256
+# the sweep of Fig. 1 (c, d): four gsBO periods sampled 200 times; 2048
 # log-spaced masses per scheme; RK4 substeps per sample on a 2^(1/3) ladder
 # from 128 down to 1 (the largest stable steps of these masses need 2 to 40),
 # below a reference of 512
-TOY_SWEEP = dict(periods=4.0, n_samples=200, n_mu=256, mu_ehrenfest=(0.02, 20.0), mu_cp=(2.0, 2000.0),
+TOY_SWEEP = dict(periods=4.0, n_samples=200, n_mu=2048, mu_ehrenfest=(0.02, 20.0), mu_cp=(2.0, 2000.0),
                  ladder_steps=28, finest=512, ratio=2 ** (1 / 3))
 
 
