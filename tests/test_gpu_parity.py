@@ -183,3 +183,21 @@ def test_invalid_arguments_return_codes():
     st = sysm.lib.me_apply_H(sysm.h, x.data_ptr(), x.data_ptr(), cfg.n_orb, cfg.n ** 3)
     assert st == B.ME_EINVAL
     sysm.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_single_orbital_steps(prec):
+    # one orbital: the 8-orbital contraction blocks, the norm partials and the
+    # density reduce over a single member
+    from oracle import dynamics
+    note(f"single orbital {prec}")
+    sysm, m, st, inp, cfg = make_pair(W.C1.replace(n_orb=1, seed=1901), precision=prec)
+    for _ in range(2):
+        sysm.step()
+        st = dynamics.aetrs_step(m, st)
+    psi = to_np(sysm.get_state()).reshape(st.psi.shape)
+    err = np.abs(psi - st.psi).max()
+    note(f"  max|dpsi| {err:.2e}")
+    assert err < (1e-10 if prec == "f64" else 1e-4)
+    assert np.abs(sysm.forces() - st.force).max() < (1e-9 if prec == "f64" else 1e-3)
+    sysm.close()

@@ -54,6 +54,8 @@ def test_toy_invalid_entries_and_arguments():
     d_R = out["d_R"].cpu().numpy()
     assert np.isfinite(d_R[0]) and np.isnan(d_R[1:]).all()
     assert np.isnan(out["samples"][:, :, 1:].cpu().numpy()).all()
+    empty = B.toy_run(p, "cp", [], [], [], 10, 100.0, max_substeps=1)      # no trajectories: nothing to do
+    assert empty["d_R"].numel() == 0 and tuple(empty["samples"].shape) == (11, 8, 0)
     with pytest.raises(B.ModehrError):
         B.toy_run(p, "ehrenfest", [1.0], [1], [1], 1 << 12, 100.0, max_substeps=1 << 13)
     with pytest.raises(B.ModehrError):
