@@ -87,6 +87,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with python -m paper_0812_2801_amd.build")
+    # torch first: it brings its own HIP runtime, rocFFT and rocBLAS under the
+    # same sonames, and the library must bind to those.  Loaded the other way
+    # round, the process maps two HIP runtimes (ROCm's and torch's), device
+    # memory from one is handed to the other, and rocFFT plans fail.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     for s in SYMBOLS:
         getattr(lib, s)

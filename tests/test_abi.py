@@ -134,3 +134,18 @@ def test_batch_validation_happens_on_the_host(lib):
     assert lib.me_init_batch(arr, 1, fake, 16, None, ctypes.byref(h)) == B.ME_ENOMEM
     assert lib.me_propagate_batch(None, 1, 1) == B.ME_EINVAL
     assert lib.me_batch_destroy(None) == B.ME_OK
+
+
+def test_one_hip_runtime_in_the_process():
+    # the library binds to the HIP runtime torch brought (same soname), so
+    # device memory and streams from torch are the library's own
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_0812_2801_amd import binding as B\n"
+            "B.load()\n"
+            "maps = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "print(len(maps))\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.strip().splitlines()[-1] == "1", out.stdout
