@@ -52,8 +52,9 @@ struct KbTables {
     int32_t* map;      // [N] slot of each grid point, or -1
     int32_t* pts;      // [ucap] grid index of each slot
     int32_t* cnt;      // [ucap] pairs per slot
-    int32_t* ion;      // [ucap][NL_KMAX]
-    void* pl;          // [ucap][NL_KMAX] projector values
+    int32_t* ion;      // [NL_KMAX][ucap]: pair k of slot s at k * ucap + s, so that
+                       // lanes on neighbouring slots read neighbouring words
+    void* pl;          // [NL_KMAX][ucap] projector values, the same layout
     int32_t* nslots;   // [1]
     int32_t* flag;     // [1] set when a point is covered by more than NL_KMAX spheres
     int32_t* blk;      // [scan blocks + 1] scratch of the slot numbering

@@ -166,7 +166,7 @@ template <typename T>
 __global__ void nl_fill_kernel(const int32_t* __restrict__ idx, const T* __restrict__ pv,
                                const int32_t* __restrict__ count, int kcap,
                                const int32_t* __restrict__ map, int32_t* __restrict__ cnt,
-                               int32_t* __restrict__ ion, T* __restrict__ pl,
+                               int32_t* __restrict__ ion, T* __restrict__ pl, int64_t ucap,
                                int32_t* __restrict__ flag) {
     const int J = blockIdx.y;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -175,8 +175,8 @@ __global__ void nl_fill_kernel(const int32_t* __restrict__ idx, const T* __restr
     const int s = map[idx[e]];
     const int pos = atomicAdd(&cnt[s], 1);
     if (pos < NL_KMAX) {
-        ion[(int64_t)s * NL_KMAX + pos] = J;
-        pl[(int64_t)s * NL_KMAX + pos] = pv[e];
+        ion[pos * ucap + s] = J;
+        pl[pos * ucap + s] = pv[e];
     } else {
         atomicOr(flag, 1);
     }
@@ -184,13 +184,18 @@ __global__ void nl_fill_kernel(const int32_t* __restrict__ idx, const T* __restr
 
 template <typename T>
 __global__ void nl_sort_kernel(const int32_t* __restrict__ nslots, int32_t* __restrict__ cnt,
-                               int32_t* __restrict__ ion, T* __restrict__ pl) {
+                               int32_t* __restrict__ ion, T* __restrict__ pl, int64_t ucap) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= *nslots) return;
     const int n = min(cnt[s], NL_KMAX);
     cnt[s] = n;
-    int32_t* ji = ion + (int64_t)s * NL_KMAX;
-    T* jp = pl + (int64_t)s * NL_KMAX;
+    // the slot's pairs into registers, insertion sort by ion, back
+    int ji[NL_KMAX];
+    T jp[NL_KMAX];
+    for (int i = 0; i < n; ++i) {
+        ji[i] = ion[i * ucap + s];
+        jp[i] = pl[i * ucap + s];
+    }
     for (int i = 1; i < n; ++i) {
         const int kj = ji[i];
         const T kp = jp[i];
@@ -202,6 +207,10 @@ __global__ void nl_sort_kernel(const int32_t* __restrict__ nslots, int32_t* __re
         }
         ji[j + 1] = kj;
         jp[j + 1] = kp;
+    }
+    for (int i = 0; i < n; ++i) {
+        ion[i * ucap + s] = ji[i];
+        pl[i * ucap + s] = jp[i];
     }
 }
 
@@ -222,9 +231,9 @@ hipError_t launch_kb_tables(const double* pos, int n_ions, int nx, int ny, int n
     nl_scan_blocks_kernel<<<1, 256, 0, s>>>(t.blk, (int)nblk, t.nslots);
     nl_number_kernel<<<(unsigned)nblk, 256, 0, s>>>(t.map, N, t.blk, t.pts);
     nl_fill_kernel<T><<<eg, 256, 0, s>>>(t.idx, reinterpret_cast<const T*>(t.p), t.count, t.kcap, t.map,
-                                         t.cnt, t.ion, reinterpret_cast<T*>(t.pl), t.flag);
+                                         t.cnt, t.ion, reinterpret_cast<T*>(t.pl), t.ucap, t.flag);
     nl_sort_kernel<T><<<(unsigned)((t.ucap + 255) / 256), 256, 0, s>>>(t.nslots, t.cnt, t.ion,
-                                                                       reinterpret_cast<T*>(t.pl));
+                                                                       reinterpret_cast<T*>(t.pl), t.ucap);
     return hipGetLastError();
 }
 
@@ -239,7 +248,7 @@ __global__ void __launch_bounds__(256) kb_fixup_kernel(cx_t<T>* __restrict__ out
                                                        const int32_t* __restrict__ pts,
                                                        const int32_t* __restrict__ cnt,
                                                        const int32_t* __restrict__ ion,
-                                                       const T* __restrict__ pl,
+                                                       const T* __restrict__ pl, int64_t ucap,
                                                        const cx_t<T>* __restrict__ cnl, T gr, T gi,
                                                        double* __restrict__ dnorm) {
     __shared__ double red[4][FIX_OB];
@@ -256,8 +265,8 @@ __global__ void __launch_bounds__(256) kb_fixup_kernel(cx_t<T>* __restrict__ out
         int jj[NL_KMAX];
         T ww[NL_KMAX];
         for (int k = 0; k < n; ++k) {
-            jj[k] = ion[(int64_t)s * NL_KMAX + k];
-            ww[k] = pl[(int64_t)s * NL_KMAX + k];
+            jj[k] = ion[k * ucap + s];
+            ww[k] = pl[k * ucap + s];
         }
 #pragma unroll
         for (int j = 0; j < FIX_OB; ++j) {
@@ -301,7 +310,7 @@ hipError_t launch_kb_fixup(cx_t<T>* out, int64_t stride, int n_orb, KbTables t,
                            const cx_t<T>* cnl, double gr, double gi, double* dnorm, hipStream_t s) {
     dim3 grid(fixup_blocks(t.ucap), (n_orb + FIX_OB - 1) / FIX_OB);
     kb_fixup_kernel<T><<<grid, 256, 0, s>>>(out, stride, n_orb, t.nslots, t.pts, t.cnt, t.ion,
-                                            reinterpret_cast<const T*>(t.pl), cnl, (T)gr, (T)gi, dnorm);
+                                            reinterpret_cast<const T*>(t.pl), t.ucap, cnl, (T)gr, (T)gi, dnorm);
     return hipGetLastError();
 }
 
