@@ -26,7 +26,7 @@ the cost of one atomic unit of simulated time for both schemes.
 ``--cp-series`` adds the system-size series (grids 48^3 to 128^3, orbitals
 and ions in proportion to the volume) behind the cost crossover.
 
-Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus N > 1 is refused: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 

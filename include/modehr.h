@@ -63,7 +63,7 @@ typedef enum {
     ME_EDEVICE = 3,       /* HIP or rocFFT error (text in me_last_error) */
     ME_ESTATE = 4,        /* call before me_set_state, or wrong mode */
     ME_EUNSTABLE = 5,     /* an orbital norm grew or became non-finite */
-    ME_EUNSUPPORTED = 6   /* valid request this build does not support (e.g. a grid
+    ME_EUNSUPPORTED = 6   /* valid request the library does not support (e.g. a grid
                              point inside more than 8 projector spheres) */
 } me_status;
 
