@@ -142,7 +142,12 @@ typedef struct {
  * Pure host computation. */
 me_status me_workspace_size(const me_params* p, size_t* bytes);
 
-/* Create a system.  workspace: caller-owned device memory of at least
+/* Create a system: the periodic real-space grid (sec. 5), the local ionic
+ * potential of eq. (ionicpotential) and the Gaussian Kleinman-Bylander
+ * projectors at R(0), i.e. every part of H of eq. (new_EoM(a)) that does not
+ * depend on the orbitals (sec. 5.1: given phi(0) and R(0), compute phi(t) and
+ * R(t); the orbitals follow with me_set_state).
+ * workspace: caller-owned device memory of at least
  * me_workspace_size bytes, 256-byte aligned, untouched by the caller until
  * me_destroy.  stream: hipStream_t (as void*) all work is enqueued on.
  * Validates p (ME_EINVAL), checks ws_bytes (ME_ENOMEM), uploads the ion data
@@ -188,11 +193,16 @@ me_status me_propagate_step(me_system* sys, const double* ctrl, me_step_report* 
 /* Diagnostics of the current state (synchronises). */
 me_status me_report(me_system* sys, me_step_report* rep);
 
-/* rho_dev[N] = f sum_A |psi_A|^2 of the current state, FP64, device. */
+/* The electronic density of eq. (density), rho = f sum_A |psi_A|^2 with
+ * f = occ (2 for the closed shell of the paper), of the current state:
+ * rho_dev[N], FP64, device, caller-owned. */
 me_status me_density(me_system* sys, double* rho_dev);
 
-/* f_host[3*n_ions] = total force on each ion at the current state, FP64,
- * host (synchronises). */
+/* The ionic forces of eq. (new_EoM(b)), F_J = -dE_KS/dR_J at fixed orbitals
+ * (eq. ionicforces read as the derivative of the discrete energy: local part
+ * by the G-space sum, nonlocal part from the projector coefficients, ion-ion
+ * part by Ewald), at the current state: f_host[3*n_ions], FP64, host,
+ * caller-owned (synchronises). */
 me_status me_forces(me_system* sys, double* f_host);
 
 /* Current ion positions and velocities, host, [n_ions][3] each; either may be

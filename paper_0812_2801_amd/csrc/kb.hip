@@ -1,7 +1,7 @@
 // Gaussian s-channel Kleinman-Bylander projector: per-ion point tables,
 // the contraction c_JA = h^3 sum_k p_J(r_k) psi_A(r_k) and the nonlocal
-// forces / energy.  The scatter E_KB sum_J p_J c_JA is fused into the
-// stencil kernel.
+// forces / energy.  The scatter E_KB sum_J p_J c_JA is added at the
+// projector points by kb_fixup_kernel after each stencil pass.
 #include "common.hpp"
 #include "geometry.hpp"
 
