@@ -96,14 +96,22 @@ class Model:
         return self.grid.dv * np.sum(np.abs(psi.reshape(psi.shape[0], -1)) ** 2, axis=1)
 
     # ------------------------------------------------------------ energy
+    def kinetic_sum(self, psi: np.ndarray) -> float:
+        """sum over the given orbitals and points of Re(conj(psi) T psi)."""
+        return float(np.sum(np.real(np.conj(psi) * self.grid.kinetic(psi))))
+
     def energy(self, pos: np.ndarray, psi: np.ndarray, rho: Optional[np.ndarray] = None,
-               vloc: Optional[np.ndarray] = None) -> dict:
+               vloc: Optional[np.ndarray] = None, kin_sum: Optional[float] = None) -> dict:
+        """kin_sum: kinetic_sum(psi) when already known (e.g. summed over
+        chunks of orbitals)."""
         g = self.grid
         if rho is None:
             rho = self.density(psi)
         if vloc is None:
             vloc = self.vloc(pos)
-        ekin = self.occ * g.dv * float(np.sum(np.real(np.conj(psi) * g.kinetic(psi))))
+        if kin_sum is None:
+            kin_sum = self.kinetic_sum(psi)
+        ekin = self.occ * g.dv * kin_sum
         eloc = g.dv * float(np.sum(rho * vloc))
         vh = potentials.hartree(g, rho)
         eh = potentials.hartree_energy(g, rho, vh)
@@ -118,11 +126,14 @@ class Model:
         return parts
 
     # ------------------------------------------------------------ forces
-    def forces(self, pos: np.ndarray, psi: np.ndarray, rho: np.ndarray, nl_form: str = "projector") -> dict:
+    def forces(self, pos: np.ndarray, psi: np.ndarray, rho: np.ndarray, nl_form: str = "projector",
+               floc: Optional[np.ndarray] = None) -> dict:
         """Hellmann-Feynman forces; nl_form "gradient" takes the nonlocal part
-        in the wave-function-gradient form (kb.force_columns_gradient)."""
+        in the wave-function-gradient form (kb.force_columns_gradient).
+        floc: the local-potential forces when already known."""
         g = self.grid
-        floc = potentials.local_forces(g, pos, self.zval, self.loc_a, rho)
+        if floc is None:
+            floc = potentials.local_forces(g, pos, self.zval, self.loc_a, rho)
         sph = self.spheres(pos)
         c = kb.contract(g, sph, psi)
         if nl_form == "gradient":

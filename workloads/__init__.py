@@ -310,6 +310,96 @@ def initial_orbitals_device(cfg: Config, device="cuda:0", chunk: int = 16):
     return x.T.contiguous() @ flat
 
 
+# ---------------------------------------------------------------- per-orbital streams
+# The same recipe as initial_orbitals, but each orbital draws its fields from
+# a stream of its own (child a of SeedSequence([seed, 4321])), so that any
+# machine can draw any subset of the orbitals, in parallel, bit for bit.
+# Used where the orbital set is too large for one sequential stream (the
+# 128^3 x 432 precision workload, whose FP64 oracle reference is computed on
+# one machine and compared on another).
+
+def _orbital_seeds(cfg: Config):
+    return np.random.SeedSequence([cfg.seed, 4321]).spawn(cfg.n_orb)
+
+
+def orbital_fields(cfg: Config, a0: int, a1: int, threads: int = 16) -> np.ndarray:
+    """The raw N(0,1) fields of orbitals a0..a1-1: float64 [a1-a0, 2, n, n, n]
+    (real and imaginary parts), each orbital from its own stream."""
+    import concurrent.futures as cf
+    n = cfg.n
+    seeds = _orbital_seeds(cfg)[a0:a1]
+    out = np.empty((a1 - a0, 2, n, n, n))
+
+    def draw(i):
+        np.random.default_rng(seeds[i]).standard_normal(out=out[i])
+
+    with cf.ThreadPoolExecutor(max(1, min(threads, a1 - a0))) as ex:
+        list(ex.map(draw, range(a1 - a0)))
+    return out
+
+
+def loewdin_matrix(s: np.ndarray) -> np.ndarray:
+    """S^(-1/2) of a Hermitian positive overlap matrix (FP64)."""
+    s = 0.5 * (s + s.conj().T)
+    w, v = np.linalg.eigh(s)
+    return (v * (1.0 / np.sqrt(w))) @ v.conj().T
+
+
+def initial_orbitals_streamed(cfg: Config, out: Optional[np.ndarray] = None,
+                              chunk: int = 8) -> np.ndarray:
+    """[n_orb, n, n, n] complex128 (into `out` when given): per-orbital
+    streams, smoothing exp(-(|G| h)^2), normalisation, one Loewdin step."""
+    import scipy.fft as sfft
+    n, h, no = cfg.n, cfg.h, cfg.n_orb
+    psi = np.empty((no, n, n, n), dtype=np.complex128) if out is None else out
+    filt = _gsq_smoothing(n, h)
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    h3 = h ** 3
+    for a0 in range(0, no, chunk):
+        a1 = min(no, a0 + chunk)
+        f = orbital_fields(cfg, a0, a1)
+        for i in range(a1 - a0):
+            z = f[i, 0] + 1j * f[i, 1]
+            z = sfft.ifftn(sfft.fftn(z, workers=workers) * filt, workers=workers)
+            z /= math.sqrt(h3 * float(np.vdot(z, z).real))
+            psi[a0 + i] = z
+    flat = psi.reshape(no, -1)
+    s = np.zeros((no, no), dtype=np.complex128)
+    step = 1 << 16
+    for i0 in range(0, flat.shape[1], step):
+        blk = flat[:, i0:i0 + step]
+        s += blk.conj() @ blk.T
+    xt = np.ascontiguousarray(loewdin_matrix(h3 * s).T)
+    for i0 in range(0, flat.shape[1], step):
+        flat[:, i0:i0 + step] = xt @ flat[:, i0:i0 + step]
+    return psi
+
+
+def initial_orbitals_streamed_device(cfg: Config, device="cuda:0", chunk: int = 16):
+    """initial_orbitals_streamed with the fields drawn on the host (the same
+    bits) and the smoothing, normalisation and Loewdin step done by torch on
+    `device` in FP64.  Returns [n_orb, n^3] complex128 on `device`."""
+    import torch
+    n, h, no = cfg.n, cfg.h, cfg.n_orb
+    dev = torch.device(device)
+    filt = torch.from_numpy(_gsq_smoothing(n, h)).to(dev)
+    h3 = h ** 3
+    psi = torch.empty((no, n, n, n), dtype=torch.complex128, device=dev)
+    for a0 in range(0, no, chunk):
+        a1 = min(no, a0 + chunk)
+        f = torch.from_numpy(orbital_fields(cfg, a0, a1)).to(dev)
+        z = torch.complex(f[:, 0], f[:, 1])
+        del f
+        z = torch.fft.ifftn(torch.fft.fftn(z, dim=(1, 2, 3)) * filt, dim=(1, 2, 3))
+        nrm = (z.abs() ** 2).sum(dim=(1, 2, 3)) * h3
+        psi[a0:a1] = z / nrm.sqrt()[:, None, None, None]
+        del z
+    flat = psi.reshape(no, -1)
+    s = h3 * (flat.conj() @ flat.T)
+    x = torch.from_numpy(loewdin_matrix(s.cpu().numpy())).to(dev)
+    return x.T.contiguous() @ flat
+
+
 def controls(cfg: Config, rng: Optional[np.random.Generator] = None,
              steps: Optional[int] = None) -> np.ndarray:
     """Per-step control amplitudes eps_n, float64 [steps]."""
