@@ -255,6 +255,28 @@ me_status me_adjoint_step(me_system* sys, double ctrl_n, double* g_ctrl_n);
  * transpose of the trilinear interpolation on an m^3 grid (g_coarse_dev). */
 me_status me_adjoint_grad_v(me_system* sys, double* g_fine_dev, double* g_coarse_dev, int32_t m);
 
+/* ------------------------------------------------- no device allocation
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The dipole
+ * of me_dipole, d = h^3 sum_i (h*ix_i - L/2) rho_i with L = n[0] h and ix_i
+ * the x index of point i, of a caller's density rho_dev[n[0]*n[1]*n[2]]
+ * (FP64, device, x fastest; caller-owned), written to d_dev[0] (device,
+ * caller-owned) on `stream` (a hipStream_t of the current device, as void*;
+ * NULL = default stream).  Asynchronous: no synchronisation, no allocation.
+ * The per-workgroup partial sums (one per 256 points) live in a fixed array
+ * of ME_NOALLOC_MAX_PARTS doubles (2 MiB) that the library holds on every GPU
+ * it runs on until the process ends; its address is taken on the first call
+ * on each device.  The sum runs in the fixed order of me_dipole, so both
+ * give the same bits for the same density.  All calls on one GPU share the
+ * array: calls that overlap on one GPU (other streams, other host threads)
+ * race.  Errors: ME_EINVAL for NULL pointers, a size below 1, h <= 0 or more
+ * than 256 * ME_NOALLOC_MAX_PARTS points (nothing launched); ME_EDEVICE if
+ * the array's address cannot be taken or the launch fails.  The text is in
+ * me_last_error(NULL). */
+#define ME_NOALLOC_MAX_PARTS 262144
+me_status me_dipole_noalloc(const double* rho_dev, const int32_t n[3], double h, double* d_dev,
+                            void* stream);
+
 /* ------------------------------------------------------- Car-Parrinello
  * The comparison scheme of sec. 3 (eq. L_CP, eq. EoM_CP): orbitals with a
  * fictitious mass mu_cp and orthonormality kept by Lagrange multipliers,

@@ -31,7 +31,7 @@ SYMBOLS = [
     "me_batch_workspace_size", "me_init_batch", "me_batch_system", "me_batch_set_tuning",
     "me_batch_get_tuning", "me_batch_autotune", "me_propagate_batch", "me_batch_timing_enable",
     "me_batch_timing_read", "me_batch_last_error", "me_batch_destroy",
-    "me_toy_run", "me_toy_distance",
+    "me_toy_run", "me_toy_distance", "me_dipole_noalloc",
 ]
 
 
@@ -123,6 +123,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.me_load_checkpoint.argtypes = [c_void_p, c_void_p]
     lib.me_set_static_potential_coarse.argtypes = [c_void_p, c_void_p, c_int32]
     lib.me_dipole.argtypes = [c_void_p, POINTER(c_double)]
+    lib.me_dipole_noalloc.argtypes = [c_void_p, POINTER(c_int32), c_double, c_void_p, c_void_p]
     lib.me_adjoint_begin.argtypes = [c_void_p, c_void_p]
     lib.me_adjoint_step.argtypes = [c_void_p, c_double, POINTER(c_double)]
     lib.me_adjoint_grad_v.argtypes = [c_void_p, c_void_p, c_void_p, c_int32]
@@ -548,3 +549,21 @@ def toy_distance(samples, ref):
     if st != ME_OK:
         raise ModehrError(st, lib.me_last_error(None).decode())
     return dist
+
+
+# ------------------------------------------------------------- no allocation
+def dipole_noalloc(rho, n, h: float, out):
+    """me_dipole_noalloc: out[0] = h^3 sum (h*ix - L/2) rho for a device FP64
+    density rho (n = (n_x, n_y, n_z), x fastest) into the device FP64 tensor
+    out, on torch's current stream, without allocating or synchronising."""
+    import torch
+    lib = load()
+    if rho.dtype != torch.float64 or out.dtype != torch.float64 or not rho.is_contiguous():
+        raise ValueError("rho must be contiguous float64 and out float64")
+    n3 = (c_int32 * 3)(*[int(v) for v in n])
+    stream = torch.cuda.current_stream(rho.device).cuda_stream
+    st = lib.me_dipole_noalloc(c_void_p(rho.data_ptr()), n3, c_double(h), c_void_p(out.data_ptr()),
+                               c_void_p(stream))
+    if st != ME_OK:
+        raise ModehrError(st, lib.me_last_error(None).decode())
+    return out

@@ -30,6 +30,14 @@ namespace {
 
 thread_local std::string g_init_error;
 
+}  // namespace
+
+// error text of a call without a handle (me_last_error(NULL)), for the other
+// source files of the library
+void me::set_thread_error(const std::string& text) { g_init_error = text; }
+
+namespace {
+
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 struct Carver {

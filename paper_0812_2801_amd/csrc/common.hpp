@@ -5,7 +5,12 @@
 #include <cstdint>
 #include <cstddef>
 
+#include <string>
+
 namespace me {
+
+// text returned by me_last_error(NULL) on this thread (calls without a handle)
+void set_thread_error(const std::string& text);
 
 // complex element type of each precision: interleaved (re, im)
 template <typename T> struct cx;

@@ -356,6 +356,42 @@ elif scenario == "toy":
     assert lib.me_toy_run(ctypes.byref(bad), 0, 1, ns, T, 1, dp(z), dp(z), dp(z), None, dp(z), dp(z), stream) == B.ME_EINVAL
     assert lib.me_toy_run(ctypes.byref(tp), 0, 1, 1 << 12, T, 1 << 13, dp(z), dp(z), dp(z), None, dp(z), dp(z),
                           stream) == B.ME_EINVAL
+elif scenario == "noalloc":
+    # the dipole with its partials in the library's fixed array: the same
+    # bits as me_dipole on a system's density, then a smaller, non-cubic
+    # density against the oracle's objective, then the refusals
+    c = W.C1.replace(n=20, n_orb=3, seed=1201)
+    inp = W.make_inputs(c)
+    h = new_system(c, inp)
+    psi0 = orbitals(c, inp)
+    held.append(psi0)                        # the copy runs when the stream does
+    ok(lib.me_set_state(h, psi0.ctypes.data, c.n_points), h)
+    rho = np.zeros(c.n_points)
+    ok(lib.me_density(h, rho.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), h)
+    ok(lib.me_sync(h), h)
+    d_sys = ctypes.c_double(0.0)
+    ok(lib.me_dipole(h, ctypes.byref(d_sys)), h)
+    d_dev = np.full(1, np.nan)
+    n3 = (ctypes.c_int32 * 3)(c.n, c.n, c.n)
+    ok(lib.me_dipole_noalloc(ctypes.c_void_p(rho.ctypes.data), n3, c.h, ctypes.c_void_p(d_dev.ctypes.data), stream))
+    ok(lib.me_sync(h), h)
+    print(f"noalloc {c.n}^3: {d_dev[0]!r} me_dipole {d_sys.value!r}", flush=True)
+    assert d_dev[0] == d_sys.value
+    ok(lib.me_destroy(h))
+    m = Model(n=c.n, h=c.h, zval=np.zeros(0), mass=np.zeros(0))
+    assert abs(d_dev[0] - adjoint.objective(m, rho.reshape(c.n, c.n, c.n))) < 1e-12 * abs(d_dev[0])
+    rng = np.random.default_rng(5)
+    small = rng.random((7, 10, 12))          # (z, y, x): n = (12, 10, 7)
+    n3s = (ctypes.c_int32 * 3)(12, 10, 7)
+    ok(lib.me_dipole_noalloc(ctypes.c_void_p(small.ctypes.data), n3s, 0.3, ctypes.c_void_p(d_dev.ctypes.data), stream))
+    want = 0.3 ** 3 * float(np.sum((0.3 * np.arange(12) - 0.5 * 12 * 0.3)[None, None, :] * small))
+    print(f"noalloc 12x10x7: {d_dev[0]!r} want {want!r}", flush=True)
+    assert abs(d_dev[0] - want) < 1e-13 * max(1.0, abs(want))
+    big = (ctypes.c_int32 * 3)(1024, 1024, 1024)
+    assert lib.me_dipole_noalloc(ctypes.c_void_p(small.ctypes.data), big, 0.3, ctypes.c_void_p(d_dev.ctypes.data),
+                                 stream) == B.ME_EINVAL
+    assert b"too large" in lib.me_last_error(None)
+    assert lib.me_dipole_noalloc(None, n3s, 0.3, ctypes.c_void_p(d_dev.ctypes.data), stream) == B.ME_EINVAL
 else:
     raise SystemExit(f"unknown scenario {scenario}")
 

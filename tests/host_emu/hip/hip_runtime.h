@@ -20,7 +20,9 @@
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __shared__ static
-#define __align__(n) alignas(n)
+#define __align__(n) __attribute__((aligned(n)))
+// a __device__ variable is host storage here: its address is the symbol's own
+#define HIP_SYMBOL(x) (&(x))
 
 typedef enum {
     hipSuccess = 0,
@@ -162,6 +164,10 @@ hipError_t hipMemcpy2DAsync(void*, size_t, const void*, size_t, size_t, size_t, 
 hipError_t hipMemcpy(void*, const void*, size_t, hipMemcpyKind);
 hipError_t hipMemsetAsync(void*, int, size_t, hipStream_t);
 hipError_t hipGetDevice(int*);
+inline hipError_t hipGetSymbolAddress(void** p, const void* sym) {
+    *p = const_cast<void*>(sym);
+    return hipSuccess;
+}
 hipError_t hipDeviceGetAttribute(int*, hipDeviceAttribute_t, int);
 hipError_t hipGetLastError();
 const char* hipGetErrorString(hipError_t);

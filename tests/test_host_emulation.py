@@ -24,7 +24,7 @@ ASAN_RT = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asa
 
 SCENARIOS = [("system", "f64"), ("system", "f32"), ("system", "f32_bf16x3"), ("batch", "f64"),
              ("batch", "f32"), ("adjoint", "f64"), ("adjoint", "f32"), ("cp", "f64"), ("cp", "f32"),
-             ("etrs", "f64"), ("toy", "f64"), ("finite", "f64"), ("finite", "f32")]
+             ("etrs", "f64"), ("toy", "f64"), ("finite", "f64"), ("finite", "f32"), ("noalloc", "f64")]
 
 pytestmark = pytest.mark.skipif(not (os.path.exists(CLANG) and ASAN_RT), reason="needs ROCm clang++ and its ASan runtime")
 
