@@ -309,6 +309,11 @@ me_status me_cp_step(me_system* sys, me_step_report* rep);
 me_status me_timing_enable(me_system* sys, int32_t enable);
 me_status me_timing_read(me_system* sys, int64_t* launches, double* total_ms,
                          double* total_bytes);
+/* The same for one kind of Horner stage: streams = 2 the first stage of each
+ * exponential (reads u = psi, writes the stage), 3 the others (read u and
+ * psi, write the stage), 0 all of them (= me_timing_read). */
+me_status me_timing_read_kind(me_system* sys, int32_t streams, int64_t* launches, double* total_ms,
+                              double* total_bytes);
 
 /* Text of the last error on this handle ("" if none).  NULL sys gives the
  * last error of a failed me_init_system on this thread. */
@@ -321,17 +326,21 @@ const char* me_strerror(me_status s);
  * control field) for every system; every orbital of every system is
  * independent inside the two Taylor exponentials of eq. (aetrs), so each of
  * their Horner stages runs as ONE persistent stencil launch over all
- * systems, whose workgroups pull (system, orbital, y-tile, z-slab) work items
- * from per-XCD device queues.  All systems share one stream and must share
- * the precision and the Taylor order; grids are limited to 192 points per
- * row; at most 32 systems.  The adjoint is not available on batched systems.
+ * systems, whose workgroups pull (system, orbital, x-tile, y-tile, z-slab)
+ * work items from per-XCD device queues.  A system whose whole x-rows do not
+ * fit the workgroup runs in x-tiles of 64 points (x-halo in LDS).  All
+ * systems share one stream and must share the precision and the Taylor
+ * order; at most 32 systems.  The adjoint is not available on batched
+ * systems.
  */
 typedef struct me_batch me_batch;
 
 /* Launch shape of the persistent stencil. */
 typedef struct {
     int32_t block;        /* threads per workgroup: multiple of 64 in [64, 1024];
-                             each system's tile is floor(block / n_x) rows */
+                             each system's tile is floor(block / n_x) whole rows,
+                             or floor(block / 64) rows of 64-point x-tiles when
+                             8 n_x > 2 block */
     int32_t wg_per_cu;    /* resident workgroups per compute unit (grid = this x CUs) */
     int32_t zdiv;         /* z-slabs per orbital column: 1, 2 or 4 */
     double stage_ms;      /* autotuner: measured time of one Horner stage over the
@@ -354,7 +363,8 @@ me_status me_init_batch(const me_params* ps, int32_t n_sys, void* workspace_dev,
 me_status me_batch_system(me_batch* b, int32_t i, me_system** out);
 
 /* Sets or reads the launch shape.  ME_EINVAL if it does not fit a system
- * (8 n_x > 2 block, LDS over 64 KiB) or wg_per_cu exceeds what is resident. */
+ * (the halo jobs of an x-tile, 8 (64 + rows), over 2 block; LDS over 64 KiB)
+ * or wg_per_cu exceeds what is resident. */
 me_status me_batch_set_tuning(me_batch* b, const me_batch_tuning* t);
 me_status me_batch_get_tuning(const me_batch* b, me_batch_tuning* t);
 

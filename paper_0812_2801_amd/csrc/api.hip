@@ -94,6 +94,7 @@ struct Geometry {
     size_t bc;        // bytes per complex
     size_t br;        // bytes per real of the compute precision
     int px, ty, nyt, zchunk, nzc;
+    int tx, nxt;       // stencil tile width (nx: whole rows) and x-tiles
     int64_t norm_cap;  // norm partials per orbital (this kernel's tiles, or a batch's)
     int kcap;
     int64_t ucap;      // upper bound of projector-covered grid points
@@ -145,6 +146,33 @@ int choose_ty(int nx, int ny, int px, size_t bc) {
     for (int ty : {16, 8, 4, 2, 1})
         if (ok(ty)) return ty;
     return -1;
+}
+
+// Stencil tile: whole x-rows (choose_ty) up to 96 points per row in FP32;
+// wider rows take x-tiles of 64 points and 12 rows (768 threads, an x-halo of
+// 4 + 4 points in LDS), which keeps the y-halo at 8 rows per 12 instead of 8
+// per 4.  MODEHR_TX / MODEHR_TY select another compiled shape (64x12, 48x16,
+// 32x24, 16x8) or, with MODEHR_TX=0, whole rows (measurements and tests).
+void choose_tile(int nx, int ny, int px, size_t bc, int* tx, int* ty) {
+    const char* ev = std::getenv("MODEHR_TX");
+    if (ev && *ev) {
+        const int ftx = std::atoi(ev);
+        if (ftx > 0 && ftx < nx) {
+            *tx = ftx;
+            *ty = env_int("MODEHR_TY", 12);
+            return;
+        }
+        *tx = nx;
+        *ty = choose_ty(nx, ny, px, bc);
+        return;
+    }
+    if (bc == 8 && nx > 96) {
+        *tx = 64;
+        *ty = 12;
+        return;
+    }
+    *tx = nx;
+    *ty = choose_ty(nx, ny, px, bc);
 }
 
 int choose_zchunk(int nz, int64_t base_blocks) {
@@ -215,11 +243,12 @@ Geometry make_geometry(const me_params* p) {
     g.bc = g.f64 ? 16 : 8;
     g.br = g.f64 ? 8 : 4;
     g.px = choose_px(g.nx, g.f64);
-    g.ty = choose_ty(g.nx, g.ny, g.px, g.bc);
-    g.nyt = g.ny / g.ty;
-    g.zchunk = choose_zchunk(g.nz, (int64_t)g.n_orb * g.nyt);
+    choose_tile(g.nx, g.ny, g.px, g.bc, &g.tx, &g.ty);
+    g.nxt = (g.nx + g.tx - 1) / g.tx;
+    g.nyt = (g.ny + g.ty - 1) / g.ty;
+    g.zchunk = choose_zchunk(g.nz, (int64_t)g.n_orb * g.nxt * g.nyt);
     g.nzc = g.nz / g.zchunk;
-    g.norm_cap = std::max<int64_t>((int64_t)g.nyt * g.nzc, 4 * (int64_t)g.ny);
+    g.norm_cap = std::max<int64_t>((int64_t)g.nxt * g.nyt * g.nzc, 4 * (int64_t)g.ny);
     const int m = (int)std::ceil(p->kb_rcut / p->h);
     g.m = m;
     int kc = 1;
@@ -251,6 +280,7 @@ constexpr int CP_KSPLIT = 256;
 
 struct Layout {
     void *psi, *bufA, *bufB, *veff0, *veff1, *cnl;
+    void* dnl;                  // split-bf16 force gather: [n_ions][n_orb][3] complex FP32
     double *vloc_cur, *vloc_next, *vstatic, *hist[3], *rho, *vh;
     double2 *rhok, *spec, *phase, *phaseT, *ewald_sg;
     void* fft_work;
@@ -294,6 +324,7 @@ static Layout carve(const Geometry& g, char* base) {
     L.veff0 = c.take<void>(g.N * g.br);
     L.veff1 = c.take<void>(g.N * g.br);
     L.cnl = c.take<void>((size_t)std::max(1, g.n_ions) * g.n_orb * g.bc);
+    L.dnl = c.take<void>((size_t)std::max(1, g.n_ions) * g.n_orb * 3 * g.bc);
     L.vloc_cur = c.take<double>(g.N * 8);
     L.vloc_next = c.take<double>(g.N * 8);
     L.vstatic = c.take<double>(g.N * 8);
@@ -348,7 +379,7 @@ static Layout carve(const Geometry& g, char* base) {
     L.ewald_part = c.take<double>(ewald_scratch_doubles(g.n_ions) * 8);
     L.norm_part = c.take<double>((size_t)g.n_orb * g.norm_cap * 8);
     L.fix_part = c.take<double>((size_t)g.n_orb * fixup_blocks(g.ucap) * 8);
-    L.kin_part = c.take<double>((size_t)g.n_orb * g.nyt * g.nzc * 8);
+    L.kin_part = c.take<double>((size_t)g.n_orb * g.nxt * g.nyt * g.nzc * 8);
     L.norms = c.take<double>((size_t)g.n_orb * 8);
     L.hxc_part = c.take<double>((size_t)g.nblk256 * 3 * 8);
     L.loc_part = c.take<double>((size_t)g.nblk256 * 8);
@@ -415,6 +446,7 @@ struct me_system {
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     std::vector<double> ev_bytes;
+    std::vector<int> ev_streams;    // complex streams of each timed launch (2: first stage, 3: others)
     std::vector<hipEvent_t> ev_pool;
     double rep_host[SLOT_COUNT];
     // adjoint bookkeeping
@@ -547,7 +579,7 @@ me_status finite_setup(me_system* sys, const me_params* p) {
     sys->zr_host.assign(g.nyt, make_int2(0, 0));
     for (int t = 0; t < g.nyt; ++t) {
         int lo = g.nz, hi = 0;
-        for (int y = t * g.ty; y < (t + 1) * g.ty; ++y)
+        for (int y = t * g.ty; y < std::min(g.ny, (t + 1) * g.ty); ++y)
             for (int J = 0; J < g.n_ions; ++J) {
                 const double dy = y * p->h - sys->pos0[3 * J + 1];
                 const double rem = p->finite_radius * p->finite_radius - dy * dy;
@@ -648,6 +680,10 @@ me_status forces_parts(me_system* sys, const double* pos, int t) {
         HIPCHK(launch_kb_forces<double>((const double2*)sys->w.psi, g.stride, g.n_orb, g.n_ions, tables(sys, t), pos,
                                         sys->geo, g.nx, g.ny, g.nz, sys->prm.nl_force_form, sys->prm.occ, sys->prm.kb_energy, sys->w.fnl,
                                         sys->w.enl_part, sys->w.kbf_part, sys->stream));
+    else if (sys->prm.precision == ME_F32_BF16X3 && sys->prm.nl_force_form == 0)
+        HIPCHK(launch_kb_forces_bf16x3((const float2*)sys->w.psi, g.stride, g.n_orb, g.n_ions, tables(sys, t), pos,
+                                       sys->geo, g.nx, g.ny, sys->prm.occ, sys->prm.kb_energy, (float2*)sys->w.cnl,
+                                       (float2*)sys->w.dnl, sys->w.fnl, sys->w.enl_part, sys->stream));
     else
         HIPCHK(launch_kb_forces<float>((const float2*)sys->w.psi, g.stride, g.n_orb, g.n_ions, tables(sys, t), pos,
                                        sys->geo, g.nx, g.ny, g.nz, sys->prm.nl_force_form, sys->prm.occ, sys->prm.kb_energy, sys->w.fnl,
@@ -681,6 +717,8 @@ StencilArgs<T> base_args(me_system* sys, const T* v, int n_orb) {
     a.n_orb = n_orb;
     a.zchunk = g.zchunk;
     a.nyt = g.nyt;
+    a.tx = g.tx;
+    a.nxt = g.nxt;
     a.nzc = g.nzc;
     a.kin = (T)(-0.5 / (sys->prm.h * sys->prm.h));
     return a;
@@ -728,7 +766,7 @@ me_status exponential(me_system* sys, const T* veff, int t, bool last) {
         a.zr = g.finite ? sys->w.zr : nullptr;
         const bool norm = last && k == 1;
         a.partial = norm ? sys->w.norm_part : nullptr;
-        if (norm) sys->norm_tiles = g.nyt * g.nzc;
+        if (norm) sys->norm_tiles = g.nxt * g.nyt * g.nzc;
         const int mode = k == K ? MODE_HORNER_FIRST : MODE_HORNER;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (sys->timing) {
@@ -742,6 +780,7 @@ me_status exponential(me_system* sys, const T* veff, int t, bool last) {
             sys->ev.emplace_back(e0, e1);
             const double streams = mode == MODE_HORNER_FIRST ? 2.0 : 3.0;
             sys->ev_bytes.push_back(streams * g.bc * (double)g.N * g.n_orb + (double)g.br * g.N);
+            sys->ev_streams.push_back((int)streams);
         }
         // nonlocal part at the projector points: out += (-i tau/k) E_KB sum_J p_J c_J
         if (g.n_ions > 0)
@@ -817,7 +856,7 @@ me_status finalize(me_system* sys, bool with_norm, bool energy, const double* fi
     f.occ = sys->prm.occ;
     f.energy = energy ? 1 : 0;
     f.kin_part = sys->w.kin_part;
-    f.kin_n = (int64_t)g.n_orb * g.nyt * g.nzc;
+    f.kin_n = (int64_t)g.n_orb * g.nxt * g.nyt * g.nzc;
     f.hxc_part = sys->w.hxc_part;
     f.hxc_n = g.nblk256;
     f.loc_part = sys->w.loc_part;
@@ -1096,6 +1135,7 @@ constexpr int BATCH_WORKERS = 4;
 
 struct BatchTile {
     int ty, nyt, zchunk, nzc, items;
+    int tx, nxt;        // tile width (nx: whole rows) and x-tiles
 };
 
 struct PhaseKey {
@@ -1163,44 +1203,70 @@ constexpr int QUEUE_SLOTS = 8;     // counters per persistent launch (one per XC
         }                                                                              \
     } while (0)
 
-int batch_hj(const me_batch* b, int block) {
+// halo jobs per thread of the whole-row systems (x-tiled ones take 2)
+int batch_hj(const me_batch* b, int block, const std::vector<BatchTile>& tiles) {
     int hj = 1;
-    for (const me_system* s : b->sys)
-        if (8 * s->g.nx > block) hj = 2;
+    for (size_t i = 0; i < b->sys.size(); ++i)
+        if (tiles[i].nxt == 1 && 8 * b->sys[i]->g.nx > block) hj = 2;
     return hj;
 }
 
 // Tiles of every system for a tuning; false if the tuning cannot run them.
+// A system whose whole rows do not fit the block (or that the halo jobs of
+// whole rows would overload) runs in x-tiles of 64 points and block/64 rows;
+// MODEHR_BATCH_TX forces x-tiles of that width on every wider row (tests).
 bool batch_tiles(const me_batch* b, const me_batch_tuning& t, std::vector<BatchTile>& out, size_t& lds) {
     if (t.block < 64 || t.block > 1024 || t.block % 64) return false;
     if (t.zdiv != 1 && t.zdiv != 2 && t.zdiv != 4) return false;
+    const int ftx = env_int("MODEHR_BATCH_TX", 0);
     out.clear();
     lds = 0;
     for (const me_system* s : b->sys) {
         const Geometry& g = s->g;
-        if (8 * g.nx > 2 * t.block) return false;
-        int ty = std::min(g.ny, t.block / g.nx);
-        while (ty > 1 && stencil_lds_bytes(ty, g.nx, g.bc) > STENCIL_LDS_MAX) --ty;
-        if (ty < 1 || stencil_lds_bytes(ty, g.nx, g.bc) > STENCIL_LDS_MAX) return false;
         BatchTile bt{};
-        bt.ty = ty;
-        bt.nyt = (g.ny + ty - 1) / ty;
+        const bool xt = (ftx > 0 && g.nx > ftx) || g.nx > t.block || 8 * g.nx > 2 * t.block;
+        if (xt) {
+            const int tx = std::min(g.nx, ftx > 0 ? ftx : 64);
+            const int ty = std::min(g.ny, t.block / tx);
+            if (ty < 1 || 8 * (tx + ty) > 2 * t.block) return false;
+            const size_t l = stencil_xt_lds_bytes(tx, ty, g.bc);
+            if (l > STENCIL_LDS_MAX) return false;
+            bt.tx = tx;
+            bt.nxt = (g.nx + tx - 1) / tx;
+            bt.ty = ty;
+            lds = std::max(lds, l);
+        } else {
+            int ty = std::min(g.ny, t.block / g.nx);
+            while (ty > 1 && stencil_lds_bytes(ty, g.nx, g.bc) > STENCIL_LDS_MAX) --ty;
+            if (ty < 1 || stencil_lds_bytes(ty, g.nx, g.bc) > STENCIL_LDS_MAX) return false;
+            bt.tx = g.nx;
+            bt.nxt = 1;
+            bt.ty = ty;
+            lds = std::max(lds, stencil_lds_bytes(ty, g.nx, g.bc));
+        }
+        bt.nyt = (g.ny + bt.ty - 1) / bt.ty;
         bt.zchunk = (g.nz + t.zdiv - 1) / t.zdiv;
         bt.nzc = (g.nz + bt.zchunk - 1) / bt.zchunk;
-        if ((int64_t)bt.nyt * bt.nzc > g.norm_cap) return false;
-        const int64_t items = (int64_t)g.n_orb * bt.nyt * bt.nzc;
+        if ((int64_t)bt.nxt * bt.nyt * bt.nzc > g.norm_cap) return false;
+        const int64_t items = (int64_t)g.n_orb * bt.nxt * bt.nyt * bt.nzc;
         if (items > (1 << 26)) return false;
         bt.items = (int)items;
-        lds = std::max(lds, stencil_lds_bytes(ty, g.nx, g.bc));
         out.push_back(bt);
     }
     return true;
 }
 
+bool batch_has_xt(const std::vector<BatchTile>& tiles) {
+    for (const BatchTile& bt : tiles)
+        if (bt.nxt > 1) return true;
+    return false;
+}
+
 template <typename T>
-int batch_max_wpc(const me_batch* b, int block, size_t lds) {
+int batch_max_wpc(const me_batch* b, int block, size_t lds, const std::vector<BatchTile>& tiles) {
     int w = 0;
-    if (batch_stencil_occupancy<T>(block, lds, batch_hj(b, block), &w) != hipSuccess) return 0;
+    if (batch_stencil_occupancy<T>(block, lds, batch_hj(b, block, tiles), batch_has_xt(tiles), &w) != hipSuccess)
+        return 0;
     return w;
 }
 
@@ -1211,7 +1277,8 @@ me_status batch_apply_tuning(me_batch* b, const me_batch_tuning& t) {
         b->err = "tuning does not fit this batch (block, zdiv or LDS)";
         return ME_EINVAL;
     }
-    const int wmax = b->f64 ? batch_max_wpc<double>(b, t.block, lds) : batch_max_wpc<float>(b, t.block, lds);
+    const int wmax = b->f64 ? batch_max_wpc<double>(b, t.block, lds, tiles)
+                            : batch_max_wpc<float>(b, t.block, lds, tiles);
     if (wmax < 1 || t.wg_per_cu < 1 || t.wg_per_cu > wmax) {
         b->err = "wg_per_cu must be in [1, " + std::to_string(wmax) + "] for this block size";
         return ME_EINVAL;
@@ -1235,7 +1302,8 @@ me_status batch_default_tuning(me_batch* b) {
         std::vector<BatchTile> tiles;
         size_t lds = 0;
         if (!batch_tiles(b, t, tiles, lds)) continue;
-        const int wmax = b->f64 ? batch_max_wpc<double>(b, block, lds) : batch_max_wpc<float>(b, block, lds);
+        const int wmax = b->f64 ? batch_max_wpc<double>(b, block, lds, tiles)
+                                : batch_max_wpc<float>(b, block, lds, tiles);
         if (wmax < 1) continue;
         t.wg_per_cu = std::min(2, wmax);
         return batch_apply_tuning(b, t);
@@ -1313,13 +1381,14 @@ me_status batch_stage(me_batch* b, const std::vector<const cx_t<T>*>& u, const s
         d.stride = g.stride;
         d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
         d.ty = bt.ty; d.nyt = bt.nyt;
+        d.tx = bt.tx; d.nxt = bt.nxt;
         d.zchunk = bt.zchunk; d.nzc = bt.nzc;
         d.item0 = item;
         d.items = bt.items;
         item += bt.items;
         d.kin = (T)(-0.5 / (s->prm.h * s->prm.h));
         d.alpha = (T)(-(s->prm.dt / (2.0 * s->prm.mu)) / k);
-        if (norm) s->norm_tiles = bt.nyt * bt.nzc;
+        if (norm) s->norm_tiles = bt.nxt * bt.nyt * bt.nzc;
         const double streams = mode == MODE_HORNER_FIRST ? 2.0 : 3.0;
         bytes += streams * g.bc * (double)g.N * g.n_orb + (double)g.br * g.N;
     }
@@ -1603,7 +1672,7 @@ me_status batch_autotune(me_batch* b, me_batch_tuning* best) {
             std::vector<BatchTile> tiles;
             size_t lds = 0;
             if (!batch_tiles(b, t, tiles, lds)) continue;
-            const int wmax = std::min(4, batch_max_wpc<T>(b, block, lds));
+            const int wmax = std::min(4, batch_max_wpc<T>(b, block, lds, tiles));
             for (int w = 1; w <= wmax; ++w) {
                 t.wg_per_cu = w;
                 if (batch_apply_tuning(b, t) != ME_OK) continue;
@@ -2218,24 +2287,34 @@ me_status me_timing_enable(me_system* sys, int32_t enable) {
     for (auto& e : sys->ev) { sys->ev_pool.push_back(e.first); sys->ev_pool.push_back(e.second); }
     sys->ev.clear();
     sys->ev_bytes.clear();
+    sys->ev_streams.clear();
     sys->timing = enable != 0;
     return ME_OK;
 }
 
-me_status me_timing_read(me_system* sys, int64_t* launches, double* total_ms, double* total_bytes) {
-    if (!sys || !launches || !total_ms || !total_bytes) return ME_EINVAL;
+me_status me_timing_read_kind(me_system* sys, int32_t streams, int64_t* launches, double* total_ms,
+                              double* total_bytes) {
+    if (!sys || !launches || !total_ms || !total_bytes || (streams != 0 && streams != 2 && streams != 3))
+        return ME_EINVAL;
     HIPCHK(hipStreamSynchronize(sys->stream));
     double ms = 0.0, by = 0.0;
+    int64_t n = 0;
     for (size_t i = 0; i < sys->ev.size(); ++i) {
+        if (streams != 0 && sys->ev_streams[i] != streams) continue;
         float t = 0.f;
         HIPCHK(hipEventElapsedTime(&t, sys->ev[i].first, sys->ev[i].second));
         ms += t;
         by += sys->ev_bytes[i];
+        ++n;
     }
-    *launches = (int64_t)sys->ev.size();
+    *launches = n;
     *total_ms = ms;
     *total_bytes = by;
     return ME_OK;
+}
+
+me_status me_timing_read(me_system* sys, int64_t* launches, double* total_ms, double* total_bytes) {
+    return me_timing_read_kind(sys, 0, launches, total_ms, total_bytes);
 }
 
 me_status me_checkpoint_size(const me_system* sys, size_t* bytes) {
@@ -2407,7 +2486,6 @@ me_status me_init_batch(const me_params* ps, int32_t n_sys, void* workspace, siz
         if (ps[i].enable_adjoint) { g_init_error = "batches do not run the adjoint"; return ME_EUNSUPPORTED; }
         if (ps[i].etrs_iterations) { g_init_error = "batches run AETRS"; return ME_EUNSUPPORTED; }
         if (ps[i].finite_radius > 0.0) { g_init_error = "batches run periodic cubes"; return ME_EUNSUPPORTED; }
-        if (ps[i].n[0] > 192) { g_init_error = "batched grids are limited to 192 points per row"; return ME_EUNSUPPORTED; }
     }
     me_batch* b = new (std::nothrow) me_batch();
     if (!b) { g_init_error = "out of host memory"; return ME_EINVAL; }

@@ -83,8 +83,9 @@ struct StencilArgs {
     int64_t stride;          // complex elements between orbitals (u, psi0, out)
     int nx, ny, nz;
     int n_orb;
-    int zchunk;              // planes per workgroup
+    int zchunk;              // planes per workgroup (the last chunk may be shorter)
     int nyt, nzc;            // tiles along y, chunks along z
+    int tx, nxt;             // tile width (nx: whole rows) and tiles along x
     T kin;                   // -1/(2 h^2)
     T alpha;                 // Horner coefficient: c_k = i*alpha, alpha = -tau/k
     double* partial;         // [n_orb][nyt*nzc] norm or expectation partials, or nullptr
@@ -105,6 +106,7 @@ struct BatchSys {
     int64_t stride;
     int nx, ny, nz;
     int ty, nyt;             // rows per tile, tiles (the last may be ragged)
+    int tx, nxt;             // tile width (nx: whole rows) and x-tiles (the last may be ragged)
     int zchunk, nzc;         // planes per slab, slabs (the last may be short)
     int item0, items;        // first work item of this system, item count
     T kin, alpha;
@@ -119,6 +121,8 @@ struct BatchStencilArgs {
 
 // dynamic LDS of a stencil workgroup: two halo tiles of (ty + 8) rows of nx
 inline size_t stencil_lds_bytes(int ty, int nx, size_t bc) { return 2 * (size_t)(ty + 8) * nx * bc; }
+// the same for an x-tile of tx columns (plus the 4 + 4 x-halo columns)
+inline size_t stencil_xt_lds_bytes(int tx, int ty, size_t bc) { return 2 * (size_t)(ty + 8) * (tx + 8) * bc; }
 
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `s` and return hipGetLastError().
@@ -130,9 +134,10 @@ hipError_t launch_stencil(const StencilArgs<T>& a, int mode, bool want_norm,
 template <typename T>
 hipError_t launch_batch_stencil(const BatchStencilArgs<T>& a, int mode, bool norm, int block, int grid,
                                 size_t lds, hipStream_t s);
-// resident workgroups per CU of the batched kernel (hj = halo runs per thread)
+// resident workgroups per CU of the batched kernel (hj = halo runs per thread,
+// xt: the variant with x-tiled systems)
 template <typename T>
-hipError_t batch_stencil_occupancy(int block, size_t lds, int hj, int* wg_per_cu);
+hipError_t batch_stencil_occupancy(int block, size_t lds, int hj, bool xt, int* wg_per_cu);
 hipError_t launch_zero_i32(int* p, int n, hipStream_t s);
 
 template <typename T>
@@ -154,6 +159,14 @@ hipError_t launch_kb_gather(const cx_t<T>* u, int64_t stride, int n_orb, int n_i
 // FP32 accumulation
 hipError_t launch_kb_gather_bf16x3(const float2* u, int64_t stride, int n_orb, int n_ions, KbTables t,
                                    double ekb_h3, float2* cnl, hipStream_t s);
+
+// the contraction and its three force columns of FP32 orbitals by split-bf16
+// MFMA (FP32 accumulation): cnl[J][A] = h^3 sum p psi, dnl[J][A][a] =
+// h^3 sum (r - R_J)_a p psi; then in FP64 fnl[J] = -2 f E_KB / s^2
+// sum_A Re(conj(c) d), enl_part[J] = f E_KB sum_A |c|^2
+hipError_t launch_kb_forces_bf16x3(const float2* psi, int64_t stride, int n_orb, int n_ions, KbTables t,
+                                   const double* pos, const KbGeom& g, int nx, int ny, double occ, double ekb,
+                                   float2* cnl, float2* dnl, double* fnl, double* enl_part, hipStream_t s);
 
 // nonlocal forces and energy, FP64 accumulation:
 // fnl[J][3] = -2 f E_KB sum_A Re(conj(c_JA) d_JA); enl_part[J] = f E_KB sum_A |c_JA|^2,

@@ -2,6 +2,8 @@
 // the contraction c_JA = h^3 sum_k p_J(r_k) psi_A(r_k) and the nonlocal
 // forces / energy.  The scatter E_KB sum_J p_J c_JA is added at the
 // projector points by kb_fixup_kernel after each stencil pass.
+#include <cstdlib>
+
 #include "common.hpp"
 #include "geometry.hpp"
 
@@ -322,7 +324,14 @@ __device__ __forceinline__ T wsum_t(T v) {
     return v;
 }
 
-// one wave per (ion, orbital); four orbitals of one ion per workgroup
+// one wave per (ion, orbital); four orbitals of one ion per workgroup.  Lane
+// l takes points l, l+64, ..., l+448 of each 512-point block of the ion's
+// list; the block's index and value loads, then its orbital loads, are all
+// issued before any sum (the loads of a point depend on its index load, so a
+// loop that waited point by point would pay a round trip per 64 points).
+// The sums run in the order of the points, as a strided loop would.
+constexpr int GATHER_U = 8;
+
 template <typename T>
 __global__ void __launch_bounds__(256) kb_gather_kernel(const cx_t<T>* __restrict__ u, int64_t stride,
                                                         int n_orb, const int32_t* __restrict__ idx,
@@ -338,11 +347,23 @@ __global__ void __launch_bounds__(256) kb_gather_kernel(const cx_t<T>* __restric
     const T* pp = pv + (int64_t)J * kcap;
     const cx_t<T>* ua = u + (int64_t)A * stride;
     T re = 0, im = 0;
-    for (int k = lane; k < K; k += 64) {
-        const cx_t<T> z = ua[ix[k]];
-        const T w = pp[k];
-        re += w * z.x;
-        im += w * z.y;
+    for (int k0 = 0; k0 < K; k0 += 64 * GATHER_U) {
+        int id[GATHER_U];
+        T w[GATHER_U];
+#pragma unroll
+        for (int i = 0; i < GATHER_U; ++i) {
+            const int k = k0 + lane + 64 * i;
+            id[i] = k < K ? ix[k] : -1;
+            w[i] = k < K ? pp[k] : (T)0;
+        }
+        cx_t<T> z[GATHER_U];
+#pragma unroll
+        for (int i = 0; i < GATHER_U; ++i) z[i] = id[i] >= 0 ? ua[id[i]] : cx_t<T>{(T)0, (T)0};
+#pragma unroll
+        for (int i = 0; i < GATHER_U; ++i) {
+            re += w[i] * z[i].x;
+            im += w[i] * z[i].y;
+        }
     }
     re = wsum_t(re);
     im = wsum_t(im);
@@ -361,14 +382,15 @@ hipError_t launch_kb_gather(const cx_t<T>* u, int64_t stride, int n_orb, int n_i
 
 // ------------------------------------------------------------ split-bf16 MFMA contraction
 // The same contraction as a matrix product on the matrix cores:
-// D[16 x 16] += A[16 x 32] B[32 x 16] with v_mfma_f32_16x16x32_bf16, where
-// A rows are 8 orbitals x (re, im) gathered at 32 projector points and B
-// column 0 holds the projector values (the other columns are zero: one
-// s-channel projector per ion leaves most of the tile empty).  Each FP32
-// operand is split into bf16 hi + lo parts and the product is accumulated in
-// FP32 as hi*hi + hi*lo + lo*hi.  Fragment layout of the 16x16x32 bf16
-// instruction: lane l holds A row l%16, k = 8(l/16)..+7; B column l%16 with
-// the same k; D column l%16, rows 4(l/16)..+3.
+// D[16 x 16] += A[16 x 32] B[32 x 16] with v_mfma_f32_16x16x32_bf16, A rows
+// = 16 orbitals at 32 of the ion's points (real parts in one chain, imaginary
+// parts in another), B column 0 = the projector at those points (one
+// s-channel projector per ion fills one column; the force gather fills
+// columns 1-3 with (r - R_J)_a p_J).  Each FP32 operand is split into bf16 hi
+// + lo parts and the product accumulated in FP32 as hi*hi + hi*lo + lo*hi.
+// Fragment layout of the 16x16x32 bf16 instruction: lane l holds A row l%16,
+// k = 8(l/16)..+7; B column l%16 with the same k; D column l%16, rows
+// 4(l/16)..+3.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
@@ -377,73 +399,202 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
     lo = (__bf16)(x - (float)hi);
 }
 
-// A workgroup takes 8 orbitals of one ion; its four waves take every fourth
-// 32-point chunk of the ion's points, and their partial tiles are summed in a
-// fixed order at the end.
-__global__ void __launch_bounds__(256) kb_gather_bf16x3_kernel(const float2* __restrict__ u, int64_t stride,
-                                                               int n_orb, const int32_t* __restrict__ idx,
-                                                               const float* __restrict__ pv,
-                                                               const int32_t* __restrict__ count, int kcap,
-                                                               float scale, float2* __restrict__ cnl) {
-    __shared__ float part[4][4][4];                               // [wave][kq][row in the quad]
+__device__ __forceinline__ void split8(const float* v, bf16x8_t& hi, bf16x8_t& lo) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        __bf16 h, l;
+        split_bf16(v[i], h, l);
+        hi[i] = h;
+        lo[i] = l;
+    }
+}
+
+__device__ __forceinline__ f32x4_t mfma3(const bf16x8_t& ah, const bf16x8_t& al, const bf16x8_t& bh,
+                                         const bf16x8_t& bl, f32x4_t acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+    return acc;
+}
+
+// A workgroup of GW waves takes 16 orbitals of one ion; wave w takes the
+// 32-point chunks w, w + GW, ... of the ion's list (one chunk for lists of up
+// to 32 GW points).  A chunk is loaded as the FP32 gather loads it (each
+// instruction two orbitals at 32 consecutive list entries, one index load per
+// lane for all 16 orbitals), staged in the wave's own LDS rows (padded
+// against bank conflicts), and read back in the MFMA fragment layout.  The
+// waves' tiles are summed in a fixed order through LDS.  FORCE: B columns 1-3
+// hold (r - R_J)_a p_J (minimum image, FP64 geometry rounded to FP32) and the
+// result goes to dnl ([n_ions][n_orb][3] complex, h^3 sum (r - R_J) p psi)
+// beside cnl.
+constexpr int BG_ROW = 32 + 2;       // LDS row of one orbital's chunk (complex), padded
+
+template <bool FORCE>
+__global__ void __launch_bounds__(1024) kb_gather_bf16x3_kernel(const float2* __restrict__ u, int64_t stride,
+                                                                int n_orb, const int32_t* __restrict__ idx,
+                                                                const float* __restrict__ pv,
+                                                                const int32_t* __restrict__ count, int kcap,
+                                                                float scale, float2* __restrict__ cnl,
+                                                                const double* __restrict__ pos, KbGeom g,
+                                                                int nx, int ny, float dscale,
+                                                                float2* __restrict__ dnl) {
+    constexpr int NC = FORCE ? 4 : 1;                 // useful B columns
+    __shared__ float2 zs[16][16][BG_ROW];             // [wave][orbital][point of the chunk]
+    __shared__ float bs[16][NC][32];                  // [wave][column][point]
+    __shared__ float part[16][2][NC][16];             // [wave][re, im][column][orbital]
     const int J = blockIdx.y;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int A0 = blockIdx.x * 8;                                // first orbital of this workgroup
+    const int GW = blockDim.x >> 6;
+    const int A0 = blockIdx.x * 16;
     const int K = count[J];
     const int32_t* ix = idx + (int64_t)J * kcap;
     const float* pp = pv + (int64_t)J * kcap;
-    const int m = lane & 15;
-    const int kq = lane >> 4;
-    const int a = A0 + (m >> 1);
-    const bool a_ok = a < n_orb;
-    const float2* ua = u + (int64_t)(a_ok ? a : 0) * stride;
-    f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 32 * wv; k0 < K; k0 += 128) {
-        bf16x8_t ah, al, bh, bl;
+    const int m = lane & 15;                          // fragment: A row (orbital) and B column
+    const int kq = lane >> 4;                         // fragment: k group of 8 points
+    const int lp = lane & 31;                         // load: point of the chunk
+    const int lo = lane >> 5;                         // load: orbital of the pair
+    double rx = 0.0, ry = 0.0, rz = 0.0;
+    if constexpr (FORCE) {
+        rx = pos[3 * J];
+        ry = pos[3 * J + 1];
+        rz = pos[3 * J + 2];
+    }
+    f32x4_t dre = {0.f, 0.f, 0.f, 0.f}, dim = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 32 * wv; k0 < K; k0 += 32 * GW) {
+        const int k = k0 + lp;
+        const int id = k < K ? ix[k] : -1;
+        float2 z[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            const int k = k0 + 8 * kq + i;
-            float av = 0.f, bv = 0.f;
-            if (k < K) {
-                if (a_ok) {
-                    const float2 z = ua[ix[k]];
-                    av = (m & 1) ? z.y : z.x;
-                }
-                if (m == 0) bv = pp[k];
-            }
-            __bf16 h, l;
-            split_bf16(av, h, l);
-            ah[i] = h;
-            al[i] = l;
-            split_bf16(bv, h, l);
-            bh[i] = h;
-            bl[i] = l;
+            const int a = A0 + 2 * i + lo;
+            z[i] = (id >= 0 && a < n_orb) ? u[(int64_t)a * stride + id] : make_float2(0.f, 0.f);
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) zs[wv][2 * i + lo][lp] = z[i];
+        if (lo == 0) {
+            const float p = id >= 0 ? pp[k] : 0.f;
+            bs[wv][0][lp] = p;
+            if constexpr (FORCE) {
+                double dx = 0.0, dy = 0.0, dz = 0.0;
+                if (id >= 0) {
+                    const int gx = id % nx, gy = (id / nx) % ny, gz = id / (nx * ny);
+                    kb_d2(g, gx, gy, gz, rx, ry, rz, dx, dy, dz);
+                }
+                bs[wv][1][lp] = (float)dx * p;
+                bs[wv][2][lp] = (float)dy * p;
+                bs[wv][3][lp] = (float)dz * p;
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);           // this wave's LDS writes complete (lgkmcnt 0)
+        __builtin_amdgcn_wave_barrier();
+        float zr[8], zi[8], bv[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float2 v = zs[wv][m][8 * kq + i];
+            zr[i] = v.x;
+            zi[i] = v.y;
+            bv[i] = m < NC ? bs[wv][m < NC ? m : 0][8 * kq + i] : 0.f;
+        }
+        __builtin_amdgcn_wave_barrier();              // reads done before the next chunk's writes
+        bf16x8_t arh, arl, aih, ail, bh, bl;
+        split8(zr, arh, arl);
+        split8(zi, aih, ail);
+        split8(bv, bh, bl);
+        dre = mfma3(arh, arl, bh, bl, dre);
+        dim = mfma3(aih, ail, bh, bl, dim);
     }
-    // column 0 holds the result: rows 4kq .. 4kq+3 (orbitals A0 + 2kq, +1; re, im)
-    if (m == 0)
-        for (int r = 0; r < 4; ++r) part[wv][kq][r] = acc[r];
+    // lane l holds D[4 kq + r][m]: column m, orbitals A0 + 4 kq + r
+    if (m < NC) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            part[wv][0][m][4 * kq + r] = dre[r];
+            part[wv][1][m][4 * kq + r] = dim[r];
+        }
+    }
     __syncthreads();
-    if (threadIdx.x < 4) {
-        const int q = threadIdx.x;
-        float v[4];
-        for (int r = 0; r < 4; ++r) v[r] = ((part[0][q][r] + part[1][q][r]) + part[2][q][r]) + part[3][q][r];
-        const int a1 = A0 + 2 * q;
-        if (a1 < n_orb) cnl[(int64_t)J * n_orb + a1] = make_float2(scale * v[0], scale * v[1]);
-        if (a1 + 1 < n_orb) cnl[(int64_t)J * n_orb + a1 + 1] = make_float2(scale * v[2], scale * v[3]);
+    const int t = threadIdx.x;
+    if (t < 16 * NC) {
+        const int o = t & 15, c = t >> 4;
+        float vr = 0.f, vi = 0.f;
+        for (int w = 0; w < GW; ++w) {
+            vr += part[w][0][c][o];
+            vi += part[w][1][c][o];
+        }
+        if (A0 + o < n_orb) {
+            if (c == 0)
+                cnl[(int64_t)J * n_orb + A0 + o] = make_float2(scale * vr, scale * vi);
+            else if constexpr (FORCE)
+                dnl[((int64_t)J * n_orb + A0 + o) * 3 + (c - 1)] = make_float2(dscale * vr, dscale * vi);
+        }
     }
+}
+
+// waves per workgroup: one per 32-point chunk of the largest ion list, at most
+// 8 (at the kernel's register use 1024-thread workgroups fit once per CU,
+// 512-thread ones three times); MODEHR_BG_WAVES overrides (measurements)
+static int bf16_gather_waves(int kcap) {
+    const char* e = std::getenv("MODEHR_BG_WAVES");
+    const int cap = (e && *e) ? std::max(1, std::min(16, std::atoi(e))) : 8;
+    return std::max(1, std::min(cap, (kcap + 31) / 32));
 }
 
 hipError_t launch_kb_gather_bf16x3(const float2* u, int64_t stride, int n_orb, int n_ions, KbTables t,
                                    double ekb_h3, float2* cnl, hipStream_t s) {
     if (n_ions == 0) return hipSuccess;
-    dim3 grid((n_orb + 7) / 8, n_ions);
-    kb_gather_bf16x3_kernel<<<grid, 256, 0, s>>>(u, stride, n_orb, t.idx, reinterpret_cast<const float*>(t.p),
-                                                 t.count, t.kcap, (float)ekb_h3, cnl);
+    dim3 grid((n_orb + 15) / 16, n_ions);
+    KbGeom g0{};
+    kb_gather_bf16x3_kernel<false><<<grid, 64 * bf16_gather_waves(t.kcap), 0, s>>>(
+        u, stride, n_orb, t.idx, reinterpret_cast<const float*>(t.p), t.count, t.kcap, (float)ekb_h3, cnl,
+        nullptr, g0, 1, 1, 0.f, nullptr);
+    return hipGetLastError();
+}
+
+// the contraction and the three force columns of FP32 orbitals by split-bf16
+// MFMA: cnl[J][A] = h^3 sum p psi (E_KB not included), dnl[J][A][a] =
+// h^3 sum (r - R_J)_a p psi; then, in FP64, fnl[J] = -2 f E_KB / s^2 sum_A
+// Re(conj(c) d) and enl[J] = f E_KB sum_A |c|^2
+__global__ void kb_forces_from_columns_kernel(const float2* __restrict__ cnl, const float2* __restrict__ dnl,
+                                              int n_orb, int n_ions, double kf, double ke,
+                                              double* __restrict__ fnl, double* __restrict__ enl) {
+    __shared__ double red[4][4];
+    const int J = blockIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double f[3] = {0.0, 0.0, 0.0}, e = 0.0;
+    for (int A = threadIdx.x; A < n_orb; A += blockDim.x) {
+        const float2 c = cnl[(int64_t)J * n_orb + A];
+        const double cr = c.x, ci = c.y;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const float2 d = dnl[((int64_t)J * n_orb + A) * 3 + ax];
+            f[ax] += cr * (double)d.x + ci * (double)d.y;
+        }
+        e += cr * cr + ci * ci;
+    }
+    double v[4] = {f[0], f[1], f[2], e};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        double x = v[c];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if (lane == 0) red[wv][c] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) fnl[3 * J + threadIdx.x] = kf * (((red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                                                            red[2][threadIdx.x]) + red[3][threadIdx.x]);
+    if (threadIdx.x == 3) enl[J] = ke * (((red[0][3] + red[1][3]) + red[2][3]) + red[3][3]);
+}
+
+hipError_t launch_kb_forces_bf16x3(const float2* psi, int64_t stride, int n_orb, int n_ions, KbTables t,
+                                   const double* pos, const KbGeom& g, int nx, int ny, double occ, double ekb,
+                                   float2* cnl, float2* dnl, double* fnl, double* enl_part, hipStream_t s) {
+    if (n_ions == 0) return hipSuccess;
+    const double h3 = g.h * g.h * g.h;
+    dim3 grid((n_orb + 15) / 16, n_ions);
+    kb_gather_bf16x3_kernel<true><<<grid, 64 * bf16_gather_waves(t.kcap), 0, s>>>(
+        psi, stride, n_orb, t.idx, reinterpret_cast<const float*>(t.p), t.count, t.kcap, (float)h3, cnl, pos, g,
+        nx, ny, (float)h3, dnl);
+    kb_forces_from_columns_kernel<<<n_ions, 256, 0, s>>>(cnl, dnl, n_orb, n_ions,
+                                                         -2.0 * occ * ekb * g.inv_s2, occ * ekb, fnl, enl_part);
     return hipGetLastError();
 }
 

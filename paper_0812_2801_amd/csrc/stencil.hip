@@ -320,6 +320,180 @@ __device__ __forceinline__ double zmarch(const cx_t<T>* __restrict__ u, const cx
     return acc;
 }
 
+// x-tiled z-march: the workgroup owns cols <= TX consecutive points of each
+// of rows <= TY consecutive y-rows, starting at (x0, y0) (the last tile of
+// a row or column may be narrower), so the tile height no longer falls as
+// the rows grow.  The LDS tile has TX + 8 columns: the tile's points at
+// columns 4 .. cols+3 and a 4-point x-halo on each side (periodic wrap
+// resolved in the global index), and rows + 8 LDS rows as in zmarch.  The
+// x-halo runs join the y-halo jobs (8 rows of cols points, then rows runs of
+// 4 + 4 points), fetched HL planes ahead like them.  Thread (tx, ty) =
+// (tid % TX, tid / TX) owns point (x0 + tx, y0 + ty) when tx < cols and
+// ty < rows; the others only load halo jobs and meet the barriers.
+// The tile shape (TX, TY) is a run-time value here; the single-system kernel
+// passes compile-time constants, the batched kernel each system's shape.  HJ
+// halo jobs per thread must cover 8 (cols + rows) jobs with blockDim.x
+// threads (blockDim.x >= TX * TY).
+template <typename T, int HJ, int MODE, bool NORM>
+__device__ __forceinline__ double zmarch_xt(const cx_t<T>* __restrict__ u, const cx_t<T>* __restrict__ p0,
+                                            cx_t<T>* __restrict__ out, const T* __restrict__ v, int nx,
+                                            int ny, int nz, int TX, int TY, int x0, int cols, int y0, int rows,
+                                            int z0, int z1, T kin, T alpha, cx_t<T>* tiles) {
+    using C = cx_t<T>;
+    constexpr int D = Pipe<T>::D;
+    constexpr int HL = Pipe<T>::HL;
+    constexpr bool HORNER = MODE == MODE_HORNER;
+    constexpr bool NEEDV = MODE != MODE_EXPECT_T;
+    const int RS = TX + 8;                                           // LDS row stride
+    const int TILE = (TY + 8) * RS;
+
+    const int tid = threadIdx.x;
+    const int tx = tid % TX;
+    const int ty = tid / TX;
+    const bool active = tx < cols && ty < rows;
+    const int plane = nx * ny;
+    const int rowoff = active ? (y0 + ty) * nx + x0 + tx : 0;
+    const int yo = (ty + 4) * RS + tx + 4;
+
+    const T c0 = (T)(3.0 * FD_C0);
+    const T cm[4] = {(T)FD_C1, (T)FD_C2, (T)FD_C3, (T)FD_C4};
+
+    // halo jobs: (LDS offset, global offset within a plane)
+    const int n_yh = 8 * cols;
+    const int n_halo = n_yh + 8 * rows;
+    int h_lds[HJ], h_off[HJ];
+    bool h_ok[HJ];
+#pragma unroll
+    for (int i = 0; i < HJ; ++i) {
+        const int j = tid + i * (int)blockDim.x;
+        h_ok[i] = j < n_halo;
+        int lds = 0, gy = 0, gx = 0;
+        if (j < n_yh) {
+            const int r = j / cols;
+            const int c = j - r * cols;
+            lds = (r < 4 ? r : rows + r) * RS + c + 4;
+            gy = wrap1(r < 4 ? y0 - 4 + r : y0 + rows + (r - 4), ny);
+            gx = x0 + c;
+        } else if (h_ok[i]) {
+            const int jj = j - n_yh;
+            const int r = jj >> 3;
+            const int c8 = jj & 7;
+            lds = (r + 4) * RS + (c8 < 4 ? c8 : cols + c8);
+            gy = y0 + r;
+            gx = wrap1(c8 < 4 ? x0 - 4 + c8 : x0 + cols + (c8 - 4), nx);
+        }
+        h_lds[i] = lds;
+        h_off[i] = gy * nx + gx;
+    }
+
+    C q[9 + D];
+    C hq[HL + 1][HJ];
+    C pq[D + 1];
+    T vq[D + 1];
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < 8 + D; ++k) q[k] = u[wrap1(z0 - 4 + k, nz) * plane + rowoff];
+    }
+#pragma unroll
+    for (int d = 0; d < HL; ++d) {
+        if (z0 + d < z1) {
+            const int zo = (z0 + d) * plane;
+#pragma unroll
+            for (int i = 0; i < HJ; ++i)
+                if (h_ok[i]) hq[d][i] = u[zo + h_off[i]];
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        if (z0 + d < z1 && active) {
+            const int zo = (z0 + d) * plane;
+            if constexpr (HORNER) load_once<T, 1>(p0 + zo + rowoff, &pq[d]);
+            if constexpr (NEEDV) vq[d] = v[zo + rowoff];
+        }
+    }
+    if (active) tiles[yo] = q[4];
+#pragma unroll
+    for (int i = 0; i < HJ; ++i)
+        if (h_ok[i]) tiles[h_lds[i]] = hq[0][i];
+    __syncthreads();
+
+    double acc = 0.0;
+    for (int z = z0; z < z1; ++z) {
+        const int buf = (z - z0) & 1;
+        if (z + HL < z1) {
+            const int zo = (z + HL) * plane;
+#pragma unroll
+            for (int i = 0; i < HJ; ++i)
+                if (h_ok[i]) hq[HL][i] = u[zo + h_off[i]];
+        }
+        if (z + D < z1 && active) {
+            const int zo = (z + D) * plane;
+            q[8 + D] = u[wrap1(z + 4 + D, nz) * plane + rowoff];
+            if constexpr (HORNER) load_once<T, 1>(p0 + zo + rowoff, &pq[D]);
+            if constexpr (NEEDV) vq[D] = v[zo + rowoff];
+        }
+        const C* tile = tiles + buf * TILE;
+
+        if (active) {
+            const C ctr = q[4];
+            T sre = c0 * ctr.x, sim = c0 * ctr.y;
+#pragma unroll
+            for (int m = 1; m <= 4; ++m) {
+                const C xp = tile[yo + m];
+                const C xm = tile[yo - m];
+                const C yp = tile[yo + m * RS];
+                const C ym = tile[yo - m * RS];
+                const C zp = q[4 + m];
+                const C zm = q[4 - m];
+                sre += cm[m - 1] * (((xp.x + xm.x) + (yp.x + ym.x)) + (zp.x + zm.x));
+                sim += cm[m - 1] * (((xp.y + xm.y) + (yp.y + ym.y)) + (zp.y + zm.y));
+            }
+            const T tre = kin * sre, tim = kin * sim;
+            if constexpr (MODE == MODE_EXPECT_T) {
+                acc += (double)ctr.x * (double)tre + (double)ctr.y * (double)tim;
+            } else {
+                const T vv = vq[0];
+                // v_eff = +inf marks points outside a finite box, where H psi is zero
+                const bool inb = vv < (T)INFINITY;
+                const T hre = inb ? tre + vv * ctr.x : (T)0;
+                const T him = inb ? tim + vv * ctr.y : (T)0;
+                C res;
+                if constexpr (MODE == MODE_APPLY) {
+                    res = C{hre, him};
+                } else if constexpr (MODE == MODE_SCALED) {
+                    res = C{-alpha * him, alpha * hre};
+                } else {
+                    const C base = HORNER ? pq[0] : ctr;
+                    res = C{base.x - alpha * him, base.y + alpha * hre};
+                }
+                if constexpr (NORM) acc += (double)res.x * (double)res.x + (double)res.y * (double)res.y;
+                store_out<T, 1>(out + z * plane + rowoff, &res);
+            }
+        }
+
+        if (z + 1 < z1) {
+            C* nt = tiles + (buf ^ 1) * TILE;
+            if (active) nt[yo] = q[5];
+#pragma unroll
+            for (int i = 0; i < HJ; ++i)
+                if (h_ok[i]) nt[h_lds[i]] = hq[1][i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 8 + D; ++k) q[k] = q[k + 1];
+#pragma unroll
+        for (int d = 0; d < HL; ++d)
+#pragma unroll
+            for (int i = 0; i < HJ; ++i) hq[d][i] = hq[d + 1][i];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            if constexpr (HORNER) pq[d] = pq[d + 1];
+            if constexpr (NEEDV) vq[d] = vq[d + 1];
+        }
+    }
+    return acc;
+}
+
 // workgroup sum of one double per thread; result in thread 0
 __device__ __forceinline__ double block_sum(double v, double* red) {
     v = wave_sum(v);
@@ -365,6 +539,42 @@ stencil_kernel(const cx_t<T>* __restrict__ u_all, const cx_t<T>* __restrict__ p0
     }
 }
 
+// One system in x-tiles: a workgroup per (orbital, x-tile, y-tile, z-chunk),
+// x-tiles fastest so that neighbouring tiles (which share halo points) run
+// close together on one XCD.
+template <typename T, int TX, int TY, int MODE, bool NORM>
+__global__ void __launch_bounds__(TX * TY) STENCIL_ATTR
+stencil_xt_kernel(const cx_t<T>* __restrict__ u_all, const cx_t<T>* __restrict__ p0_all,
+                  cx_t<T>* __restrict__ out_all, const T* __restrict__ v, double* __restrict__ partial,
+                  StencilArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx_t<T>* tiles = reinterpret_cast<cx_t<T>*>(smem_raw);     // 2 x [(TY+8)][TX+8]
+    __shared__ double red[16];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int xt = b % a.nxt;
+    int rest = b / a.nxt;
+    const int yt = rest % a.nyt;
+    rest /= a.nyt;
+    const int zc = rest % a.nzc;
+    const int A = rest / a.nzc;
+    const int x0 = xt * TX, y0 = yt * TY;
+    int z0 = zc * a.zchunk, z1 = min(z0 + a.zchunk, a.nz);
+    if (a.zr != nullptr) {          // finite box: only the planes where the tile's rows meet it
+        const int2 r = a.zr[yt];
+        z0 = max(z0, r.x);
+        z1 = max(z0, min(z1, r.y));
+    }
+    constexpr int HJ = (8 * TX + 8 * TY + TX * TY - 1) / (TX * TY);  // halo jobs per thread
+    const double acc = zmarch_xt<T, HJ, MODE, NORM>(
+        u_all + (int64_t)A * a.stride, p0_all + (int64_t)A * a.stride, out_all + (int64_t)A * a.stride, v,
+        a.nx, a.ny, a.nz, TX, TY, x0, min(TX, a.nx - x0), y0, min(TY, a.ny - y0), z0, z1, a.kin, a.alpha, tiles);
+    if constexpr (NORM || MODE == MODE_EXPECT_T) {
+        const double s = block_sum(acc, red);
+        if (threadIdx.x == 0)
+            partial[(int64_t)A * ((int64_t)a.nxt * a.nyt * a.nzc) + ((int64_t)zc * a.nyt + yt) * a.nxt + xt] = s;
+    }
+}
+
 // Many systems in one persistent launch.  Work items are (system, orbital,
 // y-tile, z-slab), numbered system by system in launch order (the host puts
 // the largest systems first), y-tiles fastest, then z-slabs, then orbitals.
@@ -395,7 +605,9 @@ __device__ int batch_pull(const BatchStencilArgs<T>& a, int* q_next) {
     return -1;
 }
 
-template <typename T, int HJ, int MODE, bool NORM>
+// XT: some systems run in x-tiles (tx < nx: items (system, orbital, x-tile,
+// y-tile, z-slab), x-tiles fastest), with at most 2 halo jobs per thread.
+template <typename T, int HJ, int MODE, bool NORM, bool XT>
 __global__ void __launch_bounds__(1024) STENCIL_ATTR batch_stencil_kernel(BatchStencilArgs<T> a) {
     using C = cx_t<T>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -413,34 +625,46 @@ __global__ void __launch_bounds__(1024) STENCIL_ATTR batch_stencil_kernel(BatchS
         while (s + 1 < a.n_sys && item >= a.sys[s + 1].item0) ++s;
         const BatchSys<T>& d = a.sys[s];
         const int local = item - d.item0;
-        const int ytile = local % d.nyt;
-        const int rest = local / d.nyt;
+        const int xtile = local % d.nxt;
+        int rest = local / d.nxt;
+        const int ytile = rest % d.nyt;
+        rest /= d.nyt;
         const int zc = rest % d.nzc;
         const int A = rest / d.nzc;
         const int y0 = ytile * d.ty;
         const int rows = min(d.ty, d.ny - y0);
         const int z0 = zc * d.zchunk;
         const int z1 = min(z0 + d.zchunk, d.nz);
-        const bool active = (int)threadIdx.x < d.nx * rows;
-        const double acc = zmarch<T, 1, 0, HJ, MODE, NORM>(
-            d.u + (int64_t)A * d.stride, d.psi0 + (int64_t)A * d.stride, d.out + (int64_t)A * d.stride, d.v,
-            d.nx, d.ny, d.nz, d.ty, y0, rows, z0, z1, d.kin, d.alpha, tiles, active);
+        double acc = 0.0;
+        if (XT && d.tx < d.nx) {
+            const int x0 = xtile * d.tx;
+            acc = zmarch_xt<T, 2, MODE, NORM>(
+                d.u + (int64_t)A * d.stride, d.psi0 + (int64_t)A * d.stride, d.out + (int64_t)A * d.stride, d.v,
+                d.nx, d.ny, d.nz, d.tx, d.ty, x0, min(d.tx, d.nx - x0), y0, rows, z0, z1, d.kin, d.alpha, tiles);
+        } else {
+            const bool active = (int)threadIdx.x < d.nx * rows;
+            acc = zmarch<T, 1, 0, HJ, MODE, NORM>(
+                d.u + (int64_t)A * d.stride, d.psi0 + (int64_t)A * d.stride, d.out + (int64_t)A * d.stride, d.v,
+                d.nx, d.ny, d.nz, d.ty, y0, rows, z0, z1, d.kin, d.alpha, tiles, active);
+        }
         if constexpr (NORM) {
             const double sum = block_sum(acc, red);
-            if (threadIdx.x == 0) d.partial[(int64_t)A * (d.nyt * d.nzc) + zc * d.nyt + ytile] = sum;
+            if (threadIdx.x == 0)
+                d.partial[(int64_t)A * ((int64_t)d.nxt * d.nyt * d.nzc) + ((int64_t)zc * d.nyt + ytile) * d.nxt +
+                          xtile] = sum;
         }
     }
 }
 
-template <typename T, int HJ>
+template <typename T, int HJ, bool XT>
 static void launch_batch_hj(const BatchStencilArgs<T>& a, int mode, bool norm, int block, int grid, size_t lds,
                             hipStream_t s) {
     if (mode == MODE_HORNER) {
-        if (norm) batch_stencil_kernel<T, HJ, MODE_HORNER, true><<<grid, block, lds, s>>>(a);
-        else batch_stencil_kernel<T, HJ, MODE_HORNER, false><<<grid, block, lds, s>>>(a);
+        if (norm) batch_stencil_kernel<T, HJ, MODE_HORNER, true, XT><<<grid, block, lds, s>>>(a);
+        else batch_stencil_kernel<T, HJ, MODE_HORNER, false, XT><<<grid, block, lds, s>>>(a);
     } else {
-        if (norm) batch_stencil_kernel<T, HJ, MODE_HORNER_FIRST, true><<<grid, block, lds, s>>>(a);
-        else batch_stencil_kernel<T, HJ, MODE_HORNER_FIRST, false><<<grid, block, lds, s>>>(a);
+        if (norm) batch_stencil_kernel<T, HJ, MODE_HORNER_FIRST, true, XT><<<grid, block, lds, s>>>(a);
+        else batch_stencil_kernel<T, HJ, MODE_HORNER_FIRST, false, XT><<<grid, block, lds, s>>>(a);
     }
 }
 
@@ -451,16 +675,29 @@ hipError_t launch_batch_stencil(const BatchStencilArgs<T>& a, int mode, bool nor
     if (block < 64 || block > 1024 || block % 64 || grid < 1 || a.n_sys < 1 || a.n_sys > MAX_BATCH)
         return hipErrorInvalidValue;
     int hj = 1;
+    bool xt = false;
     for (int i = 0; i < a.n_sys; ++i) {
         const BatchSys<T>& d = a.sys[i];
-        if (d.nx * d.ty > block || d.ty < 1 || d.nyt * d.ty < d.ny || d.nzc * d.zchunk < d.nz)
+        if (d.ty < 1 || d.nyt * d.ty < d.ny || d.nzc * d.zchunk < d.nz || d.tx < 1 || d.nxt * d.tx < d.nx)
             return hipErrorInvalidValue;
-        if (8 * d.nx > block) hj = 2;
-        if (8 * d.nx > 2 * block) return hipErrorInvalidValue;
-        if (2 * (size_t)(d.ty + 8) * d.nx * sizeof(cx_t<T>) > lds) return hipErrorInvalidValue;
+        if (d.tx < d.nx) {          // x-tiles: tile within the block, at most 2 halo jobs per thread
+            xt = true;
+            if (d.tx * d.ty > block || 8 * (d.tx + d.ty) > 2 * block) return hipErrorInvalidValue;
+            if (stencil_xt_lds_bytes(d.tx, d.ty, sizeof(cx_t<T>)) > lds) return hipErrorInvalidValue;
+        } else {
+            if (d.nxt != 1 || d.nx * d.ty > block) return hipErrorInvalidValue;
+            if (8 * d.nx > block) hj = 2;
+            if (8 * d.nx > 2 * block) return hipErrorInvalidValue;
+            if (2 * (size_t)(d.ty + 8) * d.nx * sizeof(cx_t<T>) > lds) return hipErrorInvalidValue;
+        }
     }
-    if (hj == 1) launch_batch_hj<T, 1>(a, mode, norm, block, grid, lds, s);
-    else launch_batch_hj<T, 2>(a, mode, norm, block, grid, lds, s);
+    if (xt) {
+        if (hj == 1) launch_batch_hj<T, 1, true>(a, mode, norm, block, grid, lds, s);
+        else launch_batch_hj<T, 2, true>(a, mode, norm, block, grid, lds, s);
+    } else {
+        if (hj == 1) launch_batch_hj<T, 1, false>(a, mode, norm, block, grid, lds, s);
+        else launch_batch_hj<T, 2, false>(a, mode, norm, block, grid, lds, s);
+    }
     return hipGetLastError();
 }
 template hipError_t launch_batch_stencil<double>(const BatchStencilArgs<double>&, int, bool, int, int, size_t, hipStream_t);
@@ -468,15 +705,22 @@ template hipError_t launch_batch_stencil<float>(const BatchStencilArgs<float>&, 
 
 // attributes the host needs to size a persistent launch
 template <typename T>
-hipError_t batch_stencil_occupancy(int block, size_t lds, int hj, int* wg_per_cu) {
+hipError_t batch_stencil_occupancy(int block, size_t lds, int hj, bool xt, int* wg_per_cu) {
+    if (xt) {
+        if (hj == 1)
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                wg_per_cu, batch_stencil_kernel<T, 1, MODE_HORNER, false, true>, block, lds);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            wg_per_cu, batch_stencil_kernel<T, 2, MODE_HORNER, false, true>, block, lds);
+    }
     if (hj == 1)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, batch_stencil_kernel<T, 1, MODE_HORNER, false>,
-                                                            block, lds);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, batch_stencil_kernel<T, 2, MODE_HORNER, false>,
-                                                        block, lds);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            wg_per_cu, batch_stencil_kernel<T, 1, MODE_HORNER, false, false>, block, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        wg_per_cu, batch_stencil_kernel<T, 2, MODE_HORNER, false, false>, block, lds);
 }
-template hipError_t batch_stencil_occupancy<double>(int, size_t, int, int*);
-template hipError_t batch_stencil_occupancy<float>(int, size_t, int, int*);
+template hipError_t batch_stencil_occupancy<double>(int, size_t, int, bool, int*);
+template hipError_t batch_stencil_occupancy<float>(int, size_t, int, bool, int*);
 
 // zero n ints (graph-safe replacement for a memset)
 __global__ void zero_i32_kernel(int* __restrict__ p, int n) {
@@ -513,10 +757,41 @@ static hipError_t launch_ty(const StencilArgs<T>& a, int mode, bool norm, hipStr
     return hipGetLastError();
 }
 
+template <typename T, int TX, int TY>
+static hipError_t launch_xt(const StencilArgs<T>& a, int mode, bool norm, hipStream_t s) {
+    dim3 block(TX * TY);
+    dim3 grid((unsigned)((int64_t)a.n_orb * a.nxt * a.nyt * a.nzc));
+    const size_t lds = stencil_xt_lds_bytes(TX, TY, sizeof(cx_t<T>));
+#define ME_STENCIL(M, NORM) \
+    stencil_xt_kernel<T, TX, TY, M, NORM><<<grid, block, lds, s>>>(a.u, a.psi0, a.out, a.v, a.partial, a)
+    switch (mode) {
+    case MODE_APPLY: ME_STENCIL(MODE_APPLY, false); break;
+    case MODE_HORNER:
+        if (norm) ME_STENCIL(MODE_HORNER, true); else ME_STENCIL(MODE_HORNER, false);
+        break;
+    case MODE_HORNER_FIRST:
+        if (norm) ME_STENCIL(MODE_HORNER_FIRST, true); else ME_STENCIL(MODE_HORNER_FIRST, false);
+        break;
+    case MODE_EXPECT_T: ME_STENCIL(MODE_EXPECT_T, false); break;
+    case MODE_SCALED: ME_STENCIL(MODE_SCALED, false); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef ME_STENCIL
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_stencil(const StencilArgs<T>& a, int mode, bool want_norm, int ty, int px,
                           hipStream_t s) {
     if (px != 1) return hipErrorInvalidValue;
+    if (a.tx != a.nx) {             // x-tiles: the tile shape is one of the compiled ones
+        if (a.tx < 1 || a.nxt * a.tx < a.nx || a.nyt * ty < a.ny) return hipErrorInvalidValue;
+        if (a.tx == 64 && ty == 12) return launch_xt<T, 64, 12>(a, mode, want_norm, s);
+        if (a.tx == 48 && ty == 16) return launch_xt<T, 48, 16>(a, mode, want_norm, s);
+        if (a.tx == 32 && ty == 24) return launch_xt<T, 32, 24>(a, mode, want_norm, s);
+        if (a.tx == 16 && ty == 8) return launch_xt<T, 16, 8>(a, mode, want_norm, s);    // small grids, tests
+        return hipErrorInvalidValue;
+    }
     switch (ty) {
     case 16: return launch_ty<T, 1, 16>(a, mode, want_norm, s);
     case 8: return launch_ty<T, 1, 8>(a, mode, want_norm, s);

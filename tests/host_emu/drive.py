@@ -88,7 +88,9 @@ UNEVEN = [
     W.C1.replace(name="b3", n=40, h=0.25, n_orb=2, n_ions=3, placement="lattice", jitter=0.2, seed=1004),
 ]
 
-if scenario == "system":
+if scenario in ("system", "system_xt"):
+    # system_xt runs with MODEHR_TX=16 MODEHR_TY=8: the 20^3 case in x-tiles,
+    # ragged along x (16 + 4) and y (8 + 8 + 4)
     # 20^3 with 5 orbitals and 5 ions: a tile height of 4 rows, an odd
     # orbital count for the 8-orbital contraction blocks
     for c in (W.C1, W.C1.replace(name="odd", n=20, n_orb=5, n_ions=5, placement="lattice", jitter=0.2, seed=77)):
@@ -131,7 +133,9 @@ if scenario == "system":
         print(f"{c.name}: gradient-form forces max|dF| {dfg:.2e}", flush=True)
         assert dfg <= TOL_F
         ok(lib.me_destroy(h))
-elif scenario == "batch":
+elif scenario in ("batch", "batch_xt"):
+    # batch_xt runs with MODEHR_BATCH_TX=16: every system wider than 16 points
+    # in 16-point x-tiles (ragged for 20, 24 and 40)
     arr = (B.Params * len(UNEVEN))()
     keep, inps = [], []
     for i, c in enumerate(UNEVEN):
@@ -168,8 +172,10 @@ elif scenario == "batch":
         tt = B.BatchTuning()
         ok(lib.me_batch_autotune(h, os.path.join(tmp, "tune.json").encode(), ctypes.byref(tt)), h, True)
     ok(lib.me_batch_destroy(h))
-elif scenario == "adjoint":
-    c = W.C1.replace(freeze_ions=True, coarse_n=4, control_sigma=0.01, steps=4, seed=901)
+elif scenario in ("adjoint", "adjoint_xt"):
+    # adjoint_xt: a 20^3 grid, so that the forced 16 x 8 x-tiles are ragged
+    c = W.C1.replace(freeze_ions=True, coarse_n=4, control_sigma=0.01, steps=4, seed=901,
+                     n=20 if scenario == "adjoint_xt" else 16)
     inp = W.make_inputs(c)
     dv = 0.01 * np.random.default_rng(0).standard_normal((4, 4, 4))
     J0, ge0, gv0 = adjoint.gradient(Model.from_config(c), inp["psi"], inp["pos"], inp["ctrl"], dv)
@@ -356,6 +362,50 @@ elif scenario == "toy":
     assert lib.me_toy_run(ctypes.byref(bad), 0, 1, ns, T, 1, dp(z), dp(z), dp(z), None, dp(z), dp(z), stream) == B.ME_EINVAL
     assert lib.me_toy_run(ctypes.byref(tp), 0, 1, 1 << 12, T, 1 << 13, dp(z), dp(z), dp(z), None, dp(z), dp(z),
                           stream) == B.ME_EINVAL
+elif scenario == "c2_sequence":
+    # the benchmark's call sequence on the 96^3 workload (its grid, its 64
+    # ions and projector tables, 2 of its 128 orbitals): state, one step
+    # (sampled against the oracle), 3 warm-up steps, timing on, 6 steps (every
+    # phase of the table / buffer / history rotation), timing read, timing
+    # off, report, destroy, then the workspace released while the runtime
+    # stays live
+    c = W.C2.replace(n_orb=2)
+    inp = W.make_inputs(c)
+    h = new_system(c, inp)
+    ws_holder = len(held) - 1                # new_system's last buffer is the workspace
+    psi0 = orbitals(c, inp)
+    held.append(psi0)
+    ok(lib.me_set_state(h, psi0.ctypes.data, c.n_points), h)
+    ok(lib.me_propagate_step(h, None, None), h)
+    got, _ = state(h, c)
+    m = Model.from_config(c)
+    st = dynamics.init_state(m, inp["psi"], inp["pos"])
+    pos1, h0, h1 = dynamics.step_hamiltonians(m, st)
+    ref = dynamics.propagate_orbitals(m, inp["psi"], h0, h1).reshape(c.n_orb, -1)
+    d1 = float(np.abs(got - ref).max())
+    print(f"c2_sequence: one step max|dpsi| {d1:.2e}", flush=True)
+    assert d1 <= TOL_PSI * 10
+    for _ in range(3):
+        ok(lib.me_propagate_step(h, None, None), h)
+    ok(lib.me_timing_enable(h, 1), h)
+    for _ in range(6):
+        ok(lib.me_propagate_step(h, None, None), h)
+    n_, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    ok(lib.me_timing_read(h, ctypes.byref(n_), ctypes.byref(ms), ctypes.byref(by)), h)
+    assert n_.value == 6 * 2 * 4, n_.value
+    ok(lib.me_timing_enable(h, 0), h)
+    rep = B.StepReport()
+    ok(lib.me_report(h, ctypes.byref(rep)), h)
+    print(f"c2_sequence: 10 steps, max norm deviation {rep.max_norm_dev:.2e}", flush=True)
+    assert rep.max_norm_dev < 1e-5
+    ok(lib.me_destroy(h))
+    # the workspace goes back to the allocator (ASan poisons it): any access
+    # that outlived the handle would now be reported
+    del held[ws_holder]
+    import gc
+    gc.collect()
+    ok(lib.me_dipole_noalloc(ctypes.c_void_p(np.zeros(8).ctypes.data), (ctypes.c_int32 * 3)(2, 2, 2), 0.3,
+                             ctypes.c_void_p(np.zeros(1).ctypes.data), stream))
 elif scenario == "noalloc":
     # the dipole with its partials in the library's fixed array: the same
     # bits as me_dipole on a system's density, then a smaller, non-cubic

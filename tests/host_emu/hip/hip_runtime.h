@@ -141,6 +141,11 @@ inline emu_f32x4 emu_mfma_f32_16x16x32_bf16(emu_bf16x8 a, emu_bf16x8 b, emu_f32x
     return r;
 }
 #define __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, cbsz, abid, blgp) emu_mfma_f32_16x16x32_bf16(a, b, c)
+// a wave barrier is a rendezvous of the wave's live lanes (any wave operation
+// is one); waiting for memory counters has nothing to wait for here
+inline void emu_wave_barrier() { (void)__ballot(1); }
+#define __builtin_amdgcn_wave_barrier() emu_wave_barrier()
+#define __builtin_amdgcn_s_waitcnt(x) ((void)0)
 
 // runtime API (emu.cpp)
 hipError_t hipStreamCreateWithFlags(hipStream_t*, unsigned);

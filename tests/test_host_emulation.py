@@ -24,7 +24,9 @@ ASAN_RT = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asa
 
 SCENARIOS = [("system", "f64"), ("system", "f32"), ("system", "f32_bf16x3"), ("batch", "f64"),
              ("batch", "f32"), ("adjoint", "f64"), ("adjoint", "f32"), ("cp", "f64"), ("cp", "f32"),
-             ("etrs", "f64"), ("toy", "f64"), ("finite", "f64"), ("finite", "f32"), ("noalloc", "f64")]
+             ("etrs", "f64"), ("toy", "f64"), ("finite", "f64"), ("finite", "f32"), ("noalloc", "f64"), ("system_xt", "f64"), ("system_xt", "f32"),
+             ("adjoint_xt", "f64"), ("c2_sequence", "f32"), ("c2_sequence", "f32_bf16x3"), ("batch_xt", "f64"),
+             ("batch_xt", "f32")]
 
 pytestmark = pytest.mark.skipif(not (os.path.exists(CLANG) and ASAN_RT), reason="needs ROCm clang++ and its ASan runtime")
 
@@ -62,8 +64,10 @@ def results(tmp_path_factory):
     for sc, prec in SCENARIOS:
         wd = os.path.join(d, f"{sc}_{prec}")
         os.makedirs(wd, exist_ok=True)
+        # the _xt scenarios force the x-tiled stencil (16 x 8 tiles) on their grids
+        env_sc = dict(env, MODEHR_TX="16", MODEHR_TY="8", MODEHR_BATCH_TX="16") if sc.endswith("_xt") else env
         procs[(sc, prec)] = subprocess.Popen([sys.executable, "-u", os.path.join(EMU, "drive.py"), lib, sc, prec, wd],
-                                             stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
+                                             stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env_sc)
     out = {}
     for k, p in procs.items():
         try:
