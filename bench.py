@@ -26,6 +26,10 @@ the cost of one atomic unit of simulated time for both schemes.
 ``--cp-series`` adds the system-size series (grids 48^3 to 128^3, orbitals
 and ions in proportion to the volume) behind the cost crossover.
 
+A fourth (``precision_study_128``) times the 128^3 x 432-orbital workload of
+the precision study in FP32, FP32 with the split-bf16 projector contraction
+and FP64 (its errors against the FP64 oracle are a GPU test).
+
 Prints one JSON line.  --gpus N > 1 is refused: the benchmark runs on one GPU.
 """
 from __future__ import annotations
@@ -262,6 +266,52 @@ def run_adjoint(every: int = 10):
             "J": float(J), "grad_eps_norm": float(c.grad.norm())}
 
 
+def run_c4(steps: int = 6, warmup: int = 2, precisions=("f32", "f32_bf16x3", "f64")) -> dict:
+    """The precision-study workload (128^3 grid, 216 ions on a jittered
+    lattice, 432 orbitals, mu = 4, dt = 0.08, moving ions): time per MD step
+    in each precision and the three-stream Horner stage's rate.  Orbitals
+    drawn on the device (same recipe, torch's generator)."""
+    import torch
+    import workloads as W
+    from paper_0812_2801_amd import binding as B
+    cfg = W.C4
+    psi = W.initial_orbitals_device(cfg, "cuda:0")
+    pos = W.ion_positions(cfg)
+    out = {"workload": "128^3 grid h=0.25, 216 ions Z=4 (jittered 6^3 lattice), 432 complex orbitals, mu=4, "
+                       "dt=0.08, AETRS+Taylor-4, moving ions, whole MD step"}
+    work = cfg.n_orb * cfg.n_points * 8
+    for prec in precisions:
+        p, keep = B.params_from_config(cfg, pos, precision=prec)
+        s = B.System(p, keep, device="cuda:0")
+        s.set_state(psi)
+        for _ in range(warmup):
+            s.step()
+        s.sync()
+        s.timing_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.sync()
+        n3, ms3, by3 = s.timing_read(3)
+        s.timing_enable(False)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        ms = (t1 - t0) * 1e3 / steps
+        out[prec] = {"ms_per_step": ms, "value": work / (ms * 1e-3),
+                     "stencil_three_stream": {"kernel_avg_ms": ms3 / max(1, n3),
+                                              "achieved_GBps": (by3 / max(1, n3)) / (ms3 / max(1, n3) * 1e-3) / 1e9}}
+        print(f"# c4 {prec}: {ms:.2f} ms/step", file=sys.stderr, flush=True)
+    del psi
+    torch.cuda.empty_cache()
+    if "f64" in out and "f32" in out:
+        out["speedup_f32_vs_f64"] = out["f64"]["ms_per_step"] / out["f32"]["ms_per_step"]
+    return out
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -483,6 +533,9 @@ def main():
                     help="only the propagator / force variants (ETRS, gradient-form force) on the 96^3 workload")
     ap.add_argument("--finite", action="store_true",
                     help="only the finite-box workload (union of atom-centred spheres, free-space Hartree)")
+    ap.add_argument("--c4-only", action="store_true",
+                    help="run only the 128^3 x 432 precision-study workload (profiling)")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 128^3 x 432 workload")
     ap.add_argument("--toy", action="store_true",
                     help="only the two-band toy-model sweep (d_R, d_F, Delta t_max against the mass)")
     args = ap.parse_args()
@@ -505,6 +558,9 @@ def main():
         return
     if args.toy:
         print(json.dumps({"toy_model": run_toy(not args.no_cpu)}))
+        return
+    if args.c4_only:
+        print(json.dumps({"precision_study_128": run_c4(args.steps, args.warmup)}))
         return
     if args.dt_scan:
         from paper_0812_2801_amd import scan
@@ -547,6 +603,10 @@ def main():
     if not args.no_cp:
         cp_run = run_cp(args.cp_steps, main_run["ms_per_step"], args.cp_series)
         print(f"# cp: {cp_run['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+
+    c4 = None
+    if not args.no_c4:
+        c4 = run_c4()
 
     adj = None
     if not args.no_adjoint:
@@ -643,6 +703,8 @@ def main():
                              "stencil_avg_ms": bf_run["kernel_ms"] / max(1, bf_run["launches"])}
     if adj is not None:
         out["adjoint"] = adj
+    if c4 is not None:
+        out["precision_study_128"] = c4
     if cp_run is not None:
         out["cp"] = cp_run
     if batch is not None:

@@ -95,6 +95,7 @@ struct Geometry {
     size_t br;        // bytes per real of the compute precision
     int px, ty, nyt, zchunk, nzc;
     int tx, nxt;       // stencil tile width (nx: whole rows) and x-tiles
+    int py;            // whole-row tiles: rows per thread
     int64_t norm_cap;  // norm partials per orbital (this kernel's tiles, or a batch's)
     int kcap;
     int64_t ucap;      // upper bound of projector-covered grid points
@@ -148,12 +149,18 @@ int choose_ty(int nx, int ny, int px, size_t bc) {
     return -1;
 }
 
-// Stencil tile: whole x-rows (choose_ty) up to 96 points per row in FP32;
-// wider rows take x-tiles of 64 points and 12 rows (768 threads, an x-halo of
-// 4 + 4 points in LDS), which keeps the y-halo at 8 rows per 12 instead of 8
-// per 4.  MODEHR_TX / MODEHR_TY select another compiled shape (64x12, 48x16,
-// 32x24, 16x8) or, with MODEHR_TX=0, whole rows (measurements and tests).
-void choose_tile(int nx, int ny, int px, size_t bc, int* tx, int* ty) {
+// Stencil tile.  FP64, and FP32 rows of up to 96 points: whole x-rows,
+// choose_ty rows, one row per thread.  FP32 rows of 97-256 points: whole
+// rows, tiles of 8 rows with two rows per thread (4 thread rows, so 128-point
+// rows give 512-thread workgroups, two per CU at the kernel's 120 VGPRs);
+// measured at 128^3: 4.18 ms per three-stream stage against 4.43 for x-tiles
+// and 4.35 for 4 whole rows of one per thread.  Wider FP32 rows: x-tiles of 64
+// points and 12 rows (an x-halo of 4 + 4 points in LDS).  MODEHR_TX /
+// MODEHR_TY select an x-tile shape (64x12, 48x16, 32x24, 16x8; MODEHR_TX=0:
+// whole rows, one per thread) and MODEHR_PY=2 / MODEHR_PY_TY two rows per
+// thread with 8 or 16 rows per tile (measurements and tests).
+void choose_tile(int nx, int ny, int px, size_t bc, int* tx, int* ty, int* py) {
+    *py = 1;
     const char* ev = std::getenv("MODEHR_TX");
     if (ev && *ev) {
         const int ftx = std::atoi(ev);
@@ -164,6 +171,16 @@ void choose_tile(int nx, int ny, int px, size_t bc, int* tx, int* ty) {
         }
         *tx = nx;
         *ty = choose_ty(nx, ny, px, bc);
+        return;
+    }
+    const int fpy = env_int("MODEHR_PY", 0);
+    const int pty = fpy == 2 ? env_int("MODEHR_PY_TY", 8) : 8;
+    const bool py_fits = (pty == 8 || pty == 16) && ny % pty == 0 && nx * pty / 2 <= 1024 &&
+                         stencil_lds_bytes(pty, nx, bc) <= STENCIL_LDS_MAX;
+    if (py_fits && (fpy == 2 || (fpy == 0 && bc == 8 && nx > 96))) {
+        *tx = nx;
+        *ty = pty;
+        *py = 2;
         return;
     }
     if (bc == 8 && nx > 96) {
@@ -243,7 +260,7 @@ Geometry make_geometry(const me_params* p) {
     g.bc = g.f64 ? 16 : 8;
     g.br = g.f64 ? 8 : 4;
     g.px = choose_px(g.nx, g.f64);
-    choose_tile(g.nx, g.ny, g.px, g.bc, &g.tx, &g.ty);
+    choose_tile(g.nx, g.ny, g.px, g.bc, &g.tx, &g.ty, &g.py);
     g.nxt = (g.nx + g.tx - 1) / g.tx;
     g.nyt = (g.ny + g.ty - 1) / g.ty;
     g.zchunk = choose_zchunk(g.nz, (int64_t)g.n_orb * g.nxt * g.nyt);
@@ -719,6 +736,7 @@ StencilArgs<T> base_args(me_system* sys, const T* v, int n_orb) {
     a.nyt = g.nyt;
     a.tx = g.tx;
     a.nxt = g.nxt;
+    a.py = g.py;
     a.nzc = g.nzc;
     a.kin = (T)(-0.5 / (sys->prm.h * sys->prm.h));
     return a;

@@ -86,6 +86,7 @@ struct StencilArgs {
     int zchunk;              // planes per workgroup (the last chunk may be shorter)
     int nyt, nzc;            // tiles along y, chunks along z
     int tx, nxt;             // tile width (nx: whole rows) and tiles along x
+    int py;                  // whole rows: rows per thread (1 or 2)
     T kin;                   // -1/(2 h^2)
     T alpha;                 // Horner coefficient: c_k = i*alpha, alpha = -tau/k
     double* partial;         // [n_orb][nyt*nzc] norm or expectation partials, or nullptr

@@ -320,6 +320,180 @@ __device__ __forceinline__ double zmarch(const cx_t<T>* __restrict__ u, const cx
     return acc;
 }
 
+// Whole-row z-march with PY rows per thread: the tile is TY rows, the
+// threads cover TY / PY of them, and thread (tx, ty) owns rows y0 + ty + p
+// (TY / PY) for p < PY (so a wave's loads stay contiguous rows).  Each owned
+// point keeps its own z-queue; the LDS tile, the halo jobs and the pipeline
+// are zmarch's.  Taller tiles for the same thread count halve the y-halo rows
+// per output row (8 per TY instead of 8 per TY / PY).
+template <typename T, int TY, int PY, int MODE, bool NORM>
+__device__ __forceinline__ double zmarch_py(const cx_t<T>* __restrict__ u, const cx_t<T>* __restrict__ p0,
+                                            cx_t<T>* __restrict__ out, const T* __restrict__ v, int nx,
+                                            int ny, int nz, int y0, int z0, int z1, T kin, T alpha,
+                                            cx_t<T>* tiles) {
+    using C = cx_t<T>;
+    constexpr int D = Pipe<T>::D;
+    constexpr int HL = Pipe<T>::HL;
+    constexpr int TR = TY / PY;                       // thread rows
+    constexpr int HJ = (8 + TR - 1) / TR;             // halo runs per thread
+    constexpr bool HORNER = MODE == MODE_HORNER;
+    constexpr bool NEEDV = MODE != MODE_EXPECT_T;
+    static_assert(TY % PY == 0, "rows per thread must divide the tile");
+
+    const int tid = threadIdx.x;
+    const int tx = tid % nx;
+    const int ty = tid / nx;
+    const int plane = nx * ny;
+    const int tile_elems = (TY + 8) * nx;
+
+    const T c0 = (T)(3.0 * FD_C0);
+    const T cm[4] = {(T)FD_C1, (T)FD_C2, (T)FD_C3, (T)FD_C4};
+
+    int xo[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) xo[i] = (ty + 4) * nx + wrap1(tx - 4 + i, nx);
+    int rowoff[PY];
+#pragma unroll
+    for (int p = 0; p < PY; ++p) rowoff[p] = (y0 + ty + p * TR) * nx + tx;
+    const int yo = (ty + 4) * nx + tx;
+
+    const int n_halo = 8 * nx;
+    int h_lds[HJ], h_off[HJ];
+    bool h_ok[HJ];
+#pragma unroll
+    for (int i = 0; i < HJ; ++i) {
+        const int j = tid + i * (int)blockDim.x;
+        h_ok[i] = j < n_halo;
+        const int r = h_ok[i] ? j / nx : 0;
+        const int xr = h_ok[i] ? j - r * nx : 0;
+        const int lr = r < 4 ? r : TY + r;
+        const int gy = wrap1(r < 4 ? y0 - 4 + r : y0 + TY + (r - 4), ny);
+        h_lds[i] = lr * nx + xr;
+        h_off[i] = gy * nx + xr;
+    }
+
+    C q[PY][9 + D];
+    C hq[HL + 1][HJ];
+    C pq[PY][D + 1];
+    T vq[PY][D + 1];
+#pragma unroll
+    for (int p = 0; p < PY; ++p)
+#pragma unroll
+        for (int k = 0; k < 8 + D; ++k) q[p][k] = u[wrap1(z0 - 4 + k, nz) * plane + rowoff[p]];
+#pragma unroll
+    for (int d = 0; d < HL; ++d) {
+        if (z0 + d < z1) {
+            const int zo = (z0 + d) * plane;
+#pragma unroll
+            for (int i = 0; i < HJ; ++i)
+                if (h_ok[i]) hq[d][i] = u[zo + h_off[i]];
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        if (z0 + d < z1) {
+            const int zo = (z0 + d) * plane;
+#pragma unroll
+            for (int p = 0; p < PY; ++p) {
+                if constexpr (HORNER) load_once<T, 1>(p0 + zo + rowoff[p], &pq[p][d]);
+                if constexpr (NEEDV) vq[p][d] = v[zo + rowoff[p]];
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < PY; ++p) tiles[yo + p * TR * nx] = q[p][4];
+#pragma unroll
+    for (int i = 0; i < HJ; ++i)
+        if (h_ok[i]) tiles[h_lds[i]] = hq[0][i];
+    __syncthreads();
+
+    double acc = 0.0;
+    for (int z = z0; z < z1; ++z) {
+        const int buf = (z - z0) & 1;
+        if (z + HL < z1) {
+            const int zo = (z + HL) * plane;
+#pragma unroll
+            for (int i = 0; i < HJ; ++i)
+                if (h_ok[i]) hq[HL][i] = u[zo + h_off[i]];
+        }
+        if (z + D < z1) {
+            const int zo = (z + D) * plane;
+            const int zq = wrap1(z + 4 + D, nz) * plane;
+#pragma unroll
+            for (int p = 0; p < PY; ++p) {
+                q[p][8 + D] = u[zq + rowoff[p]];
+                if constexpr (HORNER) load_once<T, 1>(p0 + zo + rowoff[p], &pq[p][D]);
+                if constexpr (NEEDV) vq[p][D] = v[zo + rowoff[p]];
+            }
+        }
+        const C* tile = tiles + buf * tile_elems;
+#pragma unroll
+        for (int p = 0; p < PY; ++p) {
+            const int po = p * TR * nx;
+            const C ctr = q[p][4];
+            T sre = c0 * ctr.x, sim = c0 * ctr.y;
+#pragma unroll
+            for (int m = 1; m <= 4; ++m) {
+                const C xp = tile[po + xo[4 + m]];
+                const C xm = tile[po + xo[4 - m]];
+                const C yp = tile[po + yo + m * nx];
+                const C ym = tile[po + yo - m * nx];
+                const C zp = q[p][4 + m];
+                const C zm = q[p][4 - m];
+                sre += cm[m - 1] * (((xp.x + xm.x) + (yp.x + ym.x)) + (zp.x + zm.x));
+                sim += cm[m - 1] * (((xp.y + xm.y) + (yp.y + ym.y)) + (zp.y + zm.y));
+            }
+            const T tre = kin * sre, tim = kin * sim;
+            if constexpr (MODE == MODE_EXPECT_T) {
+                acc += (double)ctr.x * (double)tre + (double)ctr.y * (double)tim;
+            } else {
+                const T vv = vq[p][0];
+                // v_eff = +inf marks points outside a finite box, where H psi is zero
+                const bool inb = vv < (T)INFINITY;
+                const T hre = inb ? tre + vv * ctr.x : (T)0;
+                const T him = inb ? tim + vv * ctr.y : (T)0;
+                C res;
+                if constexpr (MODE == MODE_APPLY) {
+                    res = C{hre, him};
+                } else if constexpr (MODE == MODE_SCALED) {
+                    res = C{-alpha * him, alpha * hre};
+                } else {
+                    const C base = HORNER ? pq[p][0] : ctr;
+                    res = C{base.x - alpha * him, base.y + alpha * hre};
+                }
+                if constexpr (NORM) acc += (double)res.x * (double)res.x + (double)res.y * (double)res.y;
+                store_out<T, 1>(out + z * plane + rowoff[p], &res);
+            }
+        }
+
+        if (z + 1 < z1) {
+            C* nt = tiles + (buf ^ 1) * tile_elems;
+#pragma unroll
+            for (int p = 0; p < PY; ++p) nt[yo + p * TR * nx] = q[p][5];
+#pragma unroll
+            for (int i = 0; i < HJ; ++i)
+                if (h_ok[i]) nt[h_lds[i]] = hq[1][i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < PY; ++p)
+#pragma unroll
+            for (int k = 0; k < 8 + D; ++k) q[p][k] = q[p][k + 1];
+#pragma unroll
+        for (int d = 0; d < HL; ++d)
+#pragma unroll
+            for (int i = 0; i < HJ; ++i) hq[d][i] = hq[d + 1][i];
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+#pragma unroll
+            for (int p = 0; p < PY; ++p) {
+                if constexpr (HORNER) pq[p][d] = pq[p][d + 1];
+                if constexpr (NEEDV) vq[p][d] = vq[p][d + 1];
+            }
+    }
+    return acc;
+}
+
 // x-tiled z-march: the workgroup owns cols <= TX consecutive points of each
 // of rows <= TY consecutive y-rows, starting at (x0, y0) (the last tile of
 // a row or column may be narrower), so the tile height no longer falls as
@@ -533,6 +707,36 @@ stencil_kernel(const cx_t<T>* __restrict__ u_all, const cx_t<T>* __restrict__ p0
     const double acc = zmarch<T, PX, TY, 1, MODE, NORM>(
         u_all + (int64_t)A * a.stride, p0_all + (int64_t)A * a.stride, out_all + (int64_t)A * a.stride, v,
         a.nx, a.ny, a.nz, TY, ytile * TY, TY, z0, z1, a.kin, a.alpha, tiles, true);
+    if constexpr (NORM || MODE == MODE_EXPECT_T) {
+        const double s = block_sum(acc, red);
+        if (threadIdx.x == 0) partial[(int64_t)A * (a.nyt * a.nzc) + zc * a.nyt + ytile] = s;
+    }
+}
+
+// One system, whole rows, PY rows per thread: a workgroup of nx * TY / PY
+// threads per (orbital, y-tile of TY rows, z-chunk).
+template <typename T, int TY, int PY, int MODE, bool NORM>
+__global__ void __launch_bounds__(1024) STENCIL_ATTR
+stencil_py_kernel(const cx_t<T>* __restrict__ u_all, const cx_t<T>* __restrict__ p0_all,
+                  cx_t<T>* __restrict__ out_all, const T* __restrict__ v, double* __restrict__ partial,
+                  StencilArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx_t<T>* tiles = reinterpret_cast<cx_t<T>*>(smem_raw);     // 2 x [(TY+8)][nx]
+    __shared__ double red[16];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int ytile = b % a.nyt;
+    const int rest = b / a.nyt;
+    const int zc = rest % a.nzc;
+    const int A = rest / a.nzc;
+    int z0 = zc * a.zchunk, z1 = z0 + a.zchunk;
+    if (a.zr != nullptr) {          // finite box: only the planes where the tile's rows meet it
+        const int2 r = a.zr[ytile];
+        z0 = max(z0, r.x);
+        z1 = max(z0, min(z1, r.y));
+    }
+    const double acc = zmarch_py<T, TY, PY, MODE, NORM>(
+        u_all + (int64_t)A * a.stride, p0_all + (int64_t)A * a.stride, out_all + (int64_t)A * a.stride, v,
+        a.nx, a.ny, a.nz, ytile * TY, z0, z1, a.kin, a.alpha, tiles);
     if constexpr (NORM || MODE == MODE_EXPECT_T) {
         const double s = block_sum(acc, red);
         if (threadIdx.x == 0) partial[(int64_t)A * (a.nyt * a.nzc) + zc * a.nyt + ytile] = s;
@@ -780,10 +984,39 @@ static hipError_t launch_xt(const StencilArgs<T>& a, int mode, bool norm, hipStr
     return hipGetLastError();
 }
 
+template <typename T, int TY, int PY>
+static hipError_t launch_py(const StencilArgs<T>& a, int mode, bool norm, hipStream_t s) {
+    dim3 block(a.nx * TY / PY);
+    dim3 grid((unsigned)((int64_t)a.n_orb * a.nyt * a.nzc));
+    const size_t lds = 2 * (size_t)(TY + 8) * a.nx * sizeof(cx_t<T>);
+#define ME_STENCIL(M, NORM) \
+    stencil_py_kernel<T, TY, PY, M, NORM><<<grid, block, lds, s>>>(a.u, a.psi0, a.out, a.v, a.partial, a)
+    switch (mode) {
+    case MODE_APPLY: ME_STENCIL(MODE_APPLY, false); break;
+    case MODE_HORNER:
+        if (norm) ME_STENCIL(MODE_HORNER, true); else ME_STENCIL(MODE_HORNER, false);
+        break;
+    case MODE_HORNER_FIRST:
+        if (norm) ME_STENCIL(MODE_HORNER_FIRST, true); else ME_STENCIL(MODE_HORNER_FIRST, false);
+        break;
+    case MODE_EXPECT_T: ME_STENCIL(MODE_EXPECT_T, false); break;
+    case MODE_SCALED: ME_STENCIL(MODE_SCALED, false); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef ME_STENCIL
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_stencil(const StencilArgs<T>& a, int mode, bool want_norm, int ty, int px,
                           hipStream_t s) {
     if (px != 1) return hipErrorInvalidValue;
+    if (a.py == 2 && a.tx == a.nx) {   // whole rows, two rows per thread
+        if (a.nyt * ty != a.ny || (int64_t)a.nx * ty / 2 > 1024) return hipErrorInvalidValue;
+        if (ty == 16) return launch_py<T, 16, 2>(a, mode, want_norm, s);
+        if (ty == 8) return launch_py<T, 8, 2>(a, mode, want_norm, s);
+        return hipErrorInvalidValue;
+    }
     if (a.tx != a.nx) {             // x-tiles: the tile shape is one of the compiled ones
         if (a.tx < 1 || a.nxt * a.tx < a.nx || a.nyt * ty < a.ny) return hipErrorInvalidValue;
         if (a.tx == 64 && ty == 12) return launch_xt<T, 64, 12>(a, mode, want_norm, s);

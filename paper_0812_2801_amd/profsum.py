@@ -28,7 +28,19 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 STENCIL_SRC = os.path.join(HERE, "csrc", "stencil.hip")
 
-HORNER_TAGS = (", 1, false>", ", 1, true>", ", 2, false>", ", 2, true>")
+HORNER_MODES = ("1", "2")       # template MODE of the Horner stages (HORNER, HORNER_FIRST)
+
+
+def is_horner_stage(name: str) -> bool:
+    """A Horner-stage launch of one of the stencil kernels (single system,
+    x-tiled, batched); the MODE argument is the one before the NORM flag."""
+    if not any(k in name for k in ("stencil_kernel<", "stencil_xt_kernel<")):
+        return False
+    args = name.split("<", 1)[1].split(">", 1)[0].split(",")
+    args = [a.strip() for a in args]
+    if "batch_stencil_kernel<" in name:          # <T, HJ, MODE, NORM, XT>
+        return len(args) >= 3 and args[2] in HORNER_MODES
+    return len(args) >= 2 and args[-2] in HORNER_MODES   # <T, ..., MODE, NORM>
 
 
 def stencil_hash() -> str:
@@ -68,7 +80,7 @@ def traffic(fetch_dir, write_dir, cf_dir, cw_dir, copy_bytes, out, command):
                 agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
         return agg
 
-    is_stage = lambda k: "stencil_kernel" in k and any(t in k for t in HORNER_TAGS)
+    is_stage = is_horner_stage
     is_copy = lambda k: "copyBuffer" in k
     f = per_kernel(fetch_dir, is_stage)
     w = per_kernel(write_dir, is_stage)

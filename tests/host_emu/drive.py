@@ -88,7 +88,9 @@ UNEVEN = [
     W.C1.replace(name="b3", n=40, h=0.25, n_orb=2, n_ions=3, placement="lattice", jitter=0.2, seed=1004),
 ]
 
-if scenario in ("system", "system_xt"):
+if scenario in ("system", "system_xt", "system_py"):
+    # system_py runs with MODEHR_PY=2 MODEHR_PY_TY=8: the 16^3 case in tiles of
+    # 8 whole rows, two rows per thread
     # system_xt runs with MODEHR_TX=16 MODEHR_TY=8: the 20^3 case in x-tiles,
     # ragged along x (16 + 4) and y (8 + 8 + 4)
     # 20^3 with 5 orbitals and 5 ions: a tile height of 4 rows, an odd

@@ -26,7 +26,7 @@ SCENARIOS = [("system", "f64"), ("system", "f32"), ("system", "f32_bf16x3"), ("b
              ("batch", "f32"), ("adjoint", "f64"), ("adjoint", "f32"), ("cp", "f64"), ("cp", "f32"),
              ("etrs", "f64"), ("toy", "f64"), ("finite", "f64"), ("finite", "f32"), ("noalloc", "f64"), ("system_xt", "f64"), ("system_xt", "f32"),
              ("adjoint_xt", "f64"), ("c2_sequence", "f32"), ("c2_sequence", "f32_bf16x3"), ("batch_xt", "f64"),
-             ("batch_xt", "f32")]
+             ("batch_xt", "f32"), ("system_py", "f64"), ("system_py", "f32")]
 
 pytestmark = pytest.mark.skipif(not (os.path.exists(CLANG) and ASAN_RT), reason="needs ROCm clang++ and its ASan runtime")
 
@@ -66,6 +66,8 @@ def results(tmp_path_factory):
         os.makedirs(wd, exist_ok=True)
         # the _xt scenarios force the x-tiled stencil (16 x 8 tiles) on their grids
         env_sc = dict(env, MODEHR_TX="16", MODEHR_TY="8", MODEHR_BATCH_TX="16") if sc.endswith("_xt") else env
+        # the _py scenarios force whole-row tiles of 8 rows with two rows per thread
+        env_sc = dict(env_sc, MODEHR_PY="2", MODEHR_PY_TY="8") if sc.endswith("_py") else env_sc
         procs[(sc, prec)] = subprocess.Popen([sys.executable, "-u", os.path.join(EMU, "drive.py"), lib, sc, prec, wd],
                                              stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env_sc)
     out = {}
