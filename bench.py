@@ -536,6 +536,8 @@ def main():
     ap.add_argument("--c4-only", action="store_true",
                     help="run only the 128^3 x 432 precision-study workload (profiling)")
     ap.add_argument("--no-c4", action="store_true", help="skip the 128^3 x 432 workload")
+    ap.add_argument("--c4-precisions", default="f32,f32_bf16x3,f64",
+                    help="comma-separated precisions of the 128^3 x 432 workload")
     ap.add_argument("--toy", action="store_true",
                     help="only the two-band toy-model sweep (d_R, d_F, Delta t_max against the mass)")
     args = ap.parse_args()
@@ -560,7 +562,8 @@ def main():
         print(json.dumps({"toy_model": run_toy(not args.no_cpu)}))
         return
     if args.c4_only:
-        print(json.dumps({"precision_study_128": run_c4(args.steps, args.warmup)}))
+        print(json.dumps({"precision_study_128": run_c4(args.steps, args.warmup,
+                                                        tuple(args.c4_precisions.split(",")))}))
         return
     if args.dt_scan:
         from paper_0812_2801_amd import scan

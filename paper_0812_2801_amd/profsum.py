@@ -34,7 +34,7 @@ HORNER_MODES = ("1", "2")       # template MODE of the Horner stages (HORNER, HO
 def is_horner_stage(name: str) -> bool:
     """A Horner-stage launch of one of the stencil kernels (single system,
     x-tiled, batched); the MODE argument is the one before the NORM flag."""
-    if not any(k in name for k in ("stencil_kernel<", "stencil_xt_kernel<")):
+    if not any(k in name for k in ("stencil_kernel<", "stencil_xt_kernel<", "stencil_py_kernel<")):
         return False
     args = name.split("<", 1)[1].split(">", 1)[0].split(",")
     args = [a.strip() for a in args]
