@@ -475,6 +475,14 @@ struct me_system {
     rocblas_handle blas = nullptr;
     double mu_cp = 0.0, dt_cp = 0.0;
     bool cp_ready = false;
+    // Work of an MD step that the first exponential does not wait for (ions
+    // moved, V_loc and projector tables at R(t+dt), v_eff of the second
+    // exponential, the Ewald sum) runs on `side`, and the nonlocal forces run
+    // there beside the density and Hartree chain; events order both streams
+    // (default priority, created at init; null when MODEHR_OVERLAP=0).
+    hipStream_t side = nullptr;
+    rocfft_execution_info info_side = nullptr;   // FFTs enqueued on `side`
+    hipEvent_t ev_fork[2] = {nullptr, nullptr}, ev_join[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -502,6 +510,22 @@ namespace {
         me_status s_ = (expr);                                                         \
         if (s_ != ME_OK) return s_;                                                    \
     } while (0)
+
+// Enqueue the launches of a scope on the side stream: the helpers take
+// sys->stream and sys->info, so both are switched and restored on exit.
+struct OnSide {
+    me_system* s;
+    hipStream_t st;
+    rocfft_execution_info inf;
+    explicit OnSide(me_system* s_) : s(s_), st(s_->stream), inf(s_->info) {
+        s->stream = s->side;
+        s->info = s->info_side;
+    }
+    ~OnSide() {
+        s->stream = st;
+        s->info = inf;
+    }
+};
 
 KbTables tables(me_system* sys, int t) {
     KbTables k{};
@@ -682,9 +706,11 @@ me_status density_vhxc(me_system* sys, bool energy, bool push = true) {
     return ME_OK;
 }
 
-// forces at `pos` (phases of `pos` already in w.phase, tables t at pos);
-// partial results in floc_part, fnl, fion
-me_status forces_parts(me_system* sys, const double* pos, int t) {
+// forces at `pos` (phases of `pos` already in w.phase, tables t at pos), in
+// three independent parts: local (from the density's spectrum), nonlocal
+// (from the orbitals) and ion-ion; partial results in floc_part / floc, fnl /
+// enl_part, fion / eion_part
+me_status local_forces_part(me_system* sys, const double* pos) {
     const Geometry& g = sys->g;
     const double L[3] = {g.nx * sys->prm.h, g.ny * sys->prm.h, g.nz * sys->prm.h};
     if (g.finite)
@@ -693,6 +719,11 @@ me_status forces_parts(me_system* sys, const double* pos, int t) {
     else
         HIPCHK(launch_local_forces(sys->w.rhok, sys->w.phaseT, sys->w.zval, g.n_ions, g.nx, g.ny, g.nz, L,
                                    sys->prm.h, sys->prm.loc_a, sys->w.floc_part, sys->w.floc, sys->stream));
+    return ME_OK;
+}
+
+me_status nl_forces_part(me_system* sys, const double* pos, int t) {
+    const Geometry& g = sys->g;
     if (g.f64)
         HIPCHK(launch_kb_forces<double>((const double2*)sys->w.psi, g.stride, g.n_orb, g.n_ions, tables(sys, t), pos,
                                         sys->geo, g.nx, g.ny, g.nz, sys->prm.nl_force_form, sys->prm.occ, sys->prm.kb_energy, sys->w.fnl,
@@ -705,12 +736,23 @@ me_status forces_parts(me_system* sys, const double* pos, int t) {
         HIPCHK(launch_kb_forces<float>((const float2*)sys->w.psi, g.stride, g.n_orb, g.n_ions, tables(sys, t), pos,
                                        sys->geo, g.nx, g.ny, g.nz, sys->prm.nl_force_form, sys->prm.occ, sys->prm.kb_energy, sys->w.fnl,
                                        sys->w.enl_part, sys->w.kbf_part, sys->stream));
+    return ME_OK;
+}
+
+me_status ion_forces_part(me_system* sys, const double* pos) {
+    const Geometry& g = sys->g;
     if (g.finite)
         HIPCHK(launch_ion_coulomb(pos, sys->w.zval, g.n_ions, sys->w.fion, sys->w.eion_part, sys->stream));
     else
         HIPCHK(launch_ewald(sys->ewp, pos, sys->w.zval, g.n_ions, sys->w.ewald_sg, sys->w.erec_part, sys->w.fion,
                             sys->w.eion_part, sys->w.ewald_part, sys->stream));
     return ME_OK;
+}
+
+me_status forces_parts(me_system* sys, const double* pos, int t) {
+    CHK(local_forces_part(sys, pos));
+    CHK(nl_forces_part(sys, pos, t));
+    return ion_forces_part(sys, pos);
 }
 
 hipEvent_t pooled_event(me_system* sys) {
@@ -811,31 +853,26 @@ me_status exponential(me_system* sys, const T* veff, int t, bool last) {
     return ME_OK;
 }
 
-template <typename T>
-me_status two_exponentials(me_system* sys) {
-    const int next = sys->tab_cur ^ 1;
-    CHK(exponential<T>(sys, (const T*)sys->w.veff0, sys->tab_cur, false));
-    CHK(exponential<T>(sys, (const T*)sys->w.veff1, next, true));
-    return ME_OK;
-}
-
-me_status make_veff(me_system* sys, double eps, bool both) {
+// v_eff of the first exponential (v0) and / or the second (v1)
+me_status make_veff_parts(me_system* sys, double eps, bool v0, bool v1) {
     const Geometry& g = sys->g;
     const double* hn = sys->w.hist[sys->hist_newest];
     const double* hn1 = sys->w.hist[(sys->hist_newest + 2) % 3];
     const double* hn2 = sys->w.hist[(sys->hist_newest + 1) % 3];
     if (g.f64)
         HIPCHK(launch_veff<double>(sys->w.vloc_cur, sys->w.vloc_next, hn, hn1, hn2, sys->hist_count, g.nx, g.N,
-                                   sys->prm.h, Lx(sys), eps, (double*)sys->w.veff0,
-                                   both ? (double*)sys->w.veff1 : nullptr, g.finite ? sys->w.mask : nullptr,
+                                   sys->prm.h, Lx(sys), eps, v0 ? (double*)sys->w.veff0 : nullptr,
+                                   v1 ? (double*)sys->w.veff1 : nullptr, g.finite ? sys->w.mask : nullptr,
                                    sys->stream));
     else
         HIPCHK(launch_veff<float>(sys->w.vloc_cur, sys->w.vloc_next, hn, hn1, hn2, sys->hist_count, g.nx, g.N,
-                                  sys->prm.h, Lx(sys), eps, (float*)sys->w.veff0,
-                                  both ? (float*)sys->w.veff1 : nullptr, g.finite ? sys->w.mask : nullptr,
+                                  sys->prm.h, Lx(sys), eps, v0 ? (float*)sys->w.veff0 : nullptr,
+                                  v1 ? (float*)sys->w.veff1 : nullptr, g.finite ? sys->w.mask : nullptr,
                                   sys->stream));
     return ME_OK;
 }
+
+me_status make_veff(me_system* sys, double eps, bool both) { return make_veff_parts(sys, eps, true, both); }
 
 // fill the report buffer (norm check always; energies when `energy`)
 me_status finalize(me_system* sys, bool with_norm, bool energy, const double* fict_part = nullptr,
@@ -1080,10 +1117,12 @@ me_status initial_fields(me_system* sys) {
     return ME_OK;
 }
 
-// steps 1-2 of a step: ions moved, H(t+dt) prepared
-me_status step_pre(me_system* sys, double eps) {
+// steps 1-2 of a step: ions moved, H(t+dt) prepared.  With the overlap the
+// launches go to the side stream, v_eff of the first exponential excepted
+// (make_veff_parts on the main stream), and the Ewald sum at R(t+dt) is
+// taken here too.
+me_status step_pre_ions(me_system* sys, double eps, bool overlap) {
     const Geometry& g = sys->g;
-    sys->cp_ready = false;          // bufA / bufB become Taylor-stage scratch
     const int next = sys->tab_cur ^ 1;
     // 1. ions: R(t+dt) by velocity Verlet
     HIPCHK(launch_ions_predict(sys->w.pos, sys->w.vel, sys->w.frc, sys->w.mass, g.n_ions, sys->prm.dt,
@@ -1091,16 +1130,37 @@ me_status step_pre(me_system* sys, double eps) {
     // 2. ionic part of H(t+dt): V_loc and projector tables at R(t+dt)
     CHK(ion_fields(sys, sys->w.pos_next, sys->w.vloc_next));
     CHK(build_tables(sys, sys->w.pos_next, next));
-    CHK(make_veff(sys, eps, true));
+    CHK(make_veff_parts(sys, eps, !overlap, true));
+    if (overlap) CHK(ion_forces_part(sys, sys->w.pos_next));
     return ME_OK;
 }
 
+me_status step_pre(me_system* sys, double eps) {
+    sys->cp_ready = false;          // bufA / bufB become Taylor-stage scratch
+    return step_pre_ions(sys, eps, false);
+}
+
 // step 5: density, fields and forces of the propagated orbitals, ions finished
-me_status step_post(me_system* sys, bool energy) {
+// (overlap: the Ewald part was taken by step_pre_ions, the nonlocal forces
+// run on the side stream beside the density and Hartree chain)
+me_status step_post(me_system* sys, bool energy, bool overlap = false) {
     const Geometry& g = sys->g;
     const int next = sys->tab_cur ^ 1;
-    CHK(density_vhxc(sys, energy));
-    CHK(forces_parts(sys, sys->w.pos_next, next));
+    if (overlap) {
+        HIPCHK(hipEventRecord(sys->ev_fork[1], sys->stream));
+        HIPCHK(hipStreamWaitEvent(sys->side, sys->ev_fork[1], 0));
+        {
+            OnSide on(sys);
+            CHK(nl_forces_part(sys, sys->w.pos_next, next));
+        }
+        HIPCHK(hipEventRecord(sys->ev_join[1], sys->side));
+        CHK(density_vhxc(sys, energy));
+        CHK(local_forces_part(sys, sys->w.pos_next));
+        HIPCHK(hipStreamWaitEvent(sys->stream, sys->ev_join[1], 0));
+    } else {
+        CHK(density_vhxc(sys, energy));
+        CHK(forces_parts(sys, sys->w.pos_next, next));
+    }
     HIPCHK(launch_ions_finish(sys->w.pos, sys->w.vel, sys->w.frc, sys->w.pos_next, sys->w.floc, sys->w.fnl, sys->w.fion, sys->w.mass, g.n_ions, sys->prm.dt,
                               sys->prm.freeze_ions, sys->stream));
     std::swap(sys->w.vloc_cur, sys->w.vloc_next);
@@ -1111,19 +1171,33 @@ me_status step_post(me_system* sys, bool energy) {
 
 template <typename T>
 me_status step_impl(me_system* sys, double eps, bool energy) {
-    CHK(step_pre(sys, eps));
-    // 3-4. AETRS: exp(-i tau H(t+dt)) exp(-i tau H(t))
+    const bool overlap = sys->side != nullptr;
+    const int next = sys->tab_cur ^ 1;
+    sys->cp_ready = false;          // bufA / bufB become Taylor-stage scratch
+    if (overlap) {
+        HIPCHK(hipEventRecord(sys->ev_fork[0], sys->stream));
+        HIPCHK(hipStreamWaitEvent(sys->side, sys->ev_fork[0], 0));
+        {
+            OnSide on(sys);
+            CHK(step_pre_ions(sys, eps, true));
+        }
+        HIPCHK(hipEventRecord(sys->ev_join[0], sys->side));
+        CHK(make_veff_parts(sys, eps, true, false));
+    } else {
+        CHK(step_pre_ions(sys, eps, false));
+    }
+    // 3-4. AETRS: exp(-i tau H(t+dt)) exp(-i tau H(t)); the second waits for H(t+dt)
+    CHK(exponential<T>(sys, (const T*)sys->w.veff0, sys->tab_cur, false));
+    if (overlap) HIPCHK(hipStreamWaitEvent(sys->stream, sys->ev_join[0], 0));
     if (sys->g.etrs == 0) {
-        CHK(two_exponentials<T>(sys));
-        return step_post(sys, energy);
+        CHK(exponential<T>(sys, (const T*)sys->w.veff1, next, true));
+        return step_post(sys, energy, overlap);
     }
     // ETRS: the AETRS result predicts psi(t+dt); each correction rebuilds
     // v_eff of the second exponential from its density and redoes that
     // exponential from the half-step orbitals
     const Geometry& g = sys->g;
     const size_t orb = (size_t)g.n_orb * g.stride * g.bc;
-    const int next = sys->tab_cur ^ 1;
-    CHK(exponential<T>(sys, (const T*)sys->w.veff0, sys->tab_cur, false));
     HIPCHK(hipMemcpyAsync(sys->w.etrs_half, sys->w.psi, orb, hipMemcpyDeviceToDevice, sys->stream));
     CHK(exponential<T>(sys, (const T*)sys->w.veff1, next, true));
     for (int k = 0; k < g.etrs; ++k) {
@@ -1134,7 +1208,7 @@ me_status step_impl(me_system* sys, double eps, bool energy) {
         HIPCHK(hipMemcpyAsync(sys->w.psi, sys->w.etrs_half, orb, hipMemcpyDeviceToDevice, sys->stream));
         CHK(exponential<T>(sys, (const T*)sys->w.veff1, next, true));
     }
-    return step_post(sys, energy);
+    return step_post(sys, energy, overlap);
 }
 
 }  // namespace
@@ -1925,6 +1999,21 @@ me_status me_workspace_size(const me_params* p, size_t* bytes) {
     }
 }
 
+// the side stream of a system, its FFT execution info and events (waits for
+// the stream first)
+static void release_side(me_system* sys) {
+    if (sys->side) hipStreamSynchronize(sys->side);
+    if (sys->info_side) rocfft_execution_info_destroy(sys->info_side);
+    for (int i = 0; i < 2; ++i) {
+        if (sys->ev_fork[i]) hipEventDestroy(sys->ev_fork[i]);
+        if (sys->ev_join[i]) hipEventDestroy(sys->ev_join[i]);
+        sys->ev_fork[i] = sys->ev_join[i] = nullptr;
+    }
+    if (sys->side) hipStreamDestroy(sys->side);
+    sys->side = nullptr;
+    sys->info_side = nullptr;
+}
+
 me_status me_init_system(const me_params* p, void* workspace, size_t ws_bytes, void* stream,
                          me_system** out) {
     me_system* sys = nullptr;
@@ -1977,6 +2066,7 @@ me_status me_init_system(const me_params* p, void* workspace, size_t ws_bytes, v
 
         auto fail = [&](me_status s2) {
             g_init_error = sys->err;
+            release_side(sys);
             if (sys->info) rocfft_execution_info_destroy(sys->info);
             if (sys->r2c) rocfft_plan_destroy(sys->r2c);
             if (sys->c2r) rocfft_plan_destroy(sys->c2r);
@@ -2036,6 +2126,21 @@ me_status me_init_system(const me_params* p, void* workspace, size_t ws_bytes, v
             const me_status fs = finite_setup(sys, p);
             if (fs != ME_OK) return fail(fs);
         }
+        if (env_int("MODEHR_OVERLAP", 1) != 0) {
+            INITCHK(hipStreamCreateWithFlags(&sys->side, hipStreamNonBlocking));
+            for (int i = 0; i < 2; ++i) {
+                INITCHK(hipEventCreateWithFlags(&sys->ev_fork[i], hipEventDisableTiming));
+                INITCHK(hipEventCreateWithFlags(&sys->ev_join[i], hipEventDisableTiming));
+            }
+            if (rocfft_execution_info_create(&sys->info_side) != rocfft_status_success ||
+                rocfft_execution_info_set_stream(sys->info_side, sys->side) != rocfft_status_success ||
+                (std::max(w1, w2) > 0 &&
+                 rocfft_execution_info_set_work_buffer(sys->info_side, sys->w.fft_work, sys->g.fft_work) !=
+                     rocfft_status_success)) {
+                sys->err = "rocfft execution info failed (side stream)";
+                return fail(ME_EDEVICE);
+            }
+        }
 #undef INITCHK
         *out = sys;
         return ME_OK;
@@ -2049,6 +2154,7 @@ me_status me_init_system(const me_params* p, void* workspace, size_t ws_bytes, v
 me_status me_destroy(me_system* sys) {
     if (!sys) return ME_OK;
     hipStreamSynchronize(sys->stream);
+    release_side(sys);
     if (sys->blas) rocblas_destroy_handle(sys->blas);
     if (sys->info) rocfft_execution_info_destroy(sys->info);
     if (sys->r2c) rocfft_plan_destroy(sys->r2c);
