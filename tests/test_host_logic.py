@@ -32,13 +32,17 @@ def _stubs():
             assert params.split(",")[-1].strip().endswith("hipStream_t s"), name
             out.append(f'{tmpl}hipError_t {name}({params}) {{ mock_stream_op(s, "{name}"); return hipSuccess; }}')
     out += [
-        "template <typename T> hipError_t batch_stencil_occupancy(int, size_t, int, int* w) { *w = 2; return hipSuccess; }",
+        "template <typename T> hipError_t batch_stencil_occupancy(int, size_t, int, bool, int* w) { *w = 2; return hipSuccess; }",
         "int local_force_chunks(int64_t) { return 512; }",
         "size_t ewald_scratch_doubles(int n) { return (size_t)(n > 0 ? n : 1) * 32; }",
         "int ewald_sg_blocks(int ng) { return ng > 0 ? (ng + 255) / 256 : 1; }",
         "int cp_solve_blocks(int n) { return (n * n + 255) / 256; }",
         "int64_t cp_sq_blocks(int64_t N) { return (N + 255) / 256; }",
         "}",
+        # the allocation-free entry point lives in its own source (a device
+        # array); the host logic under test does not reach it
+        'extern "C" me_status me_dipole_noalloc(const double*, const int32_t*, double, double*, void*) '
+        "{ return ME_EUNSUPPORTED; }",
     ]
     return "\n".join(out) + "\n"
 
