@@ -16,8 +16,8 @@ one-step error against the FP64 CPU oracle on sampled orbitals.
 
 A second workload is timed beside it (``batched``): 16 systems of uneven
 grid size (32^3 to 96^3) and orbital count (8 to 256), FP32, advanced
-together, every Horner stage one persistent launch over all systems, steps
-replayed from a captured hipGraph, launch shape from the autotuner.
+together, every Horner stage one launch over all systems, steps replayed
+from a captured hipGraph, launch shape from the autotuner.
 
 A third workload (``cp``) times the paper's comparison scheme on the same
 96^3 system: Car-Parrinello with RATTLE / velocity Verlet (one H psi and five
@@ -94,8 +94,8 @@ def run_precision(cfg, inp, prec, steps, warmup, sample):
 
 
 def run_batch(steps, warmup, eager_steps, autotune):
-    """The batched workload: 16 uneven FP32 systems advanced together, Horner
-    stages as persistent multi-system launches, 6-step graphs replayed."""
+    """The batched workload: 16 uneven FP32 systems advanced together, each
+    Horner stage one launch over all systems, 6-step graphs replayed."""
     import tempfile
     import torch
     import workloads as W
@@ -146,7 +146,7 @@ def run_batch(steps, warmup, eager_steps, autotune):
         "value": work / (ms * 1e-3), "unit": "orbital·gridpt·Hψ/s", "ms_per_step": ms, "steps": steps,
         "graph": True, "eager_ms_per_step": (t3 - t2) * 1e3 / eager_steps,
         "tuning": tuning,
-        "stencil": {"kernel": "batch_stencil_kernel (persistent, all systems)", "achieved": achieved,
+        "stencil": {"kernel": "batch_stencil_kernel (all systems in one launch)", "achieved": achieved,
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                     "kernel_avg_ms": avg_ms, "algorithmic_bytes_per_launch": avg_bytes},
         "max_norm_dev": norm_dev,

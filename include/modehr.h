@@ -325,9 +325,11 @@ const char* me_strerror(me_status s);
  * together.  Each step is the step of me_propagate_step (sec. 5.1, no
  * control field) for every system; every orbital of every system is
  * independent inside the two Taylor exponentials of eq. (aetrs), so each of
- * their Horner stages runs as ONE persistent stencil launch over all
- * systems, whose workgroups pull (system, orbital, x-tile, y-tile, z-slab)
- * work items from per-XCD device queues.  A system whose whole x-rows do not
+ * their Horner stages runs as ONE stencil launch over all systems.  Its
+ * work items are (system, orbital, x-tile, y-tile, z-slab); each of the 8
+ * XCDs takes an even, contiguous share of every system's items, either one
+ * item per workgroup (the default) or pulled from a per-XCD device queue by
+ * a persistent grid (see me_batch_tuning).  A system whose whole x-rows do not
  * fit the workgroup runs in x-tiles of 64 points (x-halo in LDS).  All
  * systems share one stream and must share the precision and the Taylor
  * order; at most 32 systems.  The adjoint is not available on batched
@@ -335,13 +337,17 @@ const char* me_strerror(me_status s);
  */
 typedef struct me_batch me_batch;
 
-/* Launch shape of the persistent stencil. */
+/* Launch shape of the batched stencil. */
 typedef struct {
     int32_t block;        /* threads per workgroup: multiple of 64 in [64, 1024];
                              each system's tile is floor(block / n_x) whole rows,
                              or floor(block / 64) rows of 64-point x-tiles when
                              8 n_x > 2 block */
-    int32_t wg_per_cu;    /* resident workgroups per compute unit (grid = this x CUs) */
+    int32_t wg_per_cu;    /* 0: one work item per workgroup (grid = the items, each
+                             XCD taking an even share of every system's items;
+                             the default); 1-4: a persistent launch of this many
+                             resident workgroups per compute unit (grid = this x
+                             CUs) pulling items from per-XCD queues */
     int32_t zdiv;         /* z-slabs per orbital column: 1, 2 or 4 */
     double stage_ms;      /* autotuner: measured time of one Horner stage over the
                              whole batch (ms); ignored by me_batch_set_tuning */
@@ -364,12 +370,12 @@ me_status me_batch_system(me_batch* b, int32_t i, me_system** out);
 
 /* Sets or reads the launch shape.  ME_EINVAL if it does not fit a system
  * (the halo jobs of an x-tile, 8 (64 + rows), over 2 block; LDS over 64 KiB)
- * or wg_per_cu exceeds what is resident. */
+ * or wg_per_cu is negative or exceeds what is resident. */
 me_status me_batch_set_tuning(me_batch* b, const me_batch_tuning* t);
 me_status me_batch_get_tuning(const me_batch* b, me_batch_tuning* t);
 
 /* Autotuner: times one Horner stage over the batch for every launch shape
- * (block 256..1024, wg_per_cu 1..4, zdiv 1/2/4) that fits, keeps the
+ * (block 256..1024, wg_per_cu 0..4, zdiv 1/2/4) that fits, keeps the
  * fastest, and returns it in *out (nullable).  With cache_path (nullable) a
  * JSON file keyed by precision, Taylor order and the systems' shapes is
  * consulted first and updated after a search.  Needs the state of every

@@ -1371,21 +1371,21 @@ me_status batch_apply_tuning(me_batch* b, const me_batch_tuning& t) {
     }
     const int wmax = b->f64 ? batch_max_wpc<double>(b, t.block, lds, tiles)
                             : batch_max_wpc<float>(b, t.block, lds, tiles);
-    if (wmax < 1 || t.wg_per_cu < 1 || t.wg_per_cu > wmax) {
-        b->err = "wg_per_cu must be in [1, " + std::to_string(wmax) + "] for this block size";
+    if (wmax < 1 || t.wg_per_cu < 0 || t.wg_per_cu > wmax) {
+        b->err = "wg_per_cu must be in [0, " + std::to_string(wmax) + "] for this block size";
         return ME_EINVAL;
     }
     b->tune = t;
     b->tile = tiles;
     b->lds = lds;
-    b->grid = t.wg_per_cu * b->n_cu;
+    b->grid = t.wg_per_cu * b->n_cu;     // 0: one item per workgroup, grid set per launch
     if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
     if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
     return ME_OK;
 }
 
-// the untuned choice: 768 threads (1024 where a row needs it), two
-// workgroups per CU where they fit, whole z columns
+// the untuned choice: 768 threads (1024 where a row needs it), one work item
+// per workgroup, whole z columns
 me_status batch_default_tuning(me_batch* b) {
     me_batch_tuning t{};
     t.zdiv = 1;
@@ -1397,7 +1397,7 @@ me_status batch_default_tuning(me_batch* b) {
         const int wmax = b->f64 ? batch_max_wpc<double>(b, block, lds, tiles)
                                 : batch_max_wpc<float>(b, block, lds, tiles);
         if (wmax < 1) continue;
-        t.wg_per_cu = std::min(2, wmax);
+        t.wg_per_cu = 0;
         return batch_apply_tuning(b, t);
     }
     b->err = "no workgroup shape fits this batch";
@@ -1492,7 +1492,22 @@ me_status batch_stage(me_batch* b, const std::vector<const cx_t<T>*>& u, const s
         e1 = batch_event(b);
         if (e0 && e1) BHIP(hipEventRecord(e0, b->stream));
     }
-    BHIP(launch_batch_stencil<T>(a, mode, norm, b->tune.block, b->grid, b->lds, b->stream));
+    int grid = b->grid;
+    if (b->tune.wg_per_cu == 0) {
+        // one item per workgroup: 8 x the largest per-XCD share of the items
+        int share = 0;
+        for (int q = 0; q < QUEUE_SLOTS; ++q) {
+            int n = 0;
+            for (int j = 0; j < a.n_sys; ++j) {
+                const int cnt = a.sys[j].items;
+                n += (int)((int64_t)cnt * (q + 1) / QUEUE_SLOTS - (int64_t)cnt * q / QUEUE_SLOTS);
+            }
+            share = std::max(share, n);
+        }
+        a.counter = nullptr;
+        grid = QUEUE_SLOTS * share;
+    }
+    BHIP(launch_batch_stencil<T>(a, mode, norm, b->tune.block, grid, b->lds, b->stream));
     if (timed && e0 && e1) {
         BHIP(hipEventRecord(e1, b->stream));
         b->ev.emplace_back(e0, e1);
@@ -1765,7 +1780,7 @@ me_status batch_autotune(me_batch* b, me_batch_tuning* best) {
             size_t lds = 0;
             if (!batch_tiles(b, t, tiles, lds)) continue;
             const int wmax = std::min(4, batch_max_wpc<T>(b, block, lds, tiles));
-            for (int w = 1; w <= wmax; ++w) {
+            for (int w = wmax >= 1 ? 0 : 1; w <= wmax; ++w) {     // 0: one item per workgroup
                 t.wg_per_cu = w;
                 if (batch_apply_tuning(b, t) != ME_OK) continue;
                 double ms = 0.0;

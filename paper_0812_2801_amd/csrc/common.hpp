@@ -117,7 +117,8 @@ struct BatchStencilArgs {
     BatchSys<T> sys[MAX_BATCH];
     int n_sys;
     int total;               // work items over all systems
-    int* counter;            // device, 8 queue counters, zero at launch
+    int* counter;            // device, 8 queue counters, zero at launch; nullptr: one
+                             // item per workgroup (grid = 8 x the largest XCD share)
 };
 
 // dynamic LDS of a stencil workgroup: two halo tiles of (ty + 8) rows of nx

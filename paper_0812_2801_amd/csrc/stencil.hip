@@ -792,6 +792,23 @@ constexpr int QUEUES = 8;
 
 __device__ __forceinline__ int batch_slice_lo(int count, int q) { return (int)((int64_t)count * q / QUEUES); }
 
+// Without queue counters every workgroup takes one item: block b runs on XCD
+// b % 8 and takes the (b / 8)-th item of that XCD's share (each system's
+// items split into 8 contiguous slices as for the queues), or none.
+template <typename T>
+__device__ int batch_item_of_block(const BatchStencilArgs<T>& a) {
+    const int q = blockIdx.x % QUEUES;
+    int i = blockIdx.x / QUEUES;
+    for (int s = 0; s < a.n_sys; ++s) {
+        const int cnt = a.sys[s].items;
+        const int lo = batch_slice_lo(cnt, q);
+        const int len = batch_slice_lo(cnt, q + 1) - lo;
+        if (i < len) return a.sys[s].item0 + lo + i;
+        i -= len;
+    }
+    return -1;
+}
+
 template <typename T>
 __device__ int batch_pull(const BatchStencilArgs<T>& a, int* q_next) {
     while (*q_next < QUEUES) {
@@ -811,7 +828,7 @@ __device__ int batch_pull(const BatchStencilArgs<T>& a, int* q_next) {
 
 // XT: some systems run in x-tiles (tx < nx: items (system, orbital, x-tile,
 // y-tile, z-slab), x-tiles fastest), with at most 2 halo jobs per thread.
-template <typename T, int HJ, int MODE, bool NORM, bool XT>
+template <typename T, int HJ, int MODE, bool NORM, bool XT, bool ONE>
 __global__ void __launch_bounds__(1024) STENCIL_ATTR batch_stencil_kernel(BatchStencilArgs<T> a) {
     using C = cx_t<T>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -819,8 +836,13 @@ __global__ void __launch_bounds__(1024) STENCIL_ATTR batch_stencil_kernel(BatchS
     __shared__ double red[16];
     __shared__ int item_sh;
     int q_next = 0;                           // used by thread 0 only
-    for (;;) {
-        if (threadIdx.x == 0) item_sh = batch_pull(a, &q_next);
+    for (int round = 0;; ++round) {
+        if constexpr (ONE) {                  // one item per workgroup
+            if (round > 0) break;
+            if (threadIdx.x == 0) item_sh = batch_item_of_block(a);
+        } else {
+            if (threadIdx.x == 0) item_sh = batch_pull(a, &q_next);
+        }
         __syncthreads();
         const int item = item_sh;
         __syncthreads();
@@ -860,16 +882,23 @@ __global__ void __launch_bounds__(1024) STENCIL_ATTR batch_stencil_kernel(BatchS
     }
 }
 
+template <typename T, int HJ, bool XT, bool ONE>
+static void launch_batch_one(const BatchStencilArgs<T>& a, int mode, bool norm, int block, int grid, size_t lds,
+                             hipStream_t s) {
+    if (mode == MODE_HORNER) {
+        if (norm) batch_stencil_kernel<T, HJ, MODE_HORNER, true, XT, ONE><<<grid, block, lds, s>>>(a);
+        else batch_stencil_kernel<T, HJ, MODE_HORNER, false, XT, ONE><<<grid, block, lds, s>>>(a);
+    } else {
+        if (norm) batch_stencil_kernel<T, HJ, MODE_HORNER_FIRST, true, XT, ONE><<<grid, block, lds, s>>>(a);
+        else batch_stencil_kernel<T, HJ, MODE_HORNER_FIRST, false, XT, ONE><<<grid, block, lds, s>>>(a);
+    }
+}
+
 template <typename T, int HJ, bool XT>
 static void launch_batch_hj(const BatchStencilArgs<T>& a, int mode, bool norm, int block, int grid, size_t lds,
                             hipStream_t s) {
-    if (mode == MODE_HORNER) {
-        if (norm) batch_stencil_kernel<T, HJ, MODE_HORNER, true, XT><<<grid, block, lds, s>>>(a);
-        else batch_stencil_kernel<T, HJ, MODE_HORNER, false, XT><<<grid, block, lds, s>>>(a);
-    } else {
-        if (norm) batch_stencil_kernel<T, HJ, MODE_HORNER_FIRST, true, XT><<<grid, block, lds, s>>>(a);
-        else batch_stencil_kernel<T, HJ, MODE_HORNER_FIRST, false, XT><<<grid, block, lds, s>>>(a);
-    }
+    if (a.counter == nullptr) launch_batch_one<T, HJ, XT, true>(a, mode, norm, block, grid, lds, s);
+    else launch_batch_one<T, HJ, XT, false>(a, mode, norm, block, grid, lds, s);
 }
 
 template <typename T>
@@ -913,15 +942,15 @@ hipError_t batch_stencil_occupancy(int block, size_t lds, int hj, bool xt, int* 
     if (xt) {
         if (hj == 1)
             return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                wg_per_cu, batch_stencil_kernel<T, 1, MODE_HORNER, false, true>, block, lds);
+                wg_per_cu, batch_stencil_kernel<T, 1, MODE_HORNER, false, true, false>, block, lds);
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            wg_per_cu, batch_stencil_kernel<T, 2, MODE_HORNER, false, true>, block, lds);
+            wg_per_cu, batch_stencil_kernel<T, 2, MODE_HORNER, false, true, false>, block, lds);
     }
     if (hj == 1)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            wg_per_cu, batch_stencil_kernel<T, 1, MODE_HORNER, false, false>, block, lds);
+            wg_per_cu, batch_stencil_kernel<T, 1, MODE_HORNER, false, false, false>, block, lds);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        wg_per_cu, batch_stencil_kernel<T, 2, MODE_HORNER, false, false>, block, lds);
+        wg_per_cu, batch_stencil_kernel<T, 2, MODE_HORNER, false, false, false>, block, lds);
 }
 template hipError_t batch_stencil_occupancy<double>(int, size_t, int, bool, int*);
 template hipError_t batch_stencil_occupancy<float>(int, size_t, int, bool, int*);

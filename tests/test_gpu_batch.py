@@ -138,7 +138,7 @@ def test_batch_f64_follows_the_oracle():
     b.close()
 
 
-@pytest.mark.parametrize("block,wpc,zdiv", [(256, 1, 4), (512, 2, 2), (1024, 1, 1)])
+@pytest.mark.parametrize("block,wpc,zdiv", [(256, 1, 4), (512, 2, 2), (1024, 1, 1), (768, 0, 1), (512, 0, 2)])
 def test_batch_launch_shapes(block, wpc, zdiv):
     """Small blocks force two halo runs per thread (8 n_x > block) and ragged
     y-tiles; zdiv > 1 gives short last z-slabs."""
