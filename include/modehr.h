@@ -40,6 +40,12 @@
  *   - Every call that launches work enqueues it on the stream given to
  *     me_init_system (a hipStream_t passed as void*; NULL = default stream)
  *     and returns without waiting, unless its comment says it synchronises.
+ *     Inside an MD step a single system also uses a second stream of its
+ *     own (created by me_init_system, default priority, released by
+ *     me_destroy) for work the first exponential does not wait for; it is
+ *     forked from and joined back into the caller's stream by events within
+ *     the step, so when me_propagate_step returns, all of the step's work is
+ *     ordered before whatever the caller enqueues next on its stream.
  *   - Every call returns an me_status.  Arguments are validated before any
  *     launch; an invalid argument returns ME_EINVAL and changes nothing.
  *     Asynchronous device errors surface at the next synchronising call.
@@ -149,7 +155,8 @@ me_status me_workspace_size(const me_params* p, size_t* bytes);
  * R(t); the orbitals follow with me_set_state).
  * workspace: caller-owned device memory of at least
  * me_workspace_size bytes, 256-byte aligned, untouched by the caller until
- * me_destroy.  stream: hipStream_t (as void*) all work is enqueued on.
+ * me_destroy.  stream: hipStream_t (as void*) all work is enqueued on (see
+ * "Streams and errors" for the step's internal second stream).
  * Validates p (ME_EINVAL), checks ws_bytes (ME_ENOMEM), uploads the ion data
  * and builds FFT plans.  No orbital state yet: call me_set_state. */
 me_status me_init_system(const me_params* p, void* workspace, size_t ws_bytes,
