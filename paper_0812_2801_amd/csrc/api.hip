@@ -297,6 +297,7 @@ constexpr int CP_KSPLIT = 256;
 
 struct Layout {
     void *psi, *bufA, *bufB, *veff0, *veff1, *cnl;
+    void* cnl2;                 // the next stage's c_JA when a fix-up and a gather share a pass
     void* dnl;                  // split-bf16 force gather: [n_ions][n_orb][3] complex FP32
     double *vloc_cur, *vloc_next, *vstatic, *hist[3], *rho, *vh;
     double2 *rhok, *spec, *phase, *phaseT, *ewald_sg;
@@ -312,6 +313,8 @@ struct Layout {
     int32_t *tmap[2], *tpts[2], *tcnt[2], *tion[2], *tnslots[2], *tflag[2], *tblk[2];
     void* tpl[2];
     int32_t* tcount[2];
+    uint8_t* tov[2];            // per table point: covered by more than one sphere
+    int32_t *tovl[2], *tovn[2]; // slots covered by more than one sphere, and their count
     double *fnl, *enl_part, *kbf_part, *floc_part, *floc, *fion, *eion_part, *erec_part;
     double *ewald_gv, *ewald_wv, *ewald_part;
     double *norm_part, *fix_part, *norms, *kin_part, *hxc_part, *loc_part, *rep, *scal0;
@@ -341,6 +344,7 @@ static Layout carve(const Geometry& g, char* base) {
     L.veff0 = c.take<void>(g.N * g.br);
     L.veff1 = c.take<void>(g.N * g.br);
     L.cnl = c.take<void>((size_t)std::max(1, g.n_ions) * g.n_orb * g.bc);
+    L.cnl2 = c.take<void>((size_t)std::max(1, g.n_ions) * g.n_orb * g.bc);
     L.dnl = c.take<void>((size_t)std::max(1, g.n_ions) * g.n_orb * 3 * g.bc);
     L.vloc_cur = c.take<double>(g.N * 8);
     L.vloc_next = c.take<double>(g.N * 8);
@@ -381,6 +385,9 @@ static Layout carve(const Geometry& g, char* base) {
         L.tflag[t] = c.take<int32_t>(4);
         L.tblk[t] = c.take<int32_t>((size_t)(g.nscan + 1) * 4);
         L.tcount[t] = c.take<int32_t>((size_t)std::max(1, g.n_ions) * 4);
+        L.tov[t] = c.take<uint8_t>((size_t)std::max(1, g.n_ions) * g.kcap);
+        L.tovl[t] = c.take<int32_t>((size_t)g.ucap * 4);
+        L.tovn[t] = c.take<int32_t>(4);
     }
     L.fnl = c.take<double>(ion3);
     L.enl_part = c.take<double>(ion3 / 3);
@@ -542,6 +549,9 @@ KbTables tables(me_system* sys, int t) {
     k.nslots = sys->w.tnslots[t];
     k.flag = sys->w.tflag[t];
     k.blk = sys->w.tblk[t];
+    k.ov = sys->w.tov[t];
+    k.ovl = sys->w.tovl[t];
+    k.ovn = sys->w.tovn[t];
     k.ucap = sys->g.ucap;
     return k;
 }
@@ -813,11 +823,22 @@ me_status exponential(me_system* sys, const T* veff, int t, bool last) {
     const double ekb_h3 = sys->prm.kb_energy * sys->prm.h * sys->prm.h * sys->prm.h;
     const C* u = psi;
     int nb = 0;
+    // a stage's fix-up and the next stage's gather share one pass over the
+    // projector points (plain FP32 / FP64 contraction); c_JA of the current
+    // stage's input alternates between w.cnl and w.cnl2
+    const bool fuse = g.n_ions > 0 && !(sizeof(T) == 4 && sys->prm.precision == ME_F32_BF16X3) &&
+                      env_int("MODEHR_FIXGATHER", 1) != 0;
+    C* cnl_buf[2] = {(C*)sys->w.cnl, (C*)sys->w.cnl2};
+    int cb = 0;                        // cnl_buf[cb] holds c_JA of the current stage's input
+    bool have_c = false;               // ... already, from the previous stage's fused pass
     for (int k = K; k >= 1; --k) {
         // the last stage overwrites psi in place (each point reads its own
         // psi0 only), except for K = 1 where it also reads psi's neighbours
         C* out = (k == 1 && K > 1) ? psi : bufs[nb];
-        CHK(gather<T>(sys, u, g.stride, g.n_orb, t, ekb_h3));
+        if (!have_c) {
+            CHK(gather<T>(sys, u, g.stride, g.n_orb, t, ekb_h3));
+            cb = 0;
+        }
         StencilArgs<T> a = base_args<T>(sys, veff, g.n_orb);
         a.u = u;
         a.psi0 = psi;
@@ -842,10 +863,20 @@ me_status exponential(me_system* sys, const T* veff, int t, bool last) {
             sys->ev_bytes.push_back(streams * g.bc * (double)g.N * g.n_orb + (double)g.br * g.N);
             sys->ev_streams.push_back((int)streams);
         }
-        // nonlocal part at the projector points: out += (-i tau/k) E_KB sum_J p_J c_J
-        if (g.n_ions > 0)
-            HIPCHK(launch_kb_fixup<T>(out, g.stride, g.n_orb, tables(sys, t), (const C*)sys->w.cnl, 0.0, -tau / k,
-                                      norm ? sys->w.fix_part : nullptr, sys->stream));
+        // nonlocal part at the projector points: out += (-i tau/k) E_KB sum_J p_J c_J,
+        // with the next stage's gather of out in the same pass where there is one
+        have_c = false;
+        if (g.n_ions > 0) {
+            if (fuse && k > 1) {
+                HIPCHK(launch_kb_fixup_gather<T>(out, g.stride, g.n_orb, g.n_ions, tables(sys, t), cnl_buf[cb], 0.0,
+                                                 -tau / k, ekb_h3, cnl_buf[cb ^ 1], sys->stream));
+                cb ^= 1;
+                have_c = true;
+            } else {
+                HIPCHK(launch_kb_fixup<T>(out, g.stride, g.n_orb, tables(sys, t), cnl_buf[cb], 0.0, -tau / k,
+                                          norm ? sys->w.fix_part : nullptr, sys->stream));
+            }
+        }
         u = out;
         nb ^= 1;
     }

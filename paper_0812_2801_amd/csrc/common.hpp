@@ -64,6 +64,9 @@ struct KbTables {
     int32_t* flag;     // [1] set when a point is covered by more than NL_KMAX spheres
     int32_t* blk;      // [scan blocks + 1] scratch of the slot numbering
     int64_t ucap;
+    uint8_t* ov;       // [n_ions][kcap] 1 where the table point is covered by another sphere too
+    int32_t* ovl;      // [ucap] slots covered by more than one sphere (any order), count in *ovn
+    int32_t* ovn;      // [1]
 };
 
 enum StencilMode : int {
@@ -156,6 +159,18 @@ hipError_t launch_kb_fixup(cx_t<T>* out, int64_t stride, int n_orb, KbTables t,
 template <typename T>
 hipError_t launch_kb_gather(const cx_t<T>* u, int64_t stride, int n_orb, int n_ions,
                             KbTables t, double ekb_h3, cx_t<T>* cnl, hipStream_t s);
+
+// One stage's fix-up and the next stage's gather in one pass over the
+// projector points: out_A(r) += (gr + i gi) sum_J p_J(r) cnl_in[J][A], then
+// cnl_out[J][A] = ekb_h3 sum_k p_J(k) out_A(idx_J(k)) of the fixed values.
+// Points covered by one sphere are fixed in place by that sphere's pass;
+// points covered by several are fixed by kb_fix_overlap_kernel afterwards
+// (inside this launch each pass computes their fixed value for its own sum
+// without writing it), so every sum has a fixed order.
+template <typename T>
+hipError_t launch_kb_fixup_gather(cx_t<T>* out, int64_t stride, int n_orb, int n_ions, KbTables t,
+                                  const cx_t<T>* cnl_in, double gr, double gi, double ekb_h3, cx_t<T>* cnl_out,
+                                  hipStream_t s);
 
 // the same contraction for FP32 orbitals as split-bf16 (bf16x3) MFMA with
 // FP32 accumulation

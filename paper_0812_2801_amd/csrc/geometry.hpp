@@ -27,6 +27,21 @@ __device__ __forceinline__ double kb_value(const KbGeom& g, double d2) {
     return g.pnorm * exp(-d2 * g.inv2s2);
 }
 
+// The nonlocal term at one point, in the order and rounding that the fix-up
+// kernels share: s += p c over the covering projectors in ascending ion
+// order, then v += (gr + i gi) s.
+template <typename T>
+__device__ __forceinline__ void nl_acc(T p, cx_t<T> c, T& sr, T& si) {
+    sr = sr + p * c.x;
+    si = si + p * c.y;
+}
+template <typename T>
+__device__ __forceinline__ cx_t<T> nl_add(cx_t<T> v, T sr, T si, T gr, T gi) {
+    v.x = v.x + (gr * sr - gi * si);
+    v.y = v.y + (gr * si + gi * sr);
+    return v;
+}
+
 #pragma clang fp contract(on)
 
 // blocks are dispatched round-robin over the 8 XCDs; give every XCD a

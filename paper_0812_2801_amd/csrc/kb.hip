@@ -216,6 +216,25 @@ __global__ void nl_sort_kernel(const int32_t* __restrict__ nslots, int32_t* __re
     }
 }
 
+// which table points are covered by more than one sphere, and the list of
+// such slots (their order is free: each is fixed on its own)
+__global__ void nl_overlap_points_kernel(const int32_t* __restrict__ idx, const int32_t* __restrict__ count,
+                                         int kcap, const int32_t* __restrict__ map,
+                                         const int32_t* __restrict__ cnt, uint8_t* __restrict__ ov) {
+    const int J = blockIdx.y;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < count[J]) {
+        const int64_t e = (int64_t)J * kcap + k;
+        ov[e] = cnt[map[idx[e]]] > 1 ? 1 : 0;
+    }
+}
+
+__global__ void nl_overlap_slots_kernel(const int32_t* __restrict__ nslots, const int32_t* __restrict__ cnt,
+                                        int32_t* __restrict__ ovl, int32_t* __restrict__ ovn) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < *nslots && cnt[s] > 1) ovl[atomicAdd(ovn, 1)] = s;
+}
+
 template <typename T>
 hipError_t launch_kb_tables(const double* pos, int n_ions, int nx, int ny, int nz,
                             const KbGeom& g, KbTables t, hipStream_t s) {
@@ -236,6 +255,9 @@ hipError_t launch_kb_tables(const double* pos, int n_ions, int nx, int ny, int n
                                          t.cnt, t.ion, reinterpret_cast<T*>(t.pl), t.ucap, t.flag);
     nl_sort_kernel<T><<<(unsigned)((t.ucap + 255) / 256), 256, 0, s>>>(t.nslots, t.cnt, t.ion,
                                                                        reinterpret_cast<T*>(t.pl), t.ucap);
+    fill_i32_kernel<<<1, 64, 0, s>>>(t.ovn, 1, 0);
+    nl_overlap_points_kernel<<<eg, 256, 0, s>>>(t.idx, t.count, t.kcap, t.map, t.cnt, t.ov);
+    nl_overlap_slots_kernel<<<(unsigned)((t.ucap + 255) / 256), 256, 0, s>>>(t.nslots, t.cnt, t.ovl, t.ovn);
     return hipGetLastError();
 }
 
@@ -275,16 +297,10 @@ __global__ void __launch_bounds__(256) kb_fixup_kernel(cx_t<T>* __restrict__ out
             if (j < na) {
                 const int A = A0 + j;
                 T sr = 0, si = 0;
-                for (int k = 0; k < n; ++k) {
-                    const cx_t<T> c = cnl[(int64_t)jj[k] * n_orb + A];
-                    sr += ww[k] * c.x;
-                    si += ww[k] * c.y;
-                }
+                for (int k = 0; k < n; ++k) nl_acc<T>(ww[k], cnl[(int64_t)jj[k] * n_orb + A], sr, si);
                 cx_t<T>* o = out + (int64_t)A * stride + r;
                 const cx_t<T> old = *o;
-                cx_t<T> val = old;
-                val.x += gr * sr - gi * si;
-                val.y += gr * si + gi * sr;
+                const cx_t<T> val = nl_add<T>(old, sr, si, gr, gi);
                 *o = val;
                 if (dnorm != nullptr)
                     dn[j] += ((double)val.x * val.x + (double)val.y * val.y) -
@@ -379,6 +395,124 @@ hipError_t launch_kb_gather(const cx_t<T>* u, int64_t stride, int n_orb, int n_i
                                              t.count, t.kcap, (T)ekb_h3, cnl);
     return hipGetLastError();
 }
+
+// The fix-up of one stage fused with the gather of the next: the structure
+// of kb_gather_kernel (a wave per (ion, orbital), 512-point blocks whose
+// loads are issued before the sums), each point's value fixed before it is
+// summed.  A point of one sphere only is fixed in place here (its pass is
+// the only one that touches it); a point shared with other spheres gets
+// its fixed value computed from the slot's (ion, value) pairs for the sum
+// and is written by kb_fix_overlap_kernel after this launch.  The fix-up
+// arithmetic is kb_fixup_kernel's (nl_acc / nl_add), the sums are
+// kb_gather_kernel's.
+template <typename T>
+__global__ void __launch_bounds__(256) kb_fixup_gather_kernel(
+    cx_t<T>* __restrict__ out, int64_t stride, int n_orb, const int32_t* __restrict__ idx,
+    const T* __restrict__ pv, const int32_t* __restrict__ count, int kcap, const uint8_t* __restrict__ ov,
+    const int32_t* __restrict__ map, const int32_t* __restrict__ cnt, const int32_t* __restrict__ ion,
+    const T* __restrict__ pl, int64_t ucap, const cx_t<T>* __restrict__ cnl_in, T gr, T gi, T scale,
+    cx_t<T>* __restrict__ cnl_out) {
+    const int J = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int A = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (A >= n_orb) return;
+    const int K = count[J];
+    const int32_t* ix = idx + (int64_t)J * kcap;
+    const T* pp = pv + (int64_t)J * kcap;
+    const uint8_t* po = ov + (int64_t)J * kcap;
+    cx_t<T>* ua = out + (int64_t)A * stride;
+    const cx_t<T> cj = cnl_in[(int64_t)J * n_orb + A];
+    T re = 0, im = 0;
+    for (int k0 = 0; k0 < K; k0 += 64 * GATHER_U) {
+        int id[GATHER_U];
+        T w[GATHER_U];
+        bool sh[GATHER_U];
+#pragma unroll
+        for (int i = 0; i < GATHER_U; ++i) {
+            const int k = k0 + lane + 64 * i;
+            id[i] = k < K ? ix[k] : -1;
+            w[i] = k < K ? pp[k] : (T)0;
+            sh[i] = k < K && po[k] != 0;
+        }
+        cx_t<T> z[GATHER_U];
+#pragma unroll
+        for (int i = 0; i < GATHER_U; ++i) z[i] = id[i] >= 0 ? ua[id[i]] : cx_t<T>{(T)0, (T)0};
+#pragma unroll
+        for (int i = 0; i < GATHER_U; ++i) {
+            if (id[i] < 0) continue;
+            T sr = 0, si = 0;
+            if (!sh[i]) {
+                nl_acc<T>(w[i], cj, sr, si);
+                z[i] = nl_add<T>(z[i], sr, si, gr, gi);
+                ua[id[i]] = z[i];
+            } else {                       // shared point: the slot's pairs, in ion order
+                const int sl = map[id[i]];
+                const int n = min(cnt[sl], NL_KMAX);
+                for (int q = 0; q < n; ++q)
+                    nl_acc<T>(pl[q * ucap + sl], cnl_in[(int64_t)ion[q * ucap + sl] * n_orb + A], sr, si);
+                z[i] = nl_add<T>(z[i], sr, si, gr, gi);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < GATHER_U; ++i) {
+            re += w[i] * z[i].x;
+            im += w[i] * z[i].y;
+        }
+    }
+    re = wsum_t(re);
+    im = wsum_t(im);
+    if (lane == 0) cnl_out[(int64_t)J * n_orb + A] = cx_t<T>{scale * re, scale * im};
+}
+
+// the shared points of kb_fixup_gather_kernel: a workgroup's threads stride
+// over the listed slots, FIX_OB orbitals each (kb_fixup_kernel's arithmetic)
+template <typename T>
+__global__ void __launch_bounds__(256) kb_fix_overlap_kernel(cx_t<T>* __restrict__ out, int64_t stride, int n_orb,
+                                                             const int32_t* __restrict__ ovl,
+                                                             const int32_t* __restrict__ ovn,
+                                                             const int32_t* __restrict__ pts,
+                                                             const int32_t* __restrict__ cnt,
+                                                             const int32_t* __restrict__ ion,
+                                                             const T* __restrict__ pl, int64_t ucap,
+                                                             const cx_t<T>* __restrict__ cnl, T gr, T gi) {
+    const int A0 = blockIdx.y * FIX_OB;
+    const int na = min(FIX_OB, n_orb - A0);
+    const int nov = *ovn;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nov; e += gridDim.x * blockDim.x) {
+        const int sl = ovl[e];
+        const int n = min(cnt[sl], NL_KMAX);
+        const int64_t r = pts[sl];
+        for (int j = 0; j < na; ++j) {
+            const int A = A0 + j;
+            T sr = 0, si = 0;
+            for (int q = 0; q < n; ++q)
+                nl_acc<T>(pl[q * ucap + sl], cnl[(int64_t)ion[q * ucap + sl] * n_orb + A], sr, si);
+            cx_t<T>* o = out + (int64_t)A * stride + r;
+            *o = nl_add<T>(*o, sr, si, gr, gi);
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_kb_fixup_gather(cx_t<T>* out, int64_t stride, int n_orb, int n_ions, KbTables t,
+                                  const cx_t<T>* cnl_in, double gr, double gi, double ekb_h3, cx_t<T>* cnl_out,
+                                  hipStream_t s) {
+    if (n_ions == 0) return hipSuccess;
+    dim3 grid((n_orb + 3) / 4, n_ions);
+    kb_fixup_gather_kernel<T><<<grid, 256, 0, s>>>(out, stride, n_orb, t.idx, reinterpret_cast<const T*>(t.p),
+                                                   t.count, t.kcap, t.ov, t.map, t.cnt, t.ion,
+                                                   reinterpret_cast<const T*>(t.pl), t.ucap, cnl_in, (T)gr, (T)gi,
+                                                   (T)ekb_h3, cnl_out);
+    dim3 og(16, (n_orb + FIX_OB - 1) / FIX_OB);
+    kb_fix_overlap_kernel<T><<<og, 256, 0, s>>>(out, stride, n_orb, t.ovl, t.ovn, t.pts, t.cnt, t.ion,
+                                                reinterpret_cast<const T*>(t.pl), t.ucap, cnl_in, (T)gr, (T)gi);
+    return hipGetLastError();
+}
+
+template hipError_t launch_kb_fixup_gather<double>(double2*, int64_t, int, int, KbTables, const double2*, double,
+                                                   double, double, double2*, hipStream_t);
+template hipError_t launch_kb_fixup_gather<float>(float2*, int64_t, int, int, KbTables, const float2*, double,
+                                                  double, double, float2*, hipStream_t);
 
 // ------------------------------------------------------------ split-bf16 MFMA contraction
 // The same contraction as a matrix product on the matrix cores:
