@@ -1558,6 +1558,13 @@ me_status batch_exponential(me_batch* b, int e, bool last) {
     std::vector<const C*> u(n);
     std::vector<C*> out(n);
     for (int i = 0; i < n; ++i) u[i] = (const C*)b->sys[i]->w.psi;
+    // as in exponential(): a stage's fix-up shares a pass with the next
+    // stage's gather (plain contraction); cb[i] says which of w.cnl / w.cnl2
+    // holds system i's c_JA of the current stage's input
+    const bool fuse = !(sizeof(T) == 4 && b->sys[0]->prm.precision == ME_F32_BF16X3) &&
+                      env_int("MODEHR_FIXGATHER", 1) != 0;
+    std::vector<int> cb(n, 0);
+    bool have_c = false;
     int nb = 0;
     for (int k = K; k >= 1; --k) {
         const bool norm = last && k == 1;
@@ -1567,19 +1574,32 @@ me_status batch_exponential(me_batch* b, int e, bool last) {
             C* bufs[2] = {(C*)s->w.bufA, (C*)s->w.bufB};
             out[i] = (k == 1 && K > 1) ? (C*)s->w.psi : bufs[nb];
             const double ekb_h3 = s->prm.kb_energy * s->prm.h * s->prm.h * s->prm.h;
-            BSYS(gather<T>(s, u[i], s->g.stride, s->g.n_orb, t, ekb_h3), s);
+            if (!have_c || s->g.n_ions == 0) {
+                BSYS(gather<T>(s, u[i], s->g.stride, s->g.n_orb, t, ekb_h3), s);
+                cb[i] = 0;
+            }
         }
         CHK(batch_join(b));
         CHK(batch_stage<T>(b, u, out, e, k, norm, e * K + (K - k), k == K ? MODE_HORNER_FIRST : MODE_HORNER));
         CHK(batch_fork(b));
+        have_c = fuse && k > 1;
         for (int i = 0; i < n; ++i) {
             me_system* s = b->sys[i];
             const Geometry& g = s->g;
             const int t = e == 0 ? s->tab_cur : s->tab_cur ^ 1;
             const double tau = s->prm.dt / (2.0 * s->prm.mu);
-            if (g.n_ions > 0)
-                BHIP(launch_kb_fixup<T>(out[i], g.stride, g.n_orb, tables(s, t), (const C*)s->w.cnl, 0.0,
-                                        -tau / k, norm ? s->w.fix_part : nullptr, s->stream));
+            C* cnl_buf[2] = {(C*)s->w.cnl, (C*)s->w.cnl2};
+            if (g.n_ions > 0) {
+                if (have_c) {
+                    const double ekb_h3 = s->prm.kb_energy * s->prm.h * s->prm.h * s->prm.h;
+                    BHIP(launch_kb_fixup_gather<T>(out[i], g.stride, g.n_orb, g.n_ions, tables(s, t), cnl_buf[cb[i]],
+                                                   0.0, -tau / k, ekb_h3, cnl_buf[cb[i] ^ 1], s->stream));
+                    cb[i] ^= 1;
+                } else {
+                    BHIP(launch_kb_fixup<T>(out[i], g.stride, g.n_orb, tables(s, t), cnl_buf[cb[i]], 0.0,
+                                            -tau / k, norm ? s->w.fix_part : nullptr, s->stream));
+                }
+            }
             u[i] = out[i];
         }
         nb ^= 1;
