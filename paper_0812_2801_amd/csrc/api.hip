@@ -810,6 +810,21 @@ me_status gather(me_system* sys, const cx_t<T>* u, int64_t stride, int n_orb, in
     return ME_OK;
 }
 
+// a stage's fix-up out += alpha E_KB sum_J p_J c_J (c_J = cnl_in) fused with
+// the gather of the fixed out into cnl_out, by the precision's contraction
+template <typename T>
+hipError_t fixup_gather(me_system* sys, cx_t<T>* out, int t, const cx_t<T>* cnl_in, double alpha, double ekb_h3,
+                        cx_t<T>* cnl_out) {
+    const Geometry& g = sys->g;
+    if constexpr (sizeof(T) == 4) {
+        if (sys->prm.precision == ME_F32_BF16X3)
+            return launch_kb_fixup_gather_bf16x3(out, g.stride, g.n_orb, g.n_ions, tables(sys, t), cnl_in, 0.0, alpha,
+                                                 ekb_h3, cnl_out, sys->stream);
+    }
+    return launch_kb_fixup_gather<T>(out, g.stride, g.n_orb, g.n_ions, tables(sys, t), cnl_in, 0.0, alpha, ekb_h3,
+                                     cnl_out, sys->stream);
+}
+
 // One Taylor exponential psi <- T_K(tau, H) psi, Horner form:
 // u_K = psi, u_{k-1} = psi + (-i tau/k) H u_k, result u_0 written over psi.
 template <typename T>
@@ -824,10 +839,9 @@ me_status exponential(me_system* sys, const T* veff, int t, bool last) {
     const C* u = psi;
     int nb = 0;
     // a stage's fix-up and the next stage's gather share one pass over the
-    // projector points (plain FP32 / FP64 contraction); c_JA of the current
-    // stage's input alternates between w.cnl and w.cnl2
-    const bool fuse = g.n_ions > 0 && !(sizeof(T) == 4 && sys->prm.precision == ME_F32_BF16X3) &&
-                      env_int("MODEHR_FIXGATHER", 1) != 0;
+    // projector points; c_JA of the current stage's input alternates between
+    // w.cnl and w.cnl2
+    const bool fuse = g.n_ions > 0 && env_int("MODEHR_FIXGATHER", 1) != 0;
     C* cnl_buf[2] = {(C*)sys->w.cnl, (C*)sys->w.cnl2};
     int cb = 0;                        // cnl_buf[cb] holds c_JA of the current stage's input
     bool have_c = false;               // ... already, from the previous stage's fused pass
@@ -868,8 +882,7 @@ me_status exponential(me_system* sys, const T* veff, int t, bool last) {
         have_c = false;
         if (g.n_ions > 0) {
             if (fuse && k > 1) {
-                HIPCHK(launch_kb_fixup_gather<T>(out, g.stride, g.n_orb, g.n_ions, tables(sys, t), cnl_buf[cb], 0.0,
-                                                 -tau / k, ekb_h3, cnl_buf[cb ^ 1], sys->stream));
+                HIPCHK(fixup_gather<T>(sys, out, t, cnl_buf[cb], -tau / k, ekb_h3, cnl_buf[cb ^ 1]));
                 cb ^= 1;
                 have_c = true;
             } else {
@@ -1559,10 +1572,9 @@ me_status batch_exponential(me_batch* b, int e, bool last) {
     std::vector<C*> out(n);
     for (int i = 0; i < n; ++i) u[i] = (const C*)b->sys[i]->w.psi;
     // as in exponential(): a stage's fix-up shares a pass with the next
-    // stage's gather (plain contraction); cb[i] says which of w.cnl / w.cnl2
-    // holds system i's c_JA of the current stage's input
-    const bool fuse = !(sizeof(T) == 4 && b->sys[0]->prm.precision == ME_F32_BF16X3) &&
-                      env_int("MODEHR_FIXGATHER", 1) != 0;
+    // stage's gather; cb[i] says which of w.cnl / w.cnl2 holds system i's
+    // c_JA of the current stage's input
+    const bool fuse = env_int("MODEHR_FIXGATHER", 1) != 0;
     std::vector<int> cb(n, 0);
     bool have_c = false;
     int nb = 0;
@@ -1592,8 +1604,7 @@ me_status batch_exponential(me_batch* b, int e, bool last) {
             if (g.n_ions > 0) {
                 if (have_c) {
                     const double ekb_h3 = s->prm.kb_energy * s->prm.h * s->prm.h * s->prm.h;
-                    BHIP(launch_kb_fixup_gather<T>(out[i], g.stride, g.n_orb, g.n_ions, tables(s, t), cnl_buf[cb[i]],
-                                                   0.0, -tau / k, ekb_h3, cnl_buf[cb[i] ^ 1], s->stream));
+                    BHIP(fixup_gather<T>(s, out[i], t, cnl_buf[cb[i]], -tau / k, ekb_h3, cnl_buf[cb[i] ^ 1]));
                     cb[i] ^= 1;
                 } else {
                     BHIP(launch_kb_fixup<T>(out[i], g.stride, g.n_orb, tables(s, t), cnl_buf[cb[i]], 0.0,

@@ -171,6 +171,10 @@ template <typename T>
 hipError_t launch_kb_fixup_gather(cx_t<T>* out, int64_t stride, int n_orb, int n_ions, KbTables t,
                                   const cx_t<T>* cnl_in, double gr, double gi, double ekb_h3, cx_t<T>* cnl_out,
                                   hipStream_t s);
+// the same with the split-bf16 MFMA contraction (FP32 orbitals)
+hipError_t launch_kb_fixup_gather_bf16x3(float2* out, int64_t stride, int n_orb, int n_ions, KbTables t,
+                                         const float2* cnl_in, double gr, double gi, double ekb_h3, float2* cnl_out,
+                                         hipStream_t s);
 
 // the same contraction for FP32 orbitals as split-bf16 (bf16x3) MFMA with
 // FP32 accumulation

@@ -563,7 +563,20 @@ __device__ __forceinline__ f32x4_t mfma3(const bf16x8_t& ah, const bf16x8_t& al,
 // beside cnl.
 constexpr int BG_ROW = 32 + 2;       // LDS row of one orbital's chunk (complex), padded
 
-template <bool FORCE>
+// With FIX the loaded values are first fixed up as in kb_fixup_gather_kernel
+// (a point of one sphere in place, a shared one in registers only, written
+// later by kb_fix_overlap_kernel) and the contraction runs on the fixed values.
+struct FixArgs {
+    float2* out;                                      // the orbitals (the kernel's u, read and written)
+    const uint8_t* ov;
+    const int32_t *map, *cnt, *ion;
+    const float* pl;
+    int64_t ucap;
+    const float2* cnl_in;
+    float gr, gi;
+};
+
+template <bool FORCE, bool FIX = false>
 __global__ void __launch_bounds__(1024) kb_gather_bf16x3_kernel(const float2* __restrict__ u, int64_t stride,
                                                                 int n_orb, const int32_t* __restrict__ idx,
                                                                 const float* __restrict__ pv,
@@ -571,7 +584,7 @@ __global__ void __launch_bounds__(1024) kb_gather_bf16x3_kernel(const float2* __
                                                                 float scale, float2* __restrict__ cnl,
                                                                 const double* __restrict__ pos, KbGeom g,
                                                                 int nx, int ny, float dscale,
-                                                                float2* __restrict__ dnl) {
+                                                                float2* __restrict__ dnl, FixArgs fx = {}) {
     constexpr int NC = FORCE ? 4 : 1;                 // useful B columns
     __shared__ float2 zs[16][16][BG_ROW];             // [wave][orbital][point of the chunk]
     __shared__ float bs[16][NC][32];                  // [wave][column][point]
@@ -594,6 +607,7 @@ __global__ void __launch_bounds__(1024) kb_gather_bf16x3_kernel(const float2* __
         ry = pos[3 * J + 1];
         rz = pos[3 * J + 2];
     }
+    const float2* src = FIX ? fx.out : u;             // FIX: u is not used (it aliases the writes)
     f32x4_t dre = {0.f, 0.f, 0.f, 0.f}, dim = {0.f, 0.f, 0.f, 0.f};
     for (int k0 = 32 * wv; k0 < K; k0 += 32 * GW) {
         const int k = k0 + lp;
@@ -602,7 +616,31 @@ __global__ void __launch_bounds__(1024) kb_gather_bf16x3_kernel(const float2* __
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int a = A0 + 2 * i + lo;
-            z[i] = (id >= 0 && a < n_orb) ? u[(int64_t)a * stride + id] : make_float2(0.f, 0.f);
+            z[i] = (id >= 0 && a < n_orb) ? src[(int64_t)a * stride + id] : make_float2(0.f, 0.f);
+        }
+        if constexpr (FIX) {
+            if (id >= 0) {
+                const bool shared = fx.ov[(int64_t)J * kcap + k] != 0;
+                const float pk = pp[k];
+                const int sl = shared ? fx.map[id] : 0;
+                const int npair = shared ? min(fx.cnt[sl], NL_KMAX) : 0;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int a = A0 + 2 * i + lo;
+                    if (a >= n_orb) continue;
+                    float sr = 0.f, si = 0.f;
+                    if (!shared) {
+                        nl_acc<float>(pk, fx.cnl_in[(int64_t)J * n_orb + a], sr, si);
+                        z[i] = nl_add<float>(z[i], sr, si, fx.gr, fx.gi);
+                        fx.out[(int64_t)a * stride + id] = z[i];
+                    } else {
+                        for (int q = 0; q < npair; ++q)
+                            nl_acc<float>(fx.pl[q * fx.ucap + sl],
+                                          fx.cnl_in[(int64_t)fx.ion[q * fx.ucap + sl] * n_orb + a], sr, si);
+                        z[i] = nl_add<float>(z[i], sr, si, fx.gr, fx.gi);
+                    }
+                }
+            }
         }
 #pragma unroll
         for (int i = 0; i < 8; ++i) zs[wv][2 * i + lo][lp] = z[i];
@@ -681,6 +719,24 @@ hipError_t launch_kb_gather_bf16x3(const float2* u, int64_t stride, int n_orb, i
     kb_gather_bf16x3_kernel<false><<<grid, 64 * bf16_gather_waves(t.kcap), 0, s>>>(
         u, stride, n_orb, t.idx, reinterpret_cast<const float*>(t.p), t.count, t.kcap, (float)ekb_h3, cnl,
         nullptr, g0, 1, 1, 0.f, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_kb_fixup_gather_bf16x3(float2* out, int64_t stride, int n_orb, int n_ions, KbTables t,
+                                         const float2* cnl_in, double gr, double gi, double ekb_h3, float2* cnl_out,
+                                         hipStream_t s) {
+    if (n_ions == 0) return hipSuccess;
+    dim3 grid((n_orb + 15) / 16, n_ions);
+    KbGeom g0{};
+    FixArgs fx{out,  t.ov,   t.map,  t.cnt,     t.ion, reinterpret_cast<const float*>(t.pl),
+               t.ucap, cnl_in, (float)gr, (float)gi};
+    kb_gather_bf16x3_kernel<false, true><<<grid, 64 * bf16_gather_waves(t.kcap), 0, s>>>(
+        nullptr, stride, n_orb, t.idx, reinterpret_cast<const float*>(t.p), t.count, t.kcap, (float)ekb_h3, cnl_out,
+        nullptr, g0, 1, 1, 0.f, nullptr, fx);
+    dim3 og(16, (n_orb + FIX_OB - 1) / FIX_OB);
+    kb_fix_overlap_kernel<float><<<og, 256, 0, s>>>(out, stride, n_orb, t.ovl, t.ovn, t.pts, t.cnt, t.ion,
+                                                    reinterpret_cast<const float*>(t.pl), t.ucap, cnl_in, (float)gr,
+                                                    (float)gi);
     return hipGetLastError();
 }
 
