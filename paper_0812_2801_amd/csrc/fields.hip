@@ -29,6 +29,15 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
 }
 
 // ------------------------------------------------------------ density
+// rho(r) = occ sum_A |psi_A(r)|^2, the orbital sum in order in FP64 at each
+// point.  A thread takes two adjacent points of FP32 orbitals (one 16-byte
+// load per orbital, as for one FP64 point), and the orbital loop is unrolled
+// so that eight orbitals' loads are in flight at once.
+template <typename T>
+__device__ __forceinline__ double cabs2(cx_t<T> z) {
+    return (double)z.x * (double)z.x + (double)z.y * (double)z.y;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) density_kernel(const cx_t<T>* __restrict__ psi, int64_t stride,
                                                       int n_orb, int64_t N, double occ,
@@ -36,16 +45,45 @@ __global__ void __launch_bounds__(256) density_kernel(const cx_t<T>* __restrict_
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     double s = 0.0;
-    for (int A = 0; A < n_orb; ++A) {
-        const cx_t<T> z = psi[(int64_t)A * stride + i];
-        s += (double)z.x * (double)z.x + (double)z.y * (double)z.y;
-    }
+#pragma unroll 8
+    for (int A = 0; A < n_orb; ++A) s += cabs2<T>(psi[(int64_t)A * stride + i]);
     rho[i] = occ * s;
+}
+
+// FP32 orbitals, points 2i and 2i + 1 (stride and psi 16-byte aligned)
+__global__ void __launch_bounds__(256) density_pair_kernel(const float4* __restrict__ psi, int64_t stride2,
+                                                           int n_orb, int64_t N, double occ,
+                                                           double* __restrict__ rho) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (2 * i >= N) return;
+    double s0 = 0.0, s1 = 0.0;
+    if (2 * i + 1 < N) {
+#pragma unroll 8
+        for (int A = 0; A < n_orb; ++A) {
+            const float4 z = psi[(int64_t)A * stride2 + i];
+            s0 += cabs2<float>(make_float2(z.x, z.y));
+            s1 += cabs2<float>(make_float2(z.z, z.w));
+        }
+        rho[2 * i] = occ * s0;
+        rho[2 * i + 1] = occ * s1;
+    } else {                                          // odd N: the last point alone
+        const float2* p = reinterpret_cast<const float2*>(psi);
+        for (int A = 0; A < n_orb; ++A) s0 += cabs2<float>(p[(int64_t)A * 2 * stride2 + 2 * i]);
+        rho[2 * i] = occ * s0;
+    }
 }
 
 template <typename T>
 hipError_t launch_density(const cx_t<T>* psi, int64_t stride, int n_orb, int64_t N,
                           double occ, double* rho, hipStream_t s) {
+    if constexpr (sizeof(T) == 4) {
+        if (stride % 2 == 0 && reinterpret_cast<uintptr_t>(psi) % 16 == 0) {
+            const int64_t pairs = (N + 1) / 2;
+            density_pair_kernel<<<(unsigned)((pairs + 255) / 256), 256, 0, s>>>(
+                reinterpret_cast<const float4*>(psi), stride / 2, n_orb, N, occ, rho);
+            return hipGetLastError();
+        }
+    }
     density_kernel<T><<<(unsigned)((N + 255) / 256), 256, 0, s>>>(psi, stride, n_orb, N, occ, rho);
     return hipGetLastError();
 }
