@@ -401,6 +401,10 @@ me_status me_propagate_batch(me_batch* b, int32_t n_steps, int32_t use_graph);
  * me_timing_read. */
 me_status me_batch_timing_enable(me_batch* b, int32_t enable);
 me_status me_batch_timing_read(me_batch* b, int64_t* launches, double* total_ms, double* total_bytes);
+/* The same for one kind of Horner stage (streams = 2, 3 or 0), as
+ * me_timing_read_kind. */
+me_status me_batch_timing_read_kind(me_batch* b, int32_t streams, int64_t* launches, double* total_ms,
+                                    double* total_bytes);
 
 /* Text of the last error of a batch call; NULL b gives the last error of a
  * failed me_init_batch on this thread. */

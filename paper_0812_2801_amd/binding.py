@@ -31,7 +31,7 @@ SYMBOLS = [
     "me_batch_workspace_size", "me_init_batch", "me_batch_system", "me_batch_set_tuning",
     "me_batch_get_tuning", "me_batch_autotune", "me_propagate_batch", "me_batch_timing_enable",
     "me_batch_timing_read", "me_batch_last_error", "me_batch_destroy",
-    "me_toy_run", "me_toy_distance", "me_dipole_noalloc", "me_timing_read_kind",
+    "me_toy_run", "me_toy_distance", "me_dipole_noalloc", "me_timing_read_kind", "me_batch_timing_read_kind",
 ]
 
 
@@ -139,6 +139,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.me_propagate_batch.argtypes = [c_void_p, c_int32, c_int32]
     lib.me_batch_timing_enable.argtypes = [c_void_p, c_int32]
     lib.me_batch_timing_read.argtypes = [c_void_p, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]
+    lib.me_batch_timing_read_kind.argtypes = [c_void_p, c_int32, POINTER(c_int64), POINTER(c_double),
+                                              POINTER(c_double)]
     lib.me_batch_last_error.restype = c_char_p
     lib.me_batch_last_error.argtypes = [c_void_p]
     lib.me_batch_destroy.argtypes = [c_void_p]
@@ -494,11 +496,14 @@ class Batch:
     def timing_enable(self, on: bool = True):
         self._check(self.lib.me_batch_timing_enable(self.h, c_int32(1 if on else 0)))
 
-    def timing_read(self):
+    def timing_read(self, streams: int = 0):
+        """(launches, total ms, algorithmic bytes) of the timed stencil
+        launches: streams 2 the first stages, 3 the others, 0 all."""
         n = c_int64(0)
         ms = c_double(0)
         by = c_double(0)
-        self._check(self.lib.me_batch_timing_read(self.h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+        self._check(self.lib.me_batch_timing_read_kind(self.h, c_int32(streams), ctypes.byref(n), ctypes.byref(ms),
+                                                       ctypes.byref(by)))
         return n.value, ms.value, by.value
 
 

@@ -1312,6 +1312,7 @@ struct me_batch {
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     std::vector<double> ev_bytes;
+    std::vector<int> ev_streams;    // complex streams of each timed launch (2: first stage, 3: others)
     std::vector<hipEvent_t> ev_pool;
     std::string err;
 };
@@ -1556,6 +1557,7 @@ me_status batch_stage(me_batch* b, const std::vector<const cx_t<T>*>& u, const s
         BHIP(hipEventRecord(e1, b->stream));
         b->ev.emplace_back(e0, e1);
         b->ev_bytes.push_back(bytes);
+        b->ev_streams.push_back(mode == MODE_HORNER_FIRST ? 2 : 3);
     }
     return ME_OK;
 }
@@ -1802,9 +1804,15 @@ me_status batch_time_stage(me_batch* b, int reps, double* ms) {
     const int n = (int)b->sys.size();
     std::vector<const C*> u(n);
     std::vector<C*> out(n);
+    // a three-stream stage as in a step: u (a copy of psi in bufA), psi0 and
+    // the output (bufB) are three distinct arrays, so that the timing sees
+    // the step's memory traffic (with u = psi0 the second read hits cache)
     for (int i = 0; i < n; ++i) {
-        u[i] = (const C*)b->sys[i]->w.psi;
-        out[i] = (C*)b->sys[i]->w.bufA;
+        me_system* s = b->sys[i];
+        BHIP(hipMemcpyAsync(s->w.bufA, s->w.psi, (size_t)s->g.n_orb * s->g.stride * sizeof(C),
+                            hipMemcpyDeviceToDevice, b->stream));
+        u[i] = (const C*)s->w.bufA;
+        out[i] = (C*)s->w.bufB;
     }
     const int slot = 2 * b->K;                 // the tuning slot, outside a step's range
     const bool timing = b->timing;
@@ -2834,24 +2842,34 @@ me_status me_batch_timing_enable(me_batch* b, int32_t enable) {
     for (auto& e : b->ev) { b->ev_pool.push_back(e.first); b->ev_pool.push_back(e.second); }
     b->ev.clear();
     b->ev_bytes.clear();
+    b->ev_streams.clear();
     b->timing = enable != 0;
     return ME_OK;
 }
 
-me_status me_batch_timing_read(me_batch* b, int64_t* launches, double* total_ms, double* total_bytes) {
-    if (!b || !launches || !total_ms || !total_bytes) return ME_EINVAL;
+me_status me_batch_timing_read_kind(me_batch* b, int32_t streams, int64_t* launches, double* total_ms,
+                                    double* total_bytes) {
+    if (!b || !launches || !total_ms || !total_bytes || (streams != 0 && streams != 2 && streams != 3))
+        return ME_EINVAL;
     BHIP(hipStreamSynchronize(b->stream));
     double ms = 0.0, by = 0.0;
+    int64_t n = 0;
     for (size_t i = 0; i < b->ev.size(); ++i) {
+        if (streams != 0 && b->ev_streams[i] != streams) continue;
         float t = 0.f;
         BHIP(hipEventElapsedTime(&t, b->ev[i].first, b->ev[i].second));
         ms += t;
         by += b->ev_bytes[i];
+        ++n;
     }
-    *launches = (int64_t)b->ev.size();
+    *launches = n;
     *total_ms = ms;
     *total_bytes = by;
     return ME_OK;
+}
+
+me_status me_batch_timing_read(me_batch* b, int64_t* launches, double* total_ms, double* total_bytes) {
+    return me_batch_timing_read_kind(b, 0, launches, total_ms, total_bytes);
 }
 
 const char* me_batch_last_error(const me_batch* b) {
