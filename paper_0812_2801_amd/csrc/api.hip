@@ -315,6 +315,7 @@ struct Layout {
     int32_t* tcount[2];
     uint8_t* tov[2];            // per table point: covered by more than one sphere
     int32_t *tovl[2], *tovn[2]; // slots covered by more than one sphere, and their count
+    int32_t* tovc[2];           // counters of the fused fix-up + gather pass
     double *fnl, *enl_part, *kbf_part, *floc_part, *floc, *fion, *eion_part, *erec_part;
     double *ewald_gv, *ewald_wv, *ewald_part;
     double *norm_part, *fix_part, *norms, *kin_part, *hxc_part, *loc_part, *rep, *scal0;
@@ -388,6 +389,7 @@ static Layout carve(const Geometry& g, char* base) {
         L.tov[t] = c.take<uint8_t>((size_t)std::max(1, g.n_ions) * g.kcap);
         L.tovl[t] = c.take<int32_t>((size_t)g.ucap * 4);
         L.tovn[t] = c.take<int32_t>(4);
+        L.tovc[t] = c.take<int32_t>((size_t)((g.n_orb + 3) / 4) * 4);
     }
     L.fnl = c.take<double>(ion3);
     L.enl_part = c.take<double>(ion3 / 3);
@@ -552,6 +554,8 @@ KbTables tables(me_system* sys, int t) {
     k.ov = sys->w.tov[t];
     k.ovl = sys->w.tovl[t];
     k.ovn = sys->w.tovn[t];
+    k.ovc = sys->w.tovc[t];
+    k.novc = (sys->g.n_orb + 3) / 4;
     k.ucap = sys->g.ucap;
     return k;
 }

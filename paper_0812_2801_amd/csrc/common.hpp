@@ -67,6 +67,8 @@ struct KbTables {
     uint8_t* ov;       // [n_ions][kcap] 1 where the table point is covered by another sphere too
     int32_t* ovl;      // [ucap] slots covered by more than one sphere (any order), count in *ovn
     int32_t* ovn;      // [1]
+    int32_t* ovc;      // [novc] finished workgroups of each orbital group of the fused fix-up +
+    int novc;          // gather pass (zero between launches; one counter per 4 orbitals)
 };
 
 enum StencilMode : int {
@@ -164,9 +166,10 @@ hipError_t launch_kb_gather(const cx_t<T>* u, int64_t stride, int n_orb, int n_i
 // projector points: out_A(r) += (gr + i gi) sum_J p_J(r) cnl_in[J][A], then
 // cnl_out[J][A] = ekb_h3 sum_k p_J(k) out_A(idx_J(k)) of the fixed values.
 // Points covered by one sphere are fixed in place by that sphere's pass;
-// points covered by several are fixed by kb_fix_overlap_kernel afterwards
-// (inside this launch each pass computes their fixed value for its own sum
-// without writing it), so every sum has a fixed order.
+// points covered by several are written by the last workgroup of each
+// orbital group to finish (each pass computes their fixed value for its own
+// sum without writing it), so every sum has a fixed order.  Needs t.ovc
+// zeroed (launch_kb_tables does it; each launch leaves it zero).
 template <typename T>
 hipError_t launch_kb_fixup_gather(cx_t<T>* out, int64_t stride, int n_orb, int n_ions, KbTables t,
                                   const cx_t<T>* cnl_in, double gr, double gi, double ekb_h3, cx_t<T>* cnl_out,

@@ -256,6 +256,7 @@ hipError_t launch_kb_tables(const double* pos, int n_ions, int nx, int ny, int n
     nl_sort_kernel<T><<<(unsigned)((t.ucap + 255) / 256), 256, 0, s>>>(t.nslots, t.cnt, t.ion,
                                                                        reinterpret_cast<T*>(t.pl), t.ucap);
     fill_i32_kernel<<<1, 64, 0, s>>>(t.ovn, 1, 0);
+    if (t.novc > 0) fill_i32_kernel<<<(unsigned)((t.novc + 255) / 256), 256, 0, s>>>(t.ovc, t.novc, 0);
     nl_overlap_points_kernel<<<eg, 256, 0, s>>>(t.idx, t.count, t.kcap, t.map, t.cnt, t.ov);
     nl_overlap_slots_kernel<<<(unsigned)((t.ucap + 255) / 256), 256, 0, s>>>(t.nslots, t.cnt, t.ovl, t.ovn);
     return hipGetLastError();
@@ -401,95 +402,113 @@ hipError_t launch_kb_gather(const cx_t<T>* u, int64_t stride, int n_orb, int n_i
 // loads are issued before the sums), each point's value fixed before it is
 // summed.  A point of one sphere only is fixed in place here (its pass is
 // the only one that touches it); a point shared with other spheres gets
-// its fixed value computed from the slot's (ion, value) pairs for the sum
-// and is written by kb_fix_overlap_kernel after this launch.  The fix-up
-// arithmetic is kb_fixup_kernel's (nl_acc / nl_add), the sums are
+// its fixed value computed from the slot's (ion, value) pairs for the sum,
+// and is written by the last workgroup of its orbital group to finish (the
+// workgroups of one orbital group, one per ion, count themselves in ovc):
+// by then every pass has read the shared points' unfixed values.  The
+// fix-up arithmetic is kb_fixup_kernel's (nl_acc / nl_add), the sums are
 // kb_gather_kernel's.
+
+// the shared points of orbitals A0 .. A0 + na - 1, by the threads of one
+// workgroup (kb_fixup_kernel's arithmetic), then the group's counter reset
+template <typename T>
+__device__ void fix_shared_points(cx_t<T>* __restrict__ out, int64_t stride, int n_orb, int A0, int na,
+                                  const int32_t* __restrict__ ovl, const int32_t* __restrict__ ovn,
+                                  const int32_t* __restrict__ pts, const int32_t* __restrict__ cnt,
+                                  const int32_t* __restrict__ ion, const T* __restrict__ pl, int64_t ucap,
+                                  const cx_t<T>* __restrict__ cnl, T gr, T gi, int32_t* ovc_g) {
+    const int nov = *ovn;
+    for (int e = threadIdx.x; e < nov * na; e += blockDim.x) {
+        const int sl = ovl[e / na];
+        const int A = A0 + e % na;
+        const int n = min(cnt[sl], NL_KMAX);
+        T sr = 0, si = 0;
+        for (int q = 0; q < n; ++q)
+            nl_acc<T>(pl[q * ucap + sl], cnl[(int64_t)ion[q * ucap + sl] * n_orb + A], sr, si);
+        cx_t<T>* o = out + (int64_t)A * stride + pts[sl];
+        *o = nl_add<T>(*o, sr, si, gr, gi);
+    }
+    if (threadIdx.x == 0) atomicExch(ovc_g, 0);
+}
+
+// true in every thread of the workgroup that finishes its orbital group last
+// (gridDim.y workgroups per group).  A workgroup counts itself after every
+// load of its points has returned (their values are in its sums), so the
+// last one's stores come after all the group's reads.  No other ordering is
+// needed (the shared points and c_JA are not written by the other
+// workgroups), so the count is a relaxed device-scope atomic and no fence is
+// taken: a device-scope fence writes back or invalidates the XCD's L2.
+__device__ __forceinline__ bool last_of_group(int32_t* ovc_g, int* flag) {
+    __syncthreads();
+    if (threadIdx.x == 0) *flag = atomicAdd(ovc_g, 1) == (int)gridDim.y - 1;
+    __syncthreads();
+    return *flag != 0;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) kb_fixup_gather_kernel(
     cx_t<T>* __restrict__ out, int64_t stride, int n_orb, const int32_t* __restrict__ idx,
     const T* __restrict__ pv, const int32_t* __restrict__ count, int kcap, const uint8_t* __restrict__ ov,
     const int32_t* __restrict__ map, const int32_t* __restrict__ cnt, const int32_t* __restrict__ ion,
     const T* __restrict__ pl, int64_t ucap, const cx_t<T>* __restrict__ cnl_in, T gr, T gi, T scale,
-    cx_t<T>* __restrict__ cnl_out) {
+    cx_t<T>* __restrict__ cnl_out, const int32_t* __restrict__ ovl, const int32_t* __restrict__ ovn,
+    const int32_t* __restrict__ pts, int32_t* __restrict__ ovc) {
+    __shared__ int last;
     const int J = blockIdx.y;
     const int lane = threadIdx.x & 63;
     const int A = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (A >= n_orb) return;
-    const int K = count[J];
-    const int32_t* ix = idx + (int64_t)J * kcap;
-    const T* pp = pv + (int64_t)J * kcap;
-    const uint8_t* po = ov + (int64_t)J * kcap;
-    cx_t<T>* ua = out + (int64_t)A * stride;
-    const cx_t<T> cj = cnl_in[(int64_t)J * n_orb + A];
-    T re = 0, im = 0;
-    for (int k0 = 0; k0 < K; k0 += 64 * GATHER_U) {
-        int id[GATHER_U];
-        T w[GATHER_U];
-        bool sh[GATHER_U];
+    if (A < n_orb) {
+        const int K = count[J];
+        const int32_t* ix = idx + (int64_t)J * kcap;
+        const T* pp = pv + (int64_t)J * kcap;
+        const uint8_t* po = ov + (int64_t)J * kcap;
+        cx_t<T>* ua = out + (int64_t)A * stride;
+        const cx_t<T> cj = cnl_in[(int64_t)J * n_orb + A];
+        T re = 0, im = 0;
+        for (int k0 = 0; k0 < K; k0 += 64 * GATHER_U) {
+            int id[GATHER_U];
+            T w[GATHER_U];
+            bool sh[GATHER_U];
 #pragma unroll
-        for (int i = 0; i < GATHER_U; ++i) {
-            const int k = k0 + lane + 64 * i;
-            id[i] = k < K ? ix[k] : -1;
-            w[i] = k < K ? pp[k] : (T)0;
-            sh[i] = k < K && po[k] != 0;
-        }
-        cx_t<T> z[GATHER_U];
+            for (int i = 0; i < GATHER_U; ++i) {
+                const int k = k0 + lane + 64 * i;
+                id[i] = k < K ? ix[k] : -1;
+                w[i] = k < K ? pp[k] : (T)0;
+                sh[i] = k < K && po[k] != 0;
+            }
+            cx_t<T> z[GATHER_U];
 #pragma unroll
-        for (int i = 0; i < GATHER_U; ++i) z[i] = id[i] >= 0 ? ua[id[i]] : cx_t<T>{(T)0, (T)0};
+            for (int i = 0; i < GATHER_U; ++i) z[i] = id[i] >= 0 ? ua[id[i]] : cx_t<T>{(T)0, (T)0};
 #pragma unroll
-        for (int i = 0; i < GATHER_U; ++i) {
-            if (id[i] < 0) continue;
-            T sr = 0, si = 0;
-            if (!sh[i]) {
-                nl_acc<T>(w[i], cj, sr, si);
-                z[i] = nl_add<T>(z[i], sr, si, gr, gi);
-                ua[id[i]] = z[i];
-            } else {                       // shared point: the slot's pairs, in ion order
-                const int sl = map[id[i]];
-                const int n = min(cnt[sl], NL_KMAX);
-                for (int q = 0; q < n; ++q)
-                    nl_acc<T>(pl[q * ucap + sl], cnl_in[(int64_t)ion[q * ucap + sl] * n_orb + A], sr, si);
-                z[i] = nl_add<T>(z[i], sr, si, gr, gi);
+            for (int i = 0; i < GATHER_U; ++i) {
+                if (id[i] < 0) continue;
+                T sr = 0, si = 0;
+                if (!sh[i]) {
+                    nl_acc<T>(w[i], cj, sr, si);
+                    z[i] = nl_add<T>(z[i], sr, si, gr, gi);
+                    ua[id[i]] = z[i];
+                } else {                       // shared point: the slot's pairs, in ion order
+                    const int sl = map[id[i]];
+                    const int n = min(cnt[sl], NL_KMAX);
+                    for (int q = 0; q < n; ++q)
+                        nl_acc<T>(pl[q * ucap + sl], cnl_in[(int64_t)ion[q * ucap + sl] * n_orb + A], sr, si);
+                    z[i] = nl_add<T>(z[i], sr, si, gr, gi);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < GATHER_U; ++i) {
+                re += w[i] * z[i].x;
+                im += w[i] * z[i].y;
             }
         }
-#pragma unroll
-        for (int i = 0; i < GATHER_U; ++i) {
-            re += w[i] * z[i].x;
-            im += w[i] * z[i].y;
-        }
+        re = wsum_t(re);
+        im = wsum_t(im);
+        if (lane == 0) cnl_out[(int64_t)J * n_orb + A] = cx_t<T>{scale * re, scale * im};
     }
-    re = wsum_t(re);
-    im = wsum_t(im);
-    if (lane == 0) cnl_out[(int64_t)J * n_orb + A] = cx_t<T>{scale * re, scale * im};
-}
-
-// the shared points of kb_fixup_gather_kernel: a workgroup's threads stride
-// over the listed slots, FIX_OB orbitals each (kb_fixup_kernel's arithmetic)
-template <typename T>
-__global__ void __launch_bounds__(256) kb_fix_overlap_kernel(cx_t<T>* __restrict__ out, int64_t stride, int n_orb,
-                                                             const int32_t* __restrict__ ovl,
-                                                             const int32_t* __restrict__ ovn,
-                                                             const int32_t* __restrict__ pts,
-                                                             const int32_t* __restrict__ cnt,
-                                                             const int32_t* __restrict__ ion,
-                                                             const T* __restrict__ pl, int64_t ucap,
-                                                             const cx_t<T>* __restrict__ cnl, T gr, T gi) {
-    const int A0 = blockIdx.y * FIX_OB;
-    const int na = min(FIX_OB, n_orb - A0);
-    const int nov = *ovn;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nov; e += gridDim.x * blockDim.x) {
-        const int sl = ovl[e];
-        const int n = min(cnt[sl], NL_KMAX);
-        const int64_t r = pts[sl];
-        for (int j = 0; j < na; ++j) {
-            const int A = A0 + j;
-            T sr = 0, si = 0;
-            for (int q = 0; q < n; ++q)
-                nl_acc<T>(pl[q * ucap + sl], cnl[(int64_t)ion[q * ucap + sl] * n_orb + A], sr, si);
-            cx_t<T>* o = out + (int64_t)A * stride + r;
-            *o = nl_add<T>(*o, sr, si, gr, gi);
-        }
+    if (last_of_group(ovc + blockIdx.x, &last)) {
+        const int A0 = blockIdx.x * 4;
+        fix_shared_points<T>(out, stride, n_orb, A0, min(4, n_orb - A0), ovl, ovn, pts, cnt, ion, pl, ucap, cnl_in,
+                             gr, gi, ovc + blockIdx.x);
     }
 }
 
@@ -498,14 +517,12 @@ hipError_t launch_kb_fixup_gather(cx_t<T>* out, int64_t stride, int n_orb, int n
                                   const cx_t<T>* cnl_in, double gr, double gi, double ekb_h3, cx_t<T>* cnl_out,
                                   hipStream_t s) {
     if (n_ions == 0) return hipSuccess;
+    if (t.novc < (n_orb + 3) / 4) return hipErrorInvalidValue;
     dim3 grid((n_orb + 3) / 4, n_ions);
     kb_fixup_gather_kernel<T><<<grid, 256, 0, s>>>(out, stride, n_orb, t.idx, reinterpret_cast<const T*>(t.p),
                                                    t.count, t.kcap, t.ov, t.map, t.cnt, t.ion,
                                                    reinterpret_cast<const T*>(t.pl), t.ucap, cnl_in, (T)gr, (T)gi,
-                                                   (T)ekb_h3, cnl_out);
-    dim3 og(16, (n_orb + FIX_OB - 1) / FIX_OB);
-    kb_fix_overlap_kernel<T><<<og, 256, 0, s>>>(out, stride, n_orb, t.ovl, t.ovn, t.pts, t.cnt, t.ion,
-                                                reinterpret_cast<const T*>(t.pl), t.ucap, cnl_in, (T)gr, (T)gi);
+                                                   (T)ekb_h3, cnl_out, t.ovl, t.ovn, t.pts, t.ovc);
     return hipGetLastError();
 }
 
@@ -564,8 +581,9 @@ __device__ __forceinline__ f32x4_t mfma3(const bf16x8_t& ah, const bf16x8_t& al,
 constexpr int BG_ROW = 32 + 2;       // LDS row of one orbital's chunk (complex), padded
 
 // With FIX the loaded values are first fixed up as in kb_fixup_gather_kernel
-// (a point of one sphere in place, a shared one in registers only, written
-// later by kb_fix_overlap_kernel) and the contraction runs on the fixed values.
+// (a point of one sphere in place, a shared one in registers for the sum and
+// written by the last workgroup of the orbital group) and the contraction
+// runs on the fixed values.
 struct FixArgs {
     float2* out;                                      // the orbitals (the kernel's u, read and written)
     const uint8_t* ov;
@@ -574,6 +592,8 @@ struct FixArgs {
     int64_t ucap;
     const float2* cnl_in;
     float gr, gi;
+    const int32_t *ovl, *ovn, *pts;
+    int32_t* ovc;
 };
 
 template <bool FORCE, bool FIX = false>
@@ -700,6 +720,12 @@ __global__ void __launch_bounds__(1024) kb_gather_bf16x3_kernel(const float2* __
                 dnl[((int64_t)J * n_orb + A0 + o) * 3 + (c - 1)] = make_float2(dscale * vr, dscale * vi);
         }
     }
+    if constexpr (FIX) {
+        __shared__ int last;
+        if (last_of_group(fx.ovc + blockIdx.x, &last))
+            fix_shared_points<float>(fx.out, stride, n_orb, A0, min(16, n_orb - A0), fx.ovl, fx.ovn, fx.pts, fx.cnt,
+                                     fx.ion, fx.pl, fx.ucap, fx.cnl_in, fx.gr, fx.gi, fx.ovc + blockIdx.x);
+    }
 }
 
 // waves per workgroup: one per 32-point chunk of the largest ion list, at most
@@ -728,15 +754,12 @@ hipError_t launch_kb_fixup_gather_bf16x3(float2* out, int64_t stride, int n_orb,
     if (n_ions == 0) return hipSuccess;
     dim3 grid((n_orb + 15) / 16, n_ions);
     KbGeom g0{};
-    FixArgs fx{out,  t.ov,   t.map,  t.cnt,     t.ion, reinterpret_cast<const float*>(t.pl),
-               t.ucap, cnl_in, (float)gr, (float)gi};
+    if (t.novc < (n_orb + 15) / 16) return hipErrorInvalidValue;
+    FixArgs fx{out,    t.ov,      t.map,     t.cnt, t.ion, reinterpret_cast<const float*>(t.pl),
+               t.ucap, cnl_in,    (float)gr, (float)gi, t.ovl, t.ovn, t.pts, t.ovc};
     kb_gather_bf16x3_kernel<false, true><<<grid, 64 * bf16_gather_waves(t.kcap), 0, s>>>(
         nullptr, stride, n_orb, t.idx, reinterpret_cast<const float*>(t.p), t.count, t.kcap, (float)ekb_h3, cnl_out,
         nullptr, g0, 1, 1, 0.f, nullptr, fx);
-    dim3 og(16, (n_orb + FIX_OB - 1) / FIX_OB);
-    kb_fix_overlap_kernel<float><<<og, 256, 0, s>>>(out, stride, n_orb, t.ovl, t.ovn, t.pts, t.cnt, t.ion,
-                                                    reinterpret_cast<const float*>(t.pl), t.ucap, cnl_in, (float)gr,
-                                                    (float)gi);
     return hipGetLastError();
 }
 

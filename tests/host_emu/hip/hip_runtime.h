@@ -108,6 +108,7 @@ hipError_t launch(dim3 grid, dim3 block, F f, A... args) {
 #define blockDim emu::blockDim_v
 #define gridDim emu::gridDim_v
 inline void __syncthreads() { emu::syncthreads(); }
+inline void __threadfence() {}
 
 template <class T>
 inline T __shfl_xor(T v, int mask, int width = 64) {
@@ -130,6 +131,7 @@ inline unsigned long long __ballot(int pred) {
 inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
 // work-items run one at a time between switch points, so read-modify-write is atomic
 inline int atomicAdd(int* p, int v) { const int o = *p; *p = o + v; return o; }
+inline int atomicExch(int* p, int v) { const int o = *p; *p = v; return o; }
 inline int atomicOr(int* p, int v) { const int o = *p; *p = o | v; return o; }
 
 typedef __bf16 emu_bf16x8 __attribute__((ext_vector_type(8)));
