@@ -381,7 +381,8 @@ me_status me_batch_system(me_batch* b, int32_t i, me_system** out);
 me_status me_batch_set_tuning(me_batch* b, const me_batch_tuning* t);
 me_status me_batch_get_tuning(const me_batch* b, me_batch_tuning* t);
 
-/* Autotuner: times one Horner stage over the batch for every launch shape
+/* Autotuner: times three-stream Horner stages over the batch (on a copy of
+ * the orbitals in the scratch buffers) for every launch shape
  * (block 256..1024, wg_per_cu 0..4, zdiv 1/2/4) that fits, keeps the
  * fastest, and returns it in *out (nullable).  With cache_path (nullable) a
  * JSON file keyed by precision, Taylor order and the systems' shapes is

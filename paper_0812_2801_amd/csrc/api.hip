@@ -1858,7 +1858,7 @@ me_status batch_autotune(me_batch* b, me_batch_tuning* best) {
                 t.wg_per_cu = w;
                 if (batch_apply_tuning(b, t) != ME_OK) continue;
                 double ms = 0.0;
-                CHK(batch_time_stage<T>(b, 3, &ms));
+                CHK(batch_time_stage<T>(b, 8, &ms));
                 if (!any || ms < best->stage_ms) {
                     *best = t;
                     best->stage_ms = ms;
