@@ -1,9 +1,8 @@
 // Gaussian s-channel Kleinman-Bylander projector: per-ion point tables,
 // the contraction c_JA = h^3 sum_k p_J(r_k) psi_A(r_k) and the nonlocal
 // forces / energy.  The scatter E_KB sum_J p_J c_JA is added at the
-// projector points by kb_fixup_kernel after each stencil pass.
-#include <cstdlib>
-
+// projector points after each stencil pass, by kb_fixup_kernel or, together
+// with the next stage's contraction, by kb_fixup_gather_kernel.
 #include "common.hpp"
 #include "geometry.hpp"
 
@@ -445,7 +444,7 @@ __device__ __forceinline__ bool last_of_group(int32_t* ovc_g, int* flag) {
     return *flag != 0;
 }
 
-template <typename T>
+template <typename T, int ORB>
 __global__ void __launch_bounds__(256) kb_fixup_gather_kernel(
     cx_t<T>* __restrict__ out, int64_t stride, int n_orb, const int32_t* __restrict__ idx,
     const T* __restrict__ pv, const int32_t* __restrict__ count, int kcap, const uint8_t* __restrict__ ov,
@@ -456,15 +455,21 @@ __global__ void __launch_bounds__(256) kb_fixup_gather_kernel(
     __shared__ int last;
     const int J = blockIdx.y;
     const int lane = threadIdx.x & 63;
-    const int A = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (A < n_orb) {
+    const int G = 4 * ORB;                         // orbitals of the workgroup: ORB consecutive per wave
+    const int A0 = blockIdx.x * G + (threadIdx.x >> 6) * ORB;
+    if (A0 < n_orb) {
         const int K = count[J];
         const int32_t* ix = idx + (int64_t)J * kcap;
         const T* pp = pv + (int64_t)J * kcap;
         const uint8_t* po = ov + (int64_t)J * kcap;
-        cx_t<T>* ua = out + (int64_t)A * stride;
-        const cx_t<T> cj = cnl_in[(int64_t)J * n_orb + A];
-        T re = 0, im = 0;
+        cx_t<T> cj[ORB];
+        T re[ORB], im[ORB];
+#pragma unroll
+        for (int o = 0; o < ORB; ++o) {
+            cj[o] = A0 + o < n_orb ? cnl_in[(int64_t)J * n_orb + A0 + o] : cx_t<T>{(T)0, (T)0};
+            re[o] = 0;
+            im[o] = 0;
+        }
         for (int k0 = 0; k0 < K; k0 += 64 * GATHER_U) {
             int id[GATHER_U];
             T w[GATHER_U];
@@ -476,40 +481,63 @@ __global__ void __launch_bounds__(256) kb_fixup_gather_kernel(
                 w[i] = k < K ? pp[k] : (T)0;
                 sh[i] = k < K && po[k] != 0;
             }
-            cx_t<T> z[GATHER_U];
+            cx_t<T> z[ORB][GATHER_U];
 #pragma unroll
-            for (int i = 0; i < GATHER_U; ++i) z[i] = id[i] >= 0 ? ua[id[i]] : cx_t<T>{(T)0, (T)0};
+            for (int o = 0; o < ORB; ++o) {
+                const cx_t<T>* ua = out + (int64_t)(A0 + o) * stride;
 #pragma unroll
-            for (int i = 0; i < GATHER_U; ++i) {
-                if (id[i] < 0) continue;
-                T sr = 0, si = 0;
-                if (!sh[i]) {
-                    nl_acc<T>(w[i], cj, sr, si);
-                    z[i] = nl_add<T>(z[i], sr, si, gr, gi);
-                    ua[id[i]] = z[i];
-                } else {                       // shared point: the slot's pairs, in ion order
-                    const int sl = map[id[i]];
-                    const int n = min(cnt[sl], NL_KMAX);
-                    for (int q = 0; q < n; ++q)
-                        nl_acc<T>(pl[q * ucap + sl], cnl_in[(int64_t)ion[q * ucap + sl] * n_orb + A], sr, si);
-                    z[i] = nl_add<T>(z[i], sr, si, gr, gi);
+                for (int i = 0; i < GATHER_U; ++i)
+                    z[o][i] = (id[i] >= 0 && A0 + o < n_orb) ? ua[id[i]] : cx_t<T>{(T)0, (T)0};
+            }
+#pragma unroll
+            for (int o = 0; o < ORB; ++o) {
+                const int A = A0 + o;
+                if (A >= n_orb) continue;
+                cx_t<T>* ua = out + (int64_t)A * stride;
+#pragma unroll
+                for (int i = 0; i < GATHER_U; ++i) {
+                    if (id[i] < 0) continue;
+                    T sr = 0, si = 0;
+                    if (!sh[i]) {
+                        nl_acc<T>(w[i], cj[o], sr, si);
+                        z[o][i] = nl_add<T>(z[o][i], sr, si, gr, gi);
+                        ua[id[i]] = z[o][i];
+                    } else {                   // shared point: the slot's pairs, in ion order
+                        const int sl = map[id[i]];
+                        const int n = min(cnt[sl], NL_KMAX);
+                        for (int q = 0; q < n; ++q)
+                            nl_acc<T>(pl[q * ucap + sl], cnl_in[(int64_t)ion[q * ucap + sl] * n_orb + A], sr, si);
+                        z[o][i] = nl_add<T>(z[o][i], sr, si, gr, gi);
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < GATHER_U; ++i) {
+                    re[o] += w[i] * z[o][i].x;
+                    im[o] += w[i] * z[o][i].y;
                 }
             }
-#pragma unroll
-            for (int i = 0; i < GATHER_U; ++i) {
-                re += w[i] * z[i].x;
-                im += w[i] * z[i].y;
-            }
         }
-        re = wsum_t(re);
-        im = wsum_t(im);
-        if (lane == 0) cnl_out[(int64_t)J * n_orb + A] = cx_t<T>{scale * re, scale * im};
+#pragma unroll
+        for (int o = 0; o < ORB; ++o) {
+            const T r = wsum_t(re[o]);
+            const T m = wsum_t(im[o]);
+            if (lane == 0 && A0 + o < n_orb) cnl_out[(int64_t)J * n_orb + A0 + o] = cx_t<T>{scale * r, scale * m};
+        }
     }
     if (last_of_group(ovc + blockIdx.x, &last)) {
-        const int A0 = blockIdx.x * 4;
-        fix_shared_points<T>(out, stride, n_orb, A0, min(4, n_orb - A0), ovl, ovn, pts, cnt, ion, pl, ucap, cnl_in,
+        const int B0 = blockIdx.x * G;
+        fix_shared_points<T>(out, stride, n_orb, B0, min(G, n_orb - B0), ovl, ovn, pts, cnt, ion, pl, ucap, cnl_in,
                              gr, gi, ovc + blockIdx.x);
     }
+}
+
+template <typename T, int ORB>
+void launch_fg(cx_t<T>* out, int64_t stride, int n_orb, int n_ions, const KbTables& t, const cx_t<T>* cnl_in,
+               double gr, double gi, double ekb_h3, cx_t<T>* cnl_out, hipStream_t s) {
+    dim3 grid((n_orb + 4 * ORB - 1) / (4 * ORB), n_ions);
+    kb_fixup_gather_kernel<T, ORB><<<grid, 256, 0, s>>>(
+        out, stride, n_orb, t.idx, reinterpret_cast<const T*>(t.p), t.count, t.kcap, t.ov, t.map, t.cnt, t.ion,
+        reinterpret_cast<const T*>(t.pl), t.ucap, cnl_in, (T)gr, (T)gi, (T)ekb_h3, cnl_out, t.ovl, t.ovn, t.pts, t.ovc);
 }
 
 template <typename T>
@@ -518,11 +546,12 @@ hipError_t launch_kb_fixup_gather(cx_t<T>* out, int64_t stride, int n_orb, int n
                                   hipStream_t s) {
     if (n_ions == 0) return hipSuccess;
     if (t.novc < (n_orb + 3) / 4) return hipErrorInvalidValue;
-    dim3 grid((n_orb + 3) / 4, n_ions);
-    kb_fixup_gather_kernel<T><<<grid, 256, 0, s>>>(out, stride, n_orb, t.idx, reinterpret_cast<const T*>(t.p),
-                                                   t.count, t.kcap, t.ov, t.map, t.cnt, t.ion,
-                                                   reinterpret_cast<const T*>(t.pl), t.ucap, cnl_in, (T)gr, (T)gi,
-                                                   (T)ekb_h3, cnl_out, t.ovl, t.ovn, t.pts, t.ovc);
+    // FP32: two orbitals per wave (one index / projector load for both; 78
+    // VGPRs); FP64: one (two would take 136 VGPRs)
+    if constexpr (sizeof(T) == 4)
+        launch_fg<T, 2>(out, stride, n_orb, n_ions, t, cnl_in, gr, gi, ekb_h3, cnl_out, s);
+    else
+        launch_fg<T, 1>(out, stride, n_orb, n_ions, t, cnl_in, gr, gi, ekb_h3, cnl_out, s);
     return hipGetLastError();
 }
 
