@@ -925,13 +925,125 @@ __global__ void __launch_bounds__(256) kb_forces_kernel(const cx_t<T>* __restric
     }
 }
 
+// The projector form (kb_forces_kernel<T, false>) for ions of at most
+// KBF_CH points: each point's grid index, minimum-image offset and projector
+// value are computed once per workgroup into LDS instead of once per
+// orbital, and each lane's eight orbital loads are issued together.  Lanes
+// visit the points lane, lane + 64, ... in order with the same expressions
+// as kb_forces_kernel, so the sums are the same bits; a workgroup whose ion
+// has more points runs kb_forces_kernel's loop.
+constexpr int KBF_CH = 512;
+
+template <typename T>
+__global__ void __launch_bounds__(256) kb_forces_proj_kernel(const cx_t<T>* __restrict__ psi, int64_t stride,
+                                                             int n_orb, const int32_t* __restrict__ idx,
+                                                             const int32_t* __restrict__ count, int kcap,
+                                                             const double* __restrict__ pos, KbGeom g, int nx,
+                                                             int ny, double* __restrict__ part) {
+    __shared__ double red[4][4];
+    __shared__ double sw[KBF_CH], sx[KBF_CH], sy[KBF_CH], sz[KBF_CH];
+    __shared__ int sl[KBF_CH];
+    const int J = blockIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int K = count[J];
+    const int32_t* ix = idx + (int64_t)J * kcap;
+    const double rx = pos[3 * J], ry = pos[3 * J + 1], rz = pos[3 * J + 2];
+    const bool fast = K <= KBF_CH;
+    if (fast) {
+        for (int k = threadIdx.x; k < K; k += blockDim.x) {
+            const int lin = ix[k];
+            const int gx = lin % nx;
+            const int gy = (lin / nx) % ny;
+            const int gz = lin / (nx * ny);
+            double dx, dy, dz;
+            const double d2 = kb_d2(g, gx, gy, gz, rx, ry, rz, dx, dy, dz);
+            sl[k] = lin;
+            sw[k] = kb_value(g, d2);
+            sx[k] = dx;
+            sy[k] = dy;
+            sz[k] = dz;
+        }
+    }
+    __syncthreads();
+    double fx = 0, fy = 0, fz = 0, en = 0;
+    const int A_end = min(n_orb, (int)(blockIdx.y + 1) * KBF_OB);
+    for (int A = blockIdx.y * KBF_OB + wv; A < A_end; A += 4) {
+        const cx_t<T>* pa = psi + (int64_t)A * stride;
+        double cr = 0, ci = 0, xr = 0, xi = 0, yr = 0, yi = 0, zr = 0, zi = 0;
+        if (fast) {
+            cx_t<T> zv[KBF_CH / 64];
+#pragma unroll
+            for (int i = 0; i < KBF_CH / 64; ++i) {
+                const int k = lane + 64 * i;
+                zv[i] = k < K ? pa[sl[k]] : cx_t<T>{(T)0, (T)0};
+            }
+#pragma unroll
+            for (int i = 0; i < KBF_CH / 64; ++i) {
+                const int k = lane + 64 * i;
+                if (k < K) {
+                    const double w = sw[k], dx = sx[k], dy = sy[k], dz = sz[k];
+                    const double pr = w * (double)zv[i].x, pi = w * (double)zv[i].y;
+                    cr += pr; ci += pi;
+                    xr += dx * pr; xi += dx * pi;
+                    yr += dy * pr; yi += dy * pi;
+                    zr += dz * pr; zi += dz * pi;
+                }
+            }
+        } else {
+            for (int k = lane; k < K; k += 64) {
+                const int lin = ix[k];
+                const int gx = lin % nx;
+                const int gy = (lin / nx) % ny;
+                const int gz = lin / (nx * ny);
+                double dx, dy, dz;
+                const double d2 = kb_d2(g, gx, gy, gz, rx, ry, rz, dx, dy, dz);
+                const double w = kb_value(g, d2);
+                const cx_t<T> zv = pa[lin];
+                const double pr = w * (double)zv.x, pi = w * (double)zv.y;
+                cr += pr; ci += pi;
+                xr += dx * pr; xi += dx * pi;
+                yr += dy * pr; yi += dy * pi;
+                zr += dz * pr; zi += dz * pi;
+            }
+        }
+        cr = wsum_t(cr); ci = wsum_t(ci);
+        xr = wsum_t(xr); xi = wsum_t(xi);
+        yr = wsum_t(yr); yi = wsum_t(yi);
+        zr = wsum_t(zr); zi = wsum_t(zi);
+        fx += cr * xr + ci * xi;
+        fy += cr * yr + ci * yi;
+        fz += cr * zr + ci * zi;
+        en += cr * cr + ci * ci;
+    }
+    if (lane == 0) {
+        red[wv][0] = fx; red[wv][1] = fy; red[wv][2] = fz; red[wv][3] = en;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int c = threadIdx.x;
+        part[((int64_t)J * gridDim.y + blockIdx.y) * 4 + c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+    }
+}
+
+// the blocks of each ion added in order (loads issued eight blocks at a time)
 __global__ void kb_forces_reduce_kernel(const double* __restrict__ part, int nblk, int n_ions, double kf,
                                         double ke, double* __restrict__ fnl, double* __restrict__ enl) {
     const int J = blockIdx.x * blockDim.x + threadIdx.x;
     if (J >= n_ions) return;
     double s[4] = {0, 0, 0, 0};
-    for (int b = 0; b < nblk; ++b)
-        for (int c = 0; c < 4; ++c) s[c] += part[((int64_t)J * nblk + b) * 4 + c];
+    const double* pj = part + (int64_t)J * nblk * 4;
+    for (int b0 = 0; b0 < nblk; b0 += 8) {
+        double v[8][4];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[i][c] = b0 + i < nblk ? pj[(b0 + i) * 4 + c] : 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (b0 + i < nblk)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) s[c] += v[i][c];
+    }
     fnl[3 * J] = kf * s[0];
     fnl[3 * J + 1] = kf * s[1];
     fnl[3 * J + 2] = kf * s[2];
@@ -951,8 +1063,8 @@ hipError_t launch_kb_forces(const cx_t<T>* psi, int64_t stride, int n_orb, int n
         kb_forces_kernel<T, true><<<grid, 256, 0, s>>>(psi, stride, n_orb, t.idx, t.count, t.kcap, pos, g, nx, ny,
                                                        nz, scratch);
     else
-        kb_forces_kernel<T, false><<<grid, 256, 0, s>>>(psi, stride, n_orb, t.idx, t.count, t.kcap, pos, g, nx, ny,
-                                                        nz, scratch);
+        kb_forces_proj_kernel<T><<<grid, 256, 0, s>>>(psi, stride, n_orb, t.idx, t.count, t.kcap, pos, g, nx, ny,
+                                                      scratch);
     const double h6 = g.h * g.h * g.h * g.h * g.h * g.h;
     const double kf = -2.0 * occ * ekb * h6 * (form == 1 ? 1.0 / g.h : g.inv_s2);
     kb_forces_reduce_kernel<<<(n_ions + 63) / 64, 64, 0, s>>>(scratch, nblk, n_ions, kf, occ * ekb * h6, fnl,
