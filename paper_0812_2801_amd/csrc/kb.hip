@@ -851,14 +851,15 @@ constexpr int KBF_OB = 16;
 // 8th-order central first difference: f' ~ (1/h) sum_m a_m (f(x + m h) - f(x - m h))
 __device__ constexpr double FD1[4] = {4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
 
-// GRAD: the columns are h^3 sum p_J grad psi_A (finite-difference gradient,
-// the wave-function-gradient form) instead of h^3 sum p_J (r - R_J) psi_A
-template <typename T, bool GRAD>
-__global__ void __launch_bounds__(256) kb_forces_kernel(const cx_t<T>* __restrict__ psi, int64_t stride,
-                                                        int n_orb, const int32_t* __restrict__ idx,
-                                                        const int32_t* __restrict__ count, int kcap,
-                                                        const double* __restrict__ pos, KbGeom g,
-                                                        int nx, int ny, int nz, double* __restrict__ part) {
+// The wave-function-gradient form: the columns are h^3 sum p_J grad psi_A
+// (8th-order finite-difference gradient) instead of h^3 sum p_J (r - R_J)
+// psi_A (kb_forces_proj_kernel).
+template <typename T>
+__global__ void __launch_bounds__(256) kb_forces_grad_kernel(const cx_t<T>* __restrict__ psi, int64_t stride,
+                                                             int n_orb, const int32_t* __restrict__ idx,
+                                                             const int32_t* __restrict__ count, int kcap,
+                                                             const double* __restrict__ pos, KbGeom g,
+                                                             int nx, int ny, int nz, double* __restrict__ part) {
     __shared__ double red[4][4];
     const int J = blockIdx.x;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -881,30 +882,24 @@ __global__ void __launch_bounds__(256) kb_forces_kernel(const cx_t<T>* __restric
             const cx_t<T> zv = pa[lin];
             const double pr = w * (double)zv.x, pi = w * (double)zv.y;
             cr += pr; ci += pi;
-            if constexpr (GRAD) {
-                const int64_t plane = (int64_t)nx * ny;
-                const int64_t row = lin - gx, col = lin - (int64_t)gy * nx, pil = lin - (int64_t)gz * plane;
-                double ax = 0, bx = 0, ay = 0, by = 0, az = 0, bz = 0;
+            const int64_t plane = (int64_t)nx * ny;
+            const int64_t row = lin - gx, col = lin - (int64_t)gy * nx, pil = lin - (int64_t)gz * plane;
+            double ax = 0, bx = 0, ay = 0, by = 0, az = 0, bz = 0;
 #pragma unroll
-                for (int m = 1; m <= 4; ++m) {
-                    const cx_t<T> xp = pa[row + wrap1(gx + m, nx)], xm = pa[row + wrap1(gx - m, nx)];
-                    const cx_t<T> yp = pa[col + (int64_t)wrap1(gy + m, ny) * nx];
-                    const cx_t<T> ym = pa[col + (int64_t)wrap1(gy - m, ny) * nx];
-                    const cx_t<T> zp = pa[pil + (int64_t)wrap1(gz + m, nz) * plane];
-                    const cx_t<T> zm = pa[pil + (int64_t)wrap1(gz - m, nz) * plane];
-                    const double a = FD1[m - 1];
-                    ax += a * ((double)xp.x - (double)xm.x); bx += a * ((double)xp.y - (double)xm.y);
-                    ay += a * ((double)yp.x - (double)ym.x); by += a * ((double)yp.y - (double)ym.y);
-                    az += a * ((double)zp.x - (double)zm.x); bz += a * ((double)zp.y - (double)zm.y);
-                }
-                xr += w * ax; xi += w * bx;
-                yr += w * ay; yi += w * by;
-                zr += w * az; zi += w * bz;
-            } else {
-                xr += dx * pr; xi += dx * pi;
-                yr += dy * pr; yi += dy * pi;
-                zr += dz * pr; zi += dz * pi;
+            for (int m = 1; m <= 4; ++m) {
+                const cx_t<T> xp = pa[row + wrap1(gx + m, nx)], xm = pa[row + wrap1(gx - m, nx)];
+                const cx_t<T> yp = pa[col + (int64_t)wrap1(gy + m, ny) * nx];
+                const cx_t<T> ym = pa[col + (int64_t)wrap1(gy - m, ny) * nx];
+                const cx_t<T> zp = pa[pil + (int64_t)wrap1(gz + m, nz) * plane];
+                const cx_t<T> zm = pa[pil + (int64_t)wrap1(gz - m, nz) * plane];
+                const double a = FD1[m - 1];
+                ax += a * ((double)xp.x - (double)xm.x); bx += a * ((double)xp.y - (double)xm.y);
+                ay += a * ((double)yp.x - (double)ym.x); by += a * ((double)yp.y - (double)ym.y);
+                az += a * ((double)zp.x - (double)zm.x); bz += a * ((double)zp.y - (double)zm.y);
             }
+            xr += w * ax; xi += w * bx;
+            yr += w * ay; yi += w * by;
+            zr += w * az; zi += w * bz;
         }
         cr = wsum_t(cr); ci = wsum_t(ci);
         xr = wsum_t(xr); xi = wsum_t(xi);
@@ -925,13 +920,13 @@ __global__ void __launch_bounds__(256) kb_forces_kernel(const cx_t<T>* __restric
     }
 }
 
-// The projector form (kb_forces_kernel<T, false>) for ions of at most
-// KBF_CH points: each point's grid index, minimum-image offset and projector
-// value are computed once per workgroup into LDS instead of once per
-// orbital, and each lane's eight orbital loads are issued together.  Lanes
-// visit the points lane, lane + 64, ... in order with the same expressions
-// as kb_forces_kernel, so the sums are the same bits; a workgroup whose ion
-// has more points runs kb_forces_kernel's loop.
+// The projector form: columns h^3 sum p_J (r - R_J) psi_A.  For ions of at
+// most KBF_CH points each point's grid index, minimum-image offset and
+// projector value are computed once per workgroup into LDS instead of once
+// per orbital, and each lane's eight orbital loads are issued together; a
+// workgroup whose ion has more points recomputes them per orbital.  Either
+// way lanes visit the points lane, lane + 64, ... in order with the same
+// expressions, so the two give the same bits.
 constexpr int KBF_CH = 512;
 
 template <typename T>
@@ -1060,7 +1055,7 @@ hipError_t launch_kb_forces(const cx_t<T>* psi, int64_t stride, int n_orb, int n
     const int nblk = (n_orb + KBF_OB - 1) / KBF_OB;
     dim3 grid(n_ions, nblk);
     if (form == 1)
-        kb_forces_kernel<T, true><<<grid, 256, 0, s>>>(psi, stride, n_orb, t.idx, t.count, t.kcap, pos, g, nx, ny,
+        kb_forces_grad_kernel<T><<<grid, 256, 0, s>>>(psi, stride, n_orb, t.idx, t.count, t.kcap, pos, g, nx, ny,
                                                        nz, scratch);
     else
         kb_forces_proj_kernel<T><<<grid, 256, 0, s>>>(psi, stride, n_orb, t.idx, t.count, t.kcap, pos, g, nx, ny,
