@@ -1808,15 +1808,13 @@ me_status batch_time_stage(me_batch* b, int reps, double* ms) {
     const int n = (int)b->sys.size();
     std::vector<const C*> u(n);
     std::vector<C*> out(n);
-    // a three-stream stage as in a step: u (a copy of psi in bufA), psi0 and
-    // the output (bufB) are three distinct arrays, so that the timing sees
-    // the step's memory traffic (with u = psi0 the second read hits cache)
+    // a three-stream stage as in a step: u (bufA, a copy of psi made by the
+    // caller), psi0 and the output (bufB) are three distinct arrays, so that
+    // the timing sees the step's memory traffic (with u = psi0 the second
+    // read would hit cache)
     for (int i = 0; i < n; ++i) {
-        me_system* s = b->sys[i];
-        BHIP(hipMemcpyAsync(s->w.bufA, s->w.psi, (size_t)s->g.n_orb * s->g.stride * sizeof(C),
-                            hipMemcpyDeviceToDevice, b->stream));
-        u[i] = (const C*)s->w.bufA;
-        out[i] = (C*)s->w.bufB;
+        u[i] = (const C*)b->sys[i]->w.bufA;
+        out[i] = (C*)b->sys[i]->w.bufB;
     }
     const int slot = 2 * b->K;                 // the tuning slot, outside a step's range
     const bool timing = b->timing;
@@ -1845,6 +1843,9 @@ template <typename T>
 me_status batch_autotune(me_batch* b, me_batch_tuning* best) {
     best->stage_ms = 0.0;
     bool any = false;
+    for (me_system* s : b->sys)            // the timed stages' u (batch_time_stage)
+        BHIP(hipMemcpyAsync(s->w.bufA, s->w.psi, (size_t)s->g.n_orb * s->g.stride * sizeof(cx_t<T>),
+                            hipMemcpyDeviceToDevice, b->stream));
     for (int block : {256, 512, 768, 1024}) {
         for (int zdiv : {1, 2, 4}) {
             me_batch_tuning t{};
