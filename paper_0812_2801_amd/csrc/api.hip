@@ -1599,15 +1599,43 @@ me_status batch_exponential(me_batch* b, int e, bool last) {
         }
         CHK(batch_join(b));
         CHK(batch_stage<T>(b, u, out, e, k, norm, e * K + (K - k), k == K ? MODE_HORNER_FIRST : MODE_HORNER));
-        CHK(batch_fork(b));
         have_c = fuse && k > 1;
+        // the fused passes of the plain contraction: one launch over the
+        // systems (KB_BATCH at a time) on the batch stream
+        const bool one_launch = have_c && !(sizeof(T) == 4 && b->sys[0]->prm.precision == ME_F32_BF16X3);
+        if (one_launch) {
+            BatchKbArgs<T> ka{};
+            for (int i = 0; i < n; ++i) {
+                me_system* s = b->sys[i];
+                if (s->g.n_ions == 0) continue;
+                const int t = e == 0 ? s->tab_cur : s->tab_cur ^ 1;
+                C* cnl_buf[2] = {(C*)s->w.cnl, (C*)s->w.cnl2};
+                BatchKbSys<T>& d = ka.sys[ka.n_sys++];
+                d.out = out[i];
+                d.cnl_in = cnl_buf[cb[i]];
+                d.cnl_out = cnl_buf[cb[i] ^ 1];
+                d.t = tables(s, t);
+                d.stride = s->g.stride;
+                d.n_orb = s->g.n_orb;
+                d.n_ions = s->g.n_ions;
+                d.gi = (T)(-(s->prm.dt / (2.0 * s->prm.mu)) / k);
+                d.scale = (T)(s->prm.kb_energy * s->prm.h * s->prm.h * s->prm.h);
+                cb[i] ^= 1;
+                if (ka.n_sys == KB_BATCH) {
+                    BHIP(launch_batch_kb_fixup_gather<T>(ka, b->stream));
+                    ka.n_sys = 0;
+                }
+            }
+            if (ka.n_sys > 0) BHIP(launch_batch_kb_fixup_gather<T>(ka, b->stream));
+        }
+        CHK(batch_fork(b));
         for (int i = 0; i < n; ++i) {
             me_system* s = b->sys[i];
             const Geometry& g = s->g;
             const int t = e == 0 ? s->tab_cur : s->tab_cur ^ 1;
             const double tau = s->prm.dt / (2.0 * s->prm.mu);
             C* cnl_buf[2] = {(C*)s->w.cnl, (C*)s->w.cnl2};
-            if (g.n_ions > 0) {
+            if (g.n_ions > 0 && !one_launch) {
                 if (have_c) {
                     const double ekb_h3 = s->prm.kb_energy * s->prm.h * s->prm.h * s->prm.h;
                     BHIP(fixup_gather<T>(s, out[i], t, cnl_buf[cb[i]], -tau / k, ekb_h3, cnl_buf[cb[i] ^ 1]));

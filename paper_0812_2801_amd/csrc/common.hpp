@@ -174,6 +174,27 @@ template <typename T>
 hipError_t launch_kb_fixup_gather(cx_t<T>* out, int64_t stride, int n_orb, int n_ions, KbTables t,
                                   const cx_t<T>* cnl_in, double gr, double gi, double ekb_h3, cx_t<T>* cnl_out,
                                   hipStream_t s);
+// The same pass for up to KB_BATCH systems of a batch in one launch (each
+// with n_ions >= 1; gr = 0 as in the Horner stages; b0 is set by the
+// launcher).  Every system's arithmetic is that of its own launch.
+constexpr int KB_BATCH = 16;
+template <typename T>
+struct BatchKbSys {
+    cx_t<T>* out;
+    const cx_t<T>* cnl_in;
+    cx_t<T>* cnl_out;
+    KbTables t;
+    int64_t stride;
+    int n_orb, n_ions, b0;
+    T gi, scale;
+};
+template <typename T>
+struct BatchKbArgs {
+    BatchKbSys<T> sys[KB_BATCH];
+    int n_sys;
+};
+template <typename T>
+hipError_t launch_batch_kb_fixup_gather(BatchKbArgs<T> a, hipStream_t s);
 // the same with the split-bf16 MFMA contraction (FP32 orbitals)
 hipError_t launch_kb_fixup_gather_bf16x3(float2* out, int64_t stride, int n_orb, int n_ions, KbTables t,
                                          const float2* cnl_in, double gr, double gi, double ekb_h3, float2* cnl_out,

@@ -431,37 +431,37 @@ __device__ void fix_shared_points(cx_t<T>* __restrict__ out, int64_t stride, int
 }
 
 // true in every thread of the workgroup that finishes its orbital group last
-// (gridDim.y workgroups per group).  A workgroup counts itself after every
+// (members workgroups per group).  A workgroup counts itself after every
 // load of its points has returned (their values are in its sums), so the
 // last one's stores come after all the group's reads.  No other ordering is
 // needed (the shared points and c_JA are not written by the other
 // workgroups), so the count is a relaxed device-scope atomic and no fence is
 // taken: a device-scope fence writes back or invalidates the XCD's L2.
-__device__ __forceinline__ bool last_of_group(int32_t* ovc_g, int* flag) {
+__device__ __forceinline__ bool last_of_group(int32_t* ovc_g, int members, int* flag) {
     __syncthreads();
-    if (threadIdx.x == 0) *flag = atomicAdd(ovc_g, 1) == (int)gridDim.y - 1;
+    if (threadIdx.x == 0) *flag = atomicAdd(ovc_g, 1) == members - 1;
     __syncthreads();
     return *flag != 0;
 }
 
+// one workgroup of the fused pass: orbitals 4 ORB grp .. (ORB consecutive
+// per wave) of ion J; n_ions workgroups per orbital group
 template <typename T, int ORB>
-__global__ void __launch_bounds__(256) kb_fixup_gather_kernel(
-    cx_t<T>* __restrict__ out, int64_t stride, int n_orb, const int32_t* __restrict__ idx,
-    const T* __restrict__ pv, const int32_t* __restrict__ count, int kcap, const uint8_t* __restrict__ ov,
-    const int32_t* __restrict__ map, const int32_t* __restrict__ cnt, const int32_t* __restrict__ ion,
-    const T* __restrict__ pl, int64_t ucap, const cx_t<T>* __restrict__ cnl_in, T gr, T gi, T scale,
-    cx_t<T>* __restrict__ cnl_out, const int32_t* __restrict__ ovl, const int32_t* __restrict__ ovn,
-    const int32_t* __restrict__ pts, int32_t* __restrict__ ovc) {
-    __shared__ int last;
-    const int J = blockIdx.y;
+__device__ __forceinline__ void fixup_gather_block(cx_t<T>* __restrict__ out, int64_t stride, int n_orb, int n_ions,
+                                                   const KbTables& t, const cx_t<T>* __restrict__ cnl_in, T gr, T gi,
+                                                   T scale, cx_t<T>* __restrict__ cnl_out, int J, int grp,
+                                                   int* last) {
+    const T* pv = reinterpret_cast<const T*>(t.p);
+    const T* pl = reinterpret_cast<const T*>(t.pl);
+    const int64_t ucap = t.ucap;
     const int lane = threadIdx.x & 63;
     const int G = 4 * ORB;                         // orbitals of the workgroup: ORB consecutive per wave
-    const int A0 = blockIdx.x * G + (threadIdx.x >> 6) * ORB;
+    const int A0 = grp * G + (threadIdx.x >> 6) * ORB;
     if (A0 < n_orb) {
-        const int K = count[J];
-        const int32_t* ix = idx + (int64_t)J * kcap;
-        const T* pp = pv + (int64_t)J * kcap;
-        const uint8_t* po = ov + (int64_t)J * kcap;
+        const int K = t.count[J];
+        const int32_t* ix = t.idx + (int64_t)J * t.kcap;
+        const T* pp = pv + (int64_t)J * t.kcap;
+        const uint8_t* po = t.ov + (int64_t)J * t.kcap;
         cx_t<T> cj[ORB];
         T re[ORB], im[ORB];
 #pragma unroll
@@ -503,10 +503,10 @@ __global__ void __launch_bounds__(256) kb_fixup_gather_kernel(
                         z[o][i] = nl_add<T>(z[o][i], sr, si, gr, gi);
                         ua[id[i]] = z[o][i];
                     } else {                   // shared point: the slot's pairs, in ion order
-                        const int sl = map[id[i]];
-                        const int n = min(cnt[sl], NL_KMAX);
+                        const int sl = t.map[id[i]];
+                        const int n = min(t.cnt[sl], NL_KMAX);
                         for (int q = 0; q < n; ++q)
-                            nl_acc<T>(pl[q * ucap + sl], cnl_in[(int64_t)ion[q * ucap + sl] * n_orb + A], sr, si);
+                            nl_acc<T>(pl[q * ucap + sl], cnl_in[(int64_t)t.ion[q * ucap + sl] * n_orb + A], sr, si);
                         z[o][i] = nl_add<T>(z[o][i], sr, si, gr, gi);
                     }
                 }
@@ -524,21 +524,40 @@ __global__ void __launch_bounds__(256) kb_fixup_gather_kernel(
             if (lane == 0 && A0 + o < n_orb) cnl_out[(int64_t)J * n_orb + A0 + o] = cx_t<T>{scale * r, scale * m};
         }
     }
-    if (last_of_group(ovc + blockIdx.x, &last)) {
-        const int B0 = blockIdx.x * G;
-        fix_shared_points<T>(out, stride, n_orb, B0, min(G, n_orb - B0), ovl, ovn, pts, cnt, ion, pl, ucap, cnl_in,
-                             gr, gi, ovc + blockIdx.x);
+    if (last_of_group(t.ovc + grp, n_ions, last)) {
+        const int B0 = grp * G;
+        fix_shared_points<T>(out, stride, n_orb, B0, min(G, n_orb - B0), t.ovl, t.ovn, t.pts, t.cnt, t.ion, pl, ucap,
+                             cnl_in, gr, gi, t.ovc + grp);
     }
 }
 
 template <typename T, int ORB>
-void launch_fg(cx_t<T>* out, int64_t stride, int n_orb, int n_ions, const KbTables& t, const cx_t<T>* cnl_in,
-               double gr, double gi, double ekb_h3, cx_t<T>* cnl_out, hipStream_t s) {
-    dim3 grid((n_orb + 4 * ORB - 1) / (4 * ORB), n_ions);
-    kb_fixup_gather_kernel<T, ORB><<<grid, 256, 0, s>>>(
-        out, stride, n_orb, t.idx, reinterpret_cast<const T*>(t.p), t.count, t.kcap, t.ov, t.map, t.cnt, t.ion,
-        reinterpret_cast<const T*>(t.pl), t.ucap, cnl_in, (T)gr, (T)gi, (T)ekb_h3, cnl_out, t.ovl, t.ovn, t.pts, t.ovc);
+__global__ void __launch_bounds__(256) kb_fixup_gather_kernel(cx_t<T>* __restrict__ out, int64_t stride, int n_orb,
+                                                              KbTables t, const cx_t<T>* __restrict__ cnl_in, T gr,
+                                                              T gi, T scale, cx_t<T>* __restrict__ cnl_out) {
+    __shared__ int last;
+    fixup_gather_block<T, ORB>(out, stride, n_orb, (int)gridDim.y, t, cnl_in, gr, gi, scale, cnl_out, blockIdx.y,
+                               blockIdx.x, &last);
 }
+
+// the same pass for several systems in one launch: block b belongs to the
+// last system whose first block is <= b; within a system blocks run over the
+// orbital groups fastest, as the single-system grid does
+template <typename T, int ORB>
+__global__ void __launch_bounds__(256) batch_kb_fixup_gather_kernel(BatchKbArgs<T> a) {
+    __shared__ int last;
+    int s = 0;
+    while (s + 1 < a.n_sys && (int)blockIdx.x >= a.sys[s + 1].b0) ++s;
+    const BatchKbSys<T>& d = a.sys[s];
+    const int groups = (d.n_orb + 4 * ORB - 1) / (4 * ORB);
+    const int local = (int)blockIdx.x - d.b0;
+    fixup_gather_block<T, ORB>(d.out, d.stride, d.n_orb, d.n_ions, d.t, d.cnl_in, (T)0, d.gi, d.scale, d.cnl_out,
+                               local / groups, local % groups, &last);
+}
+
+// orbitals per wave of the fused pass: FP32 two (one index / projector load
+// for both; 78 VGPRs), FP64 one (two would take 136 VGPRs)
+template <typename T> constexpr int fg_orb() { return sizeof(T) == 4 ? 2 : 1; }
 
 template <typename T>
 hipError_t launch_kb_fixup_gather(cx_t<T>* out, int64_t stride, int n_orb, int n_ions, KbTables t,
@@ -546,14 +565,30 @@ hipError_t launch_kb_fixup_gather(cx_t<T>* out, int64_t stride, int n_orb, int n
                                   hipStream_t s) {
     if (n_ions == 0) return hipSuccess;
     if (t.novc < (n_orb + 3) / 4) return hipErrorInvalidValue;
-    // FP32: two orbitals per wave (one index / projector load for both; 78
-    // VGPRs); FP64: one (two would take 136 VGPRs)
-    if constexpr (sizeof(T) == 4)
-        launch_fg<T, 2>(out, stride, n_orb, n_ions, t, cnl_in, gr, gi, ekb_h3, cnl_out, s);
-    else
-        launch_fg<T, 1>(out, stride, n_orb, n_ions, t, cnl_in, gr, gi, ekb_h3, cnl_out, s);
+    constexpr int ORB = fg_orb<T>();
+    dim3 grid((n_orb + 4 * ORB - 1) / (4 * ORB), n_ions);
+    kb_fixup_gather_kernel<T, ORB><<<grid, 256, 0, s>>>(out, stride, n_orb, t, cnl_in, (T)gr, (T)gi, (T)ekb_h3,
+                                                        cnl_out);
     return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_batch_kb_fixup_gather(BatchKbArgs<T> a, hipStream_t s) {
+    constexpr int ORB = fg_orb<T>();
+    if (a.n_sys < 1 || a.n_sys > KB_BATCH) return hipErrorInvalidValue;
+    int blocks = 0;
+    for (int i = 0; i < a.n_sys; ++i) {
+        BatchKbSys<T>& d = a.sys[i];
+        if (d.n_ions < 1 || d.t.novc < (d.n_orb + 3) / 4) return hipErrorInvalidValue;
+        d.b0 = blocks;
+        blocks += ((d.n_orb + 4 * ORB - 1) / (4 * ORB)) * d.n_ions;
+    }
+    batch_kb_fixup_gather_kernel<T, ORB><<<blocks, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template hipError_t launch_batch_kb_fixup_gather<double>(BatchKbArgs<double>, hipStream_t);
+template hipError_t launch_batch_kb_fixup_gather<float>(BatchKbArgs<float>, hipStream_t);
 
 template hipError_t launch_kb_fixup_gather<double>(double2*, int64_t, int, int, KbTables, const double2*, double,
                                                    double, double, double2*, hipStream_t);
@@ -751,7 +786,7 @@ __global__ void __launch_bounds__(1024) kb_gather_bf16x3_kernel(const float2* __
     }
     if constexpr (FIX) {
         __shared__ int last;
-        if (last_of_group(fx.ovc + blockIdx.x, &last))
+        if (last_of_group(fx.ovc + blockIdx.x, (int)gridDim.y, &last))
             fix_shared_points<float>(fx.out, stride, n_orb, A0, min(16, n_orb - A0), fx.ovl, fx.ovn, fx.pts, fx.cnt,
                                      fx.ion, fx.pl, fx.ucap, fx.cnl_in, fx.gr, fx.gi, fx.ovc + blockIdx.x);
     }
